@@ -1,0 +1,188 @@
+/*
+ * vp.h - C ABI of libvp, the MI355X (gfx950) stress-velocity Newton-Krylov solver
+ * for one implicit Euler step of the viscous-plastic sea-ice momentum equation.
+ *
+ * Paper: Shih, Mehlmann, Losch, Stadler, "Robust and efficient primal-dual
+ * Newton-Krylov solvers for viscous-plastic sea-ice models" (arXiv 2204.10822).
+ *
+ * Problem (Sec. 3, eq. Av=F, eq. A, eq. F): given the previous velocity v^n, the
+ * (already advanced) thickness H and concentration A, wind v_air and ocean
+ * current v_ocean, find v = v^{n+1} with A(v, phi) = F(phi) for all Q1 test
+ * functions phi vanishing on the boundary.  The stress-velocity Newton method of
+ * Sec. 4.2 introduces pi = tau(v)/Delta(v) (eq. pi) and solves each linearisation
+ * (eq. linearSVNewton with eq. modification) by AMG-preconditioned Krylov.
+ *
+ * Discretisation: uniform structured quadrilateral mesh of [0,Lx]x[0,Ly] with
+ * nx x ny cells, Q1 velocity, cellwise-constant H and A (Sec. 5.1), 2x2 Gauss
+ * quadrature for every term, zero velocity on the whole boundary (Sec. 2).
+ *
+ * Conventions (all entry points):
+ *  - Array arguments are caller-owned, contiguous DEVICE pointers (e.g. torch
+ *    tensor data_ptr() values on the context's stream) unless stated as host.
+ *    The library never keeps a caller pointer past the call; vp_set_state copies.
+ *  - Layouts:  cell field   [ny][nx]                     (double)
+ *              node vector  [(ny+1)(nx+1)][2]  node n = j*(nx+1)+i, x comp first
+ *              pi           [4 qp][3 comp][ny][nx], comps (xx, yy, xy) of the
+ *                           symmetric 2x2 tensor; qp = qx + 2*qy, where qx (qy)
+ *                           is 0 at the Gauss point 1/2 - 1/(2 sqrt 3) of the
+ *                           cell's x (y) extent and 1 at 1/2 + 1/(2 sqrt 3).
+ *  - All work is enqueued on the stream given to vp_create.  Calls returning
+ *    host scalars synchronise that stream.
+ *  - Return codes: 0 = OK, > 0 = soft outcome with valid outputs, < 0 = error
+ *    (outputs unspecified; vp_last_error() gives text).  No C++ exception
+ *    crosses the ABI.  One context per host thread at a time.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Mesh, physics constants (Table tab:params) and step settings (Sec. 5.2/5.3). */
+typedef struct {
+  int32_t nx, ny;          /* cells per side; nodes (nx+1)(ny+1)                    */
+  double Lx, Ly;           /* domain size [m]                                       */
+  double rho_ice, rho_air, rho_ocean;  /* densities [kg/m^3]                        */
+  double C_air, C_ocean;   /* drag coefficients                                     */
+  double P_star;           /* ice strength parameter [N/m^2]                        */
+  double C_strength;       /* concentration parameter C in P = P* H exp(-C(1-A))    */
+  double e_ratio;          /* ellipse ratio e                                       */
+  double f_coriolis;       /* Coriolis parameter [1/s], explicit (Sec. 3 footnote)  */
+  double dt;               /* time step [s]                                         */
+  double delta_min;        /* Delta_min [1/s] (eq. Delta)                           */
+} vp_problem_desc;
+
+typedef struct vp_ctx_s* vp_ctx;
+
+enum {
+  VP_OK = 0,
+  VP_NOT_CONVERGED = 1,    /* Newton hit its iteration cap                          */
+  VP_LINESEARCH_FAIL = 2,  /* backtracking found no acceptable step                 */
+  VP_KRYLOV_MAXIT = 3,     /* Krylov hit maxit before rtol (outputs are the iterate)*/
+  VP_EINVAL = -1,          /* bad argument                                          */
+  VP_EHIP = -2,            /* HIP runtime error                                     */
+  VP_ENOMEM = -3,          /* device allocation failed                              */
+  VP_ESTATE = -4,          /* call out of order (e.g. solve before assemble)        */
+  VP_ENONFINITE = -5,      /* NaN/Inf met in a residual, energy or Krylov scalar    */
+  VP_EBREAKDOWN = -6       /* Krylov breakdown (indefinite or singular operator)    */
+};
+enum { VP_SVN = 0, VP_STDN = 1 };                         /* linearisation          */
+enum { VP_PREC_FP64 = 0, VP_PREC_FP32 = 1, VP_PREC_FP32_BF16COARSE = 2 };
+enum { VP_KRYLOV_FGMRES = 0, VP_KRYLOV_FCG = 1 };
+enum { VP_LS_ENERGY = 0, VP_LS_RESIDUAL = 1 };
+
+/* Create a context for one mesh.  hip_stream: a hipStream_t (NULL = null stream).
+ * Errors: VP_EINVAL for nx or ny < 2, non-positive sizes, dt, delta_min, e_ratio
+ * or negative P_star/densities; VP_ENOMEM/VP_EHIP on device failure. */
+int vp_create(const vp_problem_desc* desc, void* hip_stream, vp_ctx* out);
+void vp_destroy(vp_ctx ctx);
+/* Text of the last error on this context (or of the last vp_create failure when
+ * ctx is NULL).  Valid until the next call on the context. */
+const char* vp_last_error(vp_ctx ctx);
+
+/* Set the step's data (copied): H, A cell fields [ny][nx]; v_air, v_ocean, v_prev
+ * node vectors.  Computes P = P* H exp(-C(1-A)) (eq. ice-strength), rho_ice*H and
+ * the load vector F(phi_i) of eq. F (explicit Coriolis on v_prev - v_ocean,
+ * air stress C_a rho_a |v_a| v_a of eq. force at quadrature points).
+ * H must be >= 0 and A in [0,1]; values are not checked on the device. */
+int vp_set_state(vp_ctx ctx, const double* H, const double* A, const double* v_air,
+                 const double* v_ocean, const double* v_prev);
+
+/* Residual of eq. Av=F: r_i = A(v, phi_i) - F(phi_i) with sigma in the tau form of
+ * eq. sigma; r = 0 at boundary dofs.  r may be NULL.  rnorm (host, nullable):
+ * l2 norm over free dofs.  energy (host, nullable): Phi(v) of eq. energy.
+ * Synchronises when rnorm or energy is requested.  VP_ENONFINITE if either is
+ * not finite. */
+int vp_residual(vp_ctx ctx, const double* v, double* r, double* rnorm, double* energy);
+
+/* Assemble the linearised operator at (v, pi) into the context:
+ *  VP_SVN : eq. linearSVNewton with tau_l (x) pi_l replaced as in eq. modification
+ *  VP_STDN: eq. standardNewton1 (pi ignored, may be NULL)
+ * plus the ocean-drag Jacobian of eq. standardNewton2 and the mass term.  Stored
+ * as a 9-point block stencil with identity rows/columns at boundary dofs. */
+int vp_newton_assemble(vp_ctx ctx, const double* v, const double* pi, int variant);
+/* y = K x with the last assembled operator (FP64).  VP_ESTATE before assembly. */
+int vp_operator_apply(vp_ctx ctx, const double* x, double* y);
+/* Copy the assembled operator to a device buffer of 20*(nx+1)*(ny+1) doubles:
+ * plane k = 4*blk + 2*r + c holds entry (r,c) of the 2x2 block coupling node n
+ * (row dofs) to node n+off(blk), blk 0..4 = self, east (+1,0), north (0,+1),
+ * north-east (+1,+1), north-west (-1,+1); the other four neighbours are the
+ * transposes held by those nodes (the operator is symmetric). */
+int vp_operator_export(vp_ctx ctx, double* blocks);
+
+/* Smoothed-aggregation AMG (replaces the paper's BoomerAMG, Sec. 5.4) built on
+ * the last assembled operator: structured 3x3-node aggregates, rigid-body
+ * near-null space, one block-Jacobi smoothing of the prolongator, Galerkin
+ * coarse operators, Chebyshev smoothing, dense coarsest solve. */
+typedef struct {
+  int cheb_degree;       /* Chebyshev degree per pre/post smoothing (>= 1)         */
+  int max_coarse;        /* coarsest level dof bound (<= 1024)                     */
+  int precision;         /* VP_PREC_*: V-cycle arithmetic and coarse storage       */
+  double cheb_ratio;     /* smoothing interval [lmax/ratio, lmax]                  */
+  double omega_scale;    /* prolongator damping scale (1 = 4/(3 lmax))             */
+} vp_amg_opts;
+int vp_amg_setup(vp_ctx ctx, const vp_amg_opts* opts);
+/* z = M^{-1} r, one V-cycle.  VP_ESTATE before vp_amg_setup. */
+int vp_amg_apply(vp_ctx ctx, const double* r, double* z);
+/* Number of AMG levels (host out) and their node grids (host arrays of >= 16). */
+int vp_amg_info(vp_ctx ctx, int* levels, int* nxn, int* nyn, int* dofs_per_node);
+
+/* Krylov solve K x = b with the last assembled operator and AMG (Sec. 5.4):
+ * FGMRES(restart) right-preconditioned with classical Gram-Schmidt applied twice,
+ * or flexible CG.  x holds the initial guess on entry.  Stops at
+ * ||b - K x|| <= rtol ||b||.  VP_KRYLOV_MAXIT (soft) after maxit iterations. */
+typedef struct { int method; int restart; int maxit; double rtol; } vp_krylov_opts;
+typedef struct { int iters; double rel_resid; } vp_krylov_info;
+int vp_krylov_solve(vp_ctx ctx, const double* b, double* x, const vp_krylov_opts* opts,
+                    vp_krylov_info* info);
+
+/* Dual update (eq. tautilde with eq. modification, Sec. 4.2):
+ * pi <- pi + alpha * pi~(v, dv, pi), in place. */
+int vp_pi_update(vp_ctx ctx, const double* v, const double* dv, double* pi, double alpha);
+/* pi <- tau(v)/Delta(v) at every quadrature point (eq. pi). */
+int vp_pi_init(vp_ctx ctx, const double* v, double* pi);
+
+/* One Newton iteration in place on (v, pi): residual, assembly, AMG setup, Krylov
+ * solve to the Eisenstat-Walker tolerance, energy backtracking (halving from 1,
+ * Sec. 5.1), dual update, velocity update.  tol: relative target on
+ * ||R|| / ||R(0)|| (used for the inner-tolerance floor). */
+typedef struct {
+  int variant;           /* VP_SVN or VP_STDN                                      */
+  double tol;            /* nonlinear target, relative to ||R(v=0)||               */
+  double eta_max;        /* cap of the inner relative tolerance                    */
+  int max_backtracks;    /* halvings before VP_LINESEARCH_FAIL                     */
+  int ls_mode;           /* VP_LS_ENERGY or VP_LS_RESIDUAL                         */
+} vp_newton_opts;
+typedef struct {
+  double rnorm;          /* ||R|| at the start of the iteration                    */
+  double rnorm0;         /* ||R(v=0)||                                             */
+  double rnorm_new;      /* ||R|| after the step                                   */
+  double energy, energy_new, alpha, eta;
+  int backtracks, krylov_iters;
+} vp_newton_info;
+int vp_newton_step(vp_ctx ctx, double* v, double* pi, const vp_newton_opts* nopts,
+                   const vp_amg_opts* aopts, const vp_krylov_opts* kopts,
+                   vp_newton_info* info);
+
+/* Newton loop (Sec. 5.1 stopping rule with a relative target): iterate
+ * vp_newton_step until ||R(v)|| <= tol ||R(0)|| or maxit iterations.  Returns
+ * VP_OK, VP_NOT_CONVERGED or VP_LINESEARCH_FAIL.  history (host, nullable,
+ * maxit+1 entries) receives ||R||/||R(0)|| per iterate. */
+typedef struct {
+  int iterations, krylov_iters;
+  double rnorm0, rel_resid;
+} vp_solve_info;
+int vp_newton_solve(vp_ctx ctx, double* v, double* pi, int maxit,
+                    const vp_newton_opts* nopts, const vp_amg_opts* aopts,
+                    const vp_krylov_opts* kopts, vp_solve_info* info, double* history);
+
+/* Default option sets. */
+void vp_default_opts(vp_newton_opts* n, vp_amg_opts* a, vp_krylov_opts* k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VP_H */

@@ -1,0 +1,1015 @@
+// Structured smoothed-aggregation AMG on block 9-point stencils.
+//
+// Every level is a structured grid of nxn x nyn nodes carrying B dofs per node
+// (B = 2 on the finest level, 3 on coarse levels: the rigid-body modes), and its
+// operator is a symmetric block 9-point stencil stored as five B x B blocks per
+// node (self, E, N, NE, NW; the W, S, SW, SE couplings are the transposes held by
+// the neighbours), plane-major: A[(blk*B*B + r*B + c)*nn + node].
+//
+// Aggregates are 3x3 node blocks (the last one per direction takes the 3..5
+// remaining nodes).  One block-Jacobi smoothing step of the tentative
+// prolongator widens each column's support by one node ring, which keeps the
+// Galerkin operator P^T A P a block 9-point stencil on the aggregate grid, so
+// every level reuses the same stencil kernels and no sparse-matrix product with
+// run-time sparsity is needed.  This replaces the paper's classical AMG
+// (BoomerAMG, Sec. 5.4); its role there is the preconditioner of FGMRES for the
+// SPD linearisations with strongly varying coefficients.
+#include "vp_internal.h"
+
+namespace vp {
+
+namespace {
+
+template <typename T> struct Acc { using type = float; };
+template <> struct Acc<double> { using type = double; };
+
+// ---- aggregation along one direction ---------------------------------------
+__device__ __forceinline__ int agg_of(int i, int nagg) {
+  const int a = i / 3;
+  return a < nagg ? a : nagg - 1;
+}
+__device__ __forceinline__ int agg_last(int a, int n, int nagg) { return a == nagg - 1 ? n - 1 : 3 * a + 2; }
+// aggregate adjacent to node i through the 9-point stencil, other than its own (-1: none)
+__device__ __forceinline__ int agg_other(int i, int n, int nagg) {
+  const int a = agg_of(i, nagg);
+  if (i == 3 * a && a > 0) return a - 1;
+  if (i == agg_last(a, n, nagg) && a < nagg - 1) return a + 1;
+  return -1;
+}
+// slot (0/1) of coarse index J for node i along one direction, -1 if none
+__device__ __forceinline__ int slot1(int i, int n, int nagg, int J) {
+  if (agg_of(i, nagg) == J) return 0;
+  if (agg_other(i, n, nagg) == J) return 1;
+  return -1;
+}
+
+// ---- block access ------------------------------------------------------------
+// 9 directions: 0 self, 1 E, 2 N, 3 NE, 4 NW, 5 W, 6 S, 7 SW, 8 SE
+__constant__ int kDI[9] = {0, 1, 0, 1, -1, -1, 0, -1, 1};
+__constant__ int kDJ[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+
+// Load the B x B block coupling node (i,j) (rows) to its neighbour in direction d
+// (columns).  Caller guarantees the neighbour exists.
+template <int B, typename TM, typename TA>
+__device__ __forceinline__ void load_block(const TM* __restrict__ A, size_t nn, int nxn, int i, int j,
+                                           int d, TA (&out)[B][B]) {
+  const size_t n = (size_t)j * nxn + i;
+  if (d <= 4) {
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) out[r][c] = (TA)ld(A + (size_t)(d * B * B + r * B + c) * nn + n);
+  } else {
+    const int blk = d - 4;  // W->E(1), S->N(2), SW->NE(3), SE->NW(4)
+    const size_t m = (size_t)(j + kDJ[d]) * nxn + (i + kDI[d]);
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) out[r][c] = (TA)ld(A + (size_t)(blk * B * B + c * B + r) * nn + m);
+  }
+}
+
+template <int B, typename TA>
+__device__ __forceinline__ void invert_block(const TA (&D)[B][B], TA (&Di)[B][B]) {
+  if constexpr (B == 2) {
+    const TA det = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+    const TA id = det != TA(0) ? TA(1) / det : TA(0);
+    Di[0][0] = D[1][1] * id; Di[0][1] = -D[0][1] * id;
+    Di[1][0] = -D[1][0] * id; Di[1][1] = D[0][0] * id;
+  } else {
+    const TA c00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+    const TA c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+    const TA c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+    const TA det = D[0][0] * c00 + D[0][1] * c01 + D[0][2] * c02;
+    const TA id = det != TA(0) ? TA(1) / det : TA(0);
+    Di[0][0] = c00 * id;
+    Di[1][0] = c01 * id;
+    Di[2][0] = c02 * id;
+    Di[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
+    Di[1][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * id;
+    Di[2][1] = (D[0][1] * D[2][0] - D[0][0] * D[2][1]) * id;
+    Di[0][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * id;
+    Di[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
+    Di[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
+  }
+}
+
+// (A x)_n for node (i, j) of the stencil
+template <int B, typename TM, typename TV, typename TA>
+__device__ __forceinline__ void stencil_row(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int i,
+                                            int j, const TV* __restrict__ x, TA (&y)[B],
+                                            TA (&D)[B][B]) {
+#pragma unroll
+  for (int r = 0; r < B; ++r) y[r] = TA(0);
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const int ii = i + kDI[d], jj = j + kDJ[d];
+    if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+    TA blk[B][B];
+    load_block<B>(A, nn, nxn, i, j, d, blk);
+    if (d == 0) {
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) D[r][c] = blk[r][c];
+    }
+    const size_t m = (size_t)jj * nxn + ii;
+    TA xm[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) xm[c] = (TA)x[m * B + c];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) y[r] += blk[r][c] * xm[c];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// stencil kernels
+// ---------------------------------------------------------------------------
+// r = b - A x (b may be null: r = -A x); in-place r == b is allowed.
+template <int B, typename TM, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ x,
+             const TV* b, TV* r) {
+  using TA = typename Acc<TV>::type;
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  TA y[B], D[B][B];
+  stencil_row<B>(A, nn, nxn, nyn, i, j, x, y, D);
+#pragma unroll
+  for (int k = 0; k < B; ++k) r[n * B + k] = (TV)((b ? (TA)b[n * B + k] : TA(0)) - y[k]);
+}
+
+// y = A x (FP64 finest level), partial sums of x.y per workgroup (for CG)
+__global__ void __launch_bounds__(kBlock)
+k_apply_fine(const double* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
+             double* __restrict__ y, double* __restrict__ partials) {
+  __shared__ double lds[16];
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  double acc[1] = {0.0};
+  if (n < nn) {
+    const int i = (int)(n % nxn), j = (int)(n / nxn);
+    double yy[2], D[2][2];
+    stencil_row<2>(A, nn, nxn, nyn, i, j, x, yy, D);
+    reinterpret_cast<double2*>(y)[n] = make_double2(yy[0], yy[1]);
+    acc[0] = yy[0] * x[2 * n] + yy[1] * x[2 * n + 1];
+  }
+  if (partials) {
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+  }
+}
+
+// Chebyshev first step: d = D^{-1} src * inv_theta; x = d (zero start) or x += d.
+// copy_to_r: also r = src (pre-smoothing from a zero initial guess).
+template <int B, typename TM, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_cheb_first(const TM* __restrict__ A, size_t nn, const TV* __restrict__ src, TV* __restrict__ r,
+             TV* __restrict__ d, TV* __restrict__ x, typename Acc<TV>::type inv_theta, int add,
+             int copy_to_r) {
+  using TA = typename Acc<TV>::type;
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  TA D[B][B], Di[B][B], s[B];
+#pragma unroll
+  for (int rr = 0; rr < B; ++rr)
+#pragma unroll
+    for (int c = 0; c < B; ++c) D[rr][c] = (TA)ld(A + (size_t)(rr * B + c) * nn + n);
+  invert_block<B>(D, Di);
+#pragma unroll
+  for (int k = 0; k < B; ++k) s[k] = (TA)src[n * B + k];
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    TA dk = TA(0);
+#pragma unroll
+    for (int c = 0; c < B; ++c) dk += Di[k][c] * s[c];
+    dk *= inv_theta;
+    d[n * B + k] = (TV)dk;
+    x[n * B + k] = add ? (TV)((TA)x[n * B + k] + dk) : (TV)dk;
+    if (copy_to_r) r[n * B + k] = (TV)s[k];
+  }
+}
+
+// Chebyshev step: r -= A dp; dn = cdd dp + cdr D^{-1} r; x += dn
+template <int B, typename TM, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ dp,
+            TV* __restrict__ r, TV* __restrict__ dn, TV* __restrict__ x, typename Acc<TV>::type cdd,
+            typename Acc<TV>::type cdr) {
+  using TA = typename Acc<TV>::type;
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  TA y[B], D[B][B], Di[B][B], rn[B];
+  stencil_row<B>(A, nn, nxn, nyn, i, j, dp, y, D);
+  invert_block<B>(D, Di);
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    rn[k] = (TA)r[n * B + k] - y[k];
+    r[n * B + k] = (TV)rn[k];
+  }
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    TA t = TA(0);
+#pragma unroll
+    for (int c = 0; c < B; ++c) t += Di[k][c] * rn[c];
+    const TA dk = cdd * (TA)dp[n * B + k] + cdr * t;
+    dn[n * B + k] = (TV)dk;
+    x[n * B + k] = (TV)((TA)x[n * B + k] + dk);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// transfers: P stored per fine node as 4 slots x (B x 3), plane-major
+//   P[((slot*B + r)*3 + c)*nn + node]
+// slot = sx + 2 sy, sx = 0: own aggregate in x, 1: the adjacent one (agg_other)
+// ---------------------------------------------------------------------------
+template <int B, typename TP, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_restrict(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
+           const TV* __restrict__ r, TV* __restrict__ bc) {
+  using TA = typename Acc<TV>::type;
+  const size_t I = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= (size_t)ncx * ncy) return;
+  const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
+  const int i0 = max(3 * Ix - 1, 0), i1 = min(agg_last(Ix, nxn, ncx) + 1, nxn - 1);
+  const int j0 = max(3 * Iy - 1, 0), j1 = min(agg_last(Iy, nyn, ncy) + 1, nyn - 1);
+  TA acc[3] = {TA(0), TA(0), TA(0)};
+  for (int j = j0; j <= j1; ++j) {
+    const int sy = slot1(j, nyn, ncy, Iy);
+    if (sy < 0) continue;
+    for (int i = i0; i <= i1; ++i) {
+      const int sx = slot1(i, nxn, ncx, Ix);
+      if (sx < 0) continue;
+      const int s = sx + 2 * sy;
+      const size_t n = (size_t)j * nxn + i;
+#pragma unroll
+      for (int rr = 0; rr < B; ++rr) {
+        const TA rv = (TA)r[n * B + rr];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += (TA)ld(P + ((size_t)(s * B + rr) * 3 + c) * nn + n) * rv;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) bc[I * 3 + c] = (TV)acc[c];
+}
+
+template <int B, typename TP, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
+              const TV* __restrict__ xc, TV* __restrict__ x) {
+  using TA = typename Acc<TV>::type;
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  const int ax[2] = {agg_of(i, ncx), agg_other(i, nxn, ncx)};
+  const int ay[2] = {agg_of(j, ncy), agg_other(j, nyn, ncy)};
+  TA acc[B];
+#pragma unroll
+  for (int rr = 0; rr < B; ++rr) acc[rr] = (TA)x[n * B + rr];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int Jx = ax[s & 1], Jy = ay[s >> 1];
+    if (Jx < 0 || Jy < 0) continue;
+    const size_t J = (size_t)Jy * ncx + Jx;
+    TA xj[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xj[c] = (TA)xc[J * 3 + c];
+#pragma unroll
+    for (int rr = 0; rr < B; ++rr)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[rr] += (TA)ld(P + ((size_t)(s * B + rr) * 3 + c) * nn + n) * xj[c];
+  }
+#pragma unroll
+  for (int rr = 0; rr < B; ++rr) x[n * B + rr] = (TV)acc[rr];
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+// Near-null-space row block of node (i,j) on the finest level: rigid motions
+// (1,0), (0,1), (-y,x); zero rows at Dirichlet nodes.  (cx, cy, sc) shift and
+// scale the coordinates.
+__device__ __forceinline__ void rigid_rows(int i, int j, int nxn, int nyn, double cx, double cy,
+                                           double sc, double (&b)[3][3]) {
+  const bool bnd = i == 0 || j == 0 || i == nxn - 1 || j == nyn - 1;
+  const double x = (i - cx) * sc, y = (j - cy) * sc;
+  b[0][0] = 1.0; b[0][1] = 0.0; b[0][2] = -y;
+  b[1][0] = 0.0; b[1][1] = 1.0; b[1][2] = x;
+  b[2][0] = b[2][1] = b[2][2] = 0.0;
+  if (bnd) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) b[r][c] = 0.0;
+  }
+}
+
+// Cholesky of a 3x3 SPD matrix G = R^T R (R upper).  Tiny pivots -> zero column.
+__device__ __forceinline__ void chol3(const double (&G)[3][3], double (&R)[3][3]) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) R[r][c] = 0.0;
+  const double scale = fmax(fmax(G[0][0], G[1][1]), G[2][2]);
+  for (int k = 0; k < 3; ++k) {
+    double s = G[k][k];
+    for (int m = 0; m < k; ++m) s -= R[m][k] * R[m][k];
+    if (s <= 1e-24 * scale) continue;  // dependent column: leave R row k zero
+    R[k][k] = sqrt(s);
+    for (int c = k + 1; c < 3; ++c) {
+      double t = G[k][c];
+      for (int m = 0; m < k; ++m) t -= R[m][k] * R[m][c];
+      R[k][c] = t / R[k][k];
+    }
+  }
+}
+
+// q = b R^{-1} for a row vector b (R upper triangular; zero pivots give zero q)
+__device__ __forceinline__ void rsolve_row(const double (&R)[3][3], const double (&b)[3], double (&q)[3]) {
+  for (int c = 0; c < 3; ++c) {
+    double t = b[c];
+    for (int m = 0; m < c; ++m) t -= q[m] * R[m][c];
+    q[c] = R[c][c] != 0.0 ? t / R[c][c] : 0.0;
+  }
+}
+
+// Tentative prolongator by Cholesky-QR applied twice per aggregate, and the
+// coarse near-null space Bc = Q^T B (B with global coordinates on the finest level).
+template <int B>
+__global__ void k_tentative(int nxn, int nyn, int ncx, int ncy, const double* __restrict__ Bnull,
+                            double* __restrict__ Ptent, double* __restrict__ Bc) {
+  const size_t I = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= (size_t)ncx * ncy) return;
+  const size_t nn = (size_t)nxn * nyn, ncn = (size_t)ncx * ncy;
+  const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
+  const int i0 = 3 * Ix, i1 = agg_last(Ix, nxn, ncx), j0 = 3 * Iy, j1 = agg_last(Iy, nyn, ncy);
+  const double cx = 0.5 * (i0 + i1), cy = 0.5 * (j0 + j1);
+  const double gsc = 1.0 / (double)max(nxn, nyn);
+  auto rows = [&](int i, int j, bool local, double (&b)[3][3]) {
+    if constexpr (B == 2) {
+      if (local) rigid_rows(i, j, nxn, nyn, cx, cy, 1.0 / 3.0, b);
+      else rigid_rows(i, j, nxn, nyn, 0.0, 0.0, gsc, b);
+    } else {
+      const size_t n = (size_t)j * nxn + i;
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) b[r][c] = Bnull[(size_t)(r * 3 + c) * nn + n];
+    }
+  };
+  double R1[3][3], R2[3][3];
+  // pass 1: G = B^T B
+  double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      double b[3][3];
+      rows(i, j, true, b);
+      for (int r = 0; r < B; ++r)
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) G[a][c] += b[r][a] * b[r][c];
+    }
+  chol3(G, R1);
+  // pass 2: G2 = (B R1^-1)^T (B R1^-1)
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) G[a][c] = 0.0;
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      double b[3][3];
+      rows(i, j, true, b);
+      for (int r = 0; r < B; ++r) {
+        double q[3];
+        rsolve_row(R1, b[r], q);
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) G[a][c] += q[a] * q[c];
+      }
+    }
+  chol3(G, R2);
+  // pass 3: Q = B R1^-1 R2^-1 written per node; Bc = Q^T B_global
+  double Bcl[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      double b[3][3], bg[3][3];
+      rows(i, j, true, b);
+      rows(i, j, false, bg);
+      const size_t n = (size_t)j * nxn + i;
+      for (int r = 0; r < B; ++r) {
+        double q1[3], q[3];
+        rsolve_row(R1, b[r], q1);
+        rsolve_row(R2, q1, q);
+        for (int c = 0; c < 3; ++c) Ptent[(size_t)(r * 3 + c) * nn + n] = q[c];
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) Bcl[a][c] += q[a] * bg[r][c];
+      }
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) Bc[(size_t)(a * 3 + c) * ncn + I] = Bcl[a][c];
+}
+
+// Per-workgroup max of the Gershgorin bound of D^{-1} A (block Jacobi):
+// max over rows of sum over blocks of |D^{-1} A_nm| row sums.
+template <int B>
+__global__ void __launch_bounds__(kBlock)
+k_gershgorin(const double* __restrict__ A, size_t nn, int nxn, int nyn, double* __restrict__ partials) {
+  __shared__ double lds[16];
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double best = 0.0;
+  if (n < nn) {
+    const int i = (int)(n % nxn), j = (int)(n / nxn);
+    double D[B][B], Di[B][B];
+    load_block<B>(A, nn, nxn, i, j, 0, D);
+    invert_block<B>(D, Di);
+    double rs[B];
+    for (int r = 0; r < B; ++r) rs[r] = 0.0;
+    for (int d = 0; d < 9; ++d) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+      double blk[B][B];
+      load_block<B>(A, nn, nxn, i, j, d, blk);
+      for (int r = 0; r < B; ++r)
+        for (int c = 0; c < B; ++c) {
+          double t = 0.0;
+          for (int k = 0; k < B; ++k) t += Di[r][k] * blk[k][c];
+          rs[r] += fabs(t);
+        }
+    }
+    for (int r = 0; r < B; ++r) best = fmax(best, rs[r]);
+  }
+  best = wave_max(best);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, lds[w]);
+    partials[blockIdx.x] = m;
+  }
+}
+
+// Power iteration for lmax(D^{-1} A) (block Jacobi), device resident and warm
+// started across setups.  One step: y = D^{-1} A x / |x|, partial sums of |y|^2;
+// |x|^2 is read from nrm2_in (device), so no host synchronisation is needed.
+__global__ void k_power_init(double* __restrict__ x, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    // deterministic pseudo-random start (splitmix-style hash of the index)
+    unsigned long long z = (unsigned long long)e * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[e] = 0.5 + (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  }
+}
+
+template <int B>
+__global__ void __launch_bounds__(kBlock)
+k_power_step(const double* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
+             const double* __restrict__ nrm2_in, double* __restrict__ y, double* __restrict__ partials) {
+  __shared__ double lds[16];
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[1] = {0.0};
+  if (n < nn) {
+    const int i = (int)(n % nxn), j = (int)(n / nxn);
+    const double s = nrm2_in[0] > 0.0 ? 1.0 / sqrt(nrm2_in[0]) : 0.0;
+    double Ax[B], D[B][B], Di[B][B];
+    stencil_row<B>(A, nn, nxn, nyn, i, j, x, Ax, D);
+    invert_block<B>(D, Di);
+    for (int r = 0; r < B; ++r) {
+      double t = 0.0;
+      for (int c = 0; c < B; ++c) t += Di[r][c] * Ax[c];
+      t *= s;
+      y[n * B + r] = t;
+      acc[0] += t * t;
+    }
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+// lmax = factor * |y| (|x| = 1 after scaling), never above the Gershgorin bound
+__global__ void k_power_final(const double* __restrict__ nrm2, double factor, double* __restrict__ lmax) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double est = factor * sqrt(fmax(nrm2[0], 0.0));
+    const double g = lmax[0];
+    lmax[0] = (est > 0.0 && est < g) ? est : g;
+  }
+}
+
+__global__ void k_finish_max(const double* __restrict__ partials, int nblocks, double* __restrict__ out) {
+  __shared__ double lds[512];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmax(m, partials[b]);
+  lds[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = lds[0];
+}
+
+// Smoothed prolongator P = (I - omega D^{-1} A) Ptent, omega = omega_scale * 4/(3 lmax)
+template <int B>
+__global__ void __launch_bounds__(kBlock)
+k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
+           const double* __restrict__ Ptent, const double* __restrict__ lmax, double omega_scale,
+           double* __restrict__ P) {
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  const double omega = omega_scale * 4.0 / (3.0 * lmax[0]);
+  double D[B][B], Di[B][B];
+  load_block<B>(A, nn, nxn, i, j, 0, D);
+  invert_block<B>(D, Di);
+  const int ax[2] = {agg_of(i, ncx), agg_other(i, nxn, ncx)};
+  const int ay[2] = {agg_of(j, ncy), agg_other(j, nyn, ncy)};
+  for (int s = 0; s < 4; ++s) {
+    const int Jx = ax[s & 1], Jy = ay[s >> 1];
+    double acc[B][3];
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < 3; ++c) acc[r][c] = 0.0;
+    if (Jx >= 0 && Jy >= 0) {
+      for (int d = 0; d < 9; ++d) {
+        const int ii = i + kDI[d], jj = j + kDJ[d];
+        if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+        if (agg_of(ii, ncx) != Jx || agg_of(jj, ncy) != Jy) continue;
+        double blk[B][B];
+        load_block<B>(A, nn, nxn, i, j, d, blk);
+        const size_t m = (size_t)jj * nxn + ii;
+        for (int r = 0; r < B; ++r)
+          for (int k = 0; k < B; ++k) {
+            const double a = blk[r][k];
+            for (int c = 0; c < 3; ++c) acc[r][c] += a * Ptent[(size_t)(k * 3 + c) * nn + m];
+          }
+      }
+    }
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double t = 0.0;
+        for (int k = 0; k < B; ++k) t += Di[r][k] * acc[k][c];
+        double val = -omega * t;
+        if (s == 0) val += Ptent[(size_t)(r * 3 + c) * nn + n];
+        if (Jx < 0 || Jy < 0) val = 0.0;
+        P[((size_t)(s * B + r) * 3 + c) * nn + n] = val;
+      }
+  }
+}
+
+// Galerkin coarse operator Ac = P^T A P in the 5-block symmetric storage (B = 3)
+template <int B>
+__global__ void __launch_bounds__(128)
+k_galerkin(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
+           const double* __restrict__ P, double* __restrict__ Ac) {
+  const size_t ncn = (size_t)ncx * ncy;
+  const size_t I = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= ncn) return;
+  const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
+  const int tJx[5] = {Ix, Ix + 1, Ix, Ix + 1, Ix - 1};
+  const int tJy[5] = {Iy, Iy, Iy + 1, Iy + 1, Iy + 1};
+  double acc[5][3][3];
+  for (int t = 0; t < 5; ++t)
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) acc[t][a][c] = 0.0;
+  const int i0 = max(3 * Ix - 1, 0), i1 = min(agg_last(Ix, nxn, ncx) + 1, nxn - 1);
+  const int j0 = max(3 * Iy - 1, 0), j1 = min(agg_last(Iy, nyn, ncy) + 1, nyn - 1);
+  for (int j = j0; j <= j1; ++j) {
+    const int syI = slot1(j, nyn, ncy, Iy);
+    if (syI < 0) continue;
+    for (int i = i0; i <= i1; ++i) {
+      const int sxI = slot1(i, nxn, ncx, Ix);
+      if (sxI < 0) continue;
+      const int sI = sxI + 2 * syI;
+      const size_t n = (size_t)j * nxn + i;
+      double PI[B][3];
+      for (int r = 0; r < B; ++r)
+        for (int c = 0; c < 3; ++c) PI[r][c] = P[((size_t)(sI * B + r) * 3 + c) * nn + n];
+      for (int d = 0; d < 9; ++d) {
+        const int ii = i + kDI[d], jj = j + kDJ[d];
+        if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+        double blk[B][B];
+        load_block<B>(A, nn, nxn, i, j, d, blk);
+        // Y = PI^T blk  (3 x B)
+        double Y[3][B];
+        for (int a = 0; a < 3; ++a)
+          for (int k = 0; k < B; ++k) {
+            double t = 0.0;
+            for (int r = 0; r < B; ++r) t += PI[r][a] * blk[r][k];
+            Y[a][k] = t;
+          }
+        const size_t m = (size_t)jj * nxn + ii;
+        for (int t = 0; t < 5; ++t) {
+          const int Jx = tJx[t], Jy = tJy[t];
+          if (Jx < 0 || Jx >= ncx || Jy >= ncy) continue;
+          const int sx = slot1(ii, nxn, ncx, Jx), sy = slot1(jj, nyn, ncy, Jy);
+          if (sx < 0 || sy < 0) continue;
+          const int sJ = sx + 2 * sy;
+          for (int k = 0; k < B; ++k)
+            for (int c = 0; c < 3; ++c) {
+              const double pv = P[((size_t)(sJ * B + k) * 3 + c) * nn + m];
+              for (int a = 0; a < 3; ++a) acc[t][a][c] += Y[a][k] * pv;
+            }
+        }
+      }
+    }
+  }
+  // symmetrise the diagonal block; guard empty coarse dofs
+  for (int a = 0; a < 3; ++a)
+    for (int c = a + 1; c < 3; ++c) {
+      const double s = 0.5 * (acc[0][a][c] + acc[0][c][a]);
+      acc[0][a][c] = acc[0][c][a] = s;
+    }
+  for (int a = 0; a < 3; ++a)
+    if (acc[0][a][a] == 0.0) acc[0][a][a] = 1.0;
+  for (int t = 0; t < 5; ++t) {
+    const int Jx = tJx[t], Jy = tJy[t];
+    const bool valid = !(Jx < 0 || Jx >= ncx || Jy >= ncy);
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c)
+        Ac[(size_t)(t * 9 + a * 3 + c) * ncn + I] = valid ? acc[t][a][c] : 0.0;
+  }
+}
+
+// Dense matrix (row-major nd x nd, nd = B*nn) of a stencil level.  Zero-filled by caller.
+template <int B>
+__global__ void k_to_dense(const double* __restrict__ A, size_t nn, int nxn, int nyn, double* __restrict__ M) {
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  const size_t nd = (size_t)B * nn;
+  for (int d = 0; d < 9; ++d) {
+    const int ii = i + kDI[d], jj = j + kDJ[d];
+    if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+    double blk[B][B];
+    load_block<B>(A, nn, nxn, i, j, d, blk);
+    const size_t m = (size_t)jj * nxn + ii;
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < B; ++c) M[(n * B + r) * nd + m * B + c] = blk[r][c];
+  }
+}
+
+// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting needed), one workgroup.
+__global__ void __launch_bounds__(1024) k_gauss_jordan(double* __restrict__ M, int nd) {
+  __shared__ double rowk[1024];
+  __shared__ double colk[1024];
+  for (int k = 0; k < nd; ++k) {
+    const double piv = M[(size_t)k * nd + k];
+    const double ip = piv != 0.0 ? 1.0 / piv : 0.0;
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+      rowk[t] = M[(size_t)k * nd + t];
+      colk[t] = M[(size_t)t * nd + k];
+    }
+    __syncthreads();
+    for (size_t e = threadIdx.x; e < (size_t)nd * nd; e += blockDim.x) {
+      const int r = (int)(e / nd), c = (int)(e % nd);
+      double v;
+      if (r == k && c == k) v = ip;
+      else if (r == k) v = rowk[c] * ip;
+      else if (c == k) v = -colk[r] * ip;
+      else v = M[e] - colk[r] * rowk[c] * ip;
+      M[e] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename TM, typename TV>
+__global__ void k_dense_apply(const TM* __restrict__ M, int nd, const TV* __restrict__ b, TV* __restrict__ x) {
+  using TA = typename Acc<TV>::type;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nd) return;
+  TA s = TA(0);
+  for (int c = 0; c < nd; ++c) s += (TA)M[(size_t)r * nd + c] * (TA)b[c];
+  x[r] = (TV)s;
+}
+
+template <typename TS, typename TD>
+__global__ void k_convert(const TS* __restrict__ s, TD* __restrict__ d, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    d[e] = (TD)s[e];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+T* dalloc(size_t n) {
+  void* p = nullptr;
+  VP_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+void free_vectors(Level& L) {
+  void** v[5] = {&L.x, &L.b, &L.r, &L.d0, &L.d1};
+  for (auto pp : v) {
+    if (*pp) (void)hipFree(*pp);
+    *pp = nullptr;
+  }
+}
+
+template <typename TS, typename TD>
+void convert(hipStream_t s, const TS* src, TD* dst, size_t n) {
+  hipLaunchKernelGGL((k_convert<TS, TD>), dim3(std::min<size_t>((n + 255) / 256, 4096) + 1), dim3(256), 0, s,
+                     src, dst, n);
+  VP_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void amg_free(vp_ctx c) {
+  for (int l = 0; l < kMaxLevels; ++l) {
+    Level& L = c->lev[l];
+    if (l > 0) dfree(L.A64);
+    dfree(L.A32);
+    dfree(L.Ptent);
+    dfree(L.P64);
+    dfree(L.P32);
+    dfree(L.Bnull);
+    dfree(L.lmax);
+    dfree(L.pv0);
+    dfree(L.pv1);
+    dfree(L.pnrm);
+    dfree(L.Ainv64);
+    dfree(L.Ainv32);
+    free_vectors(L);
+    L = Level();
+  }
+  dfree(c->dense);
+  c->nlev = 0;
+  c->amg_struct = false;
+  c->amg_ready = false;
+}
+
+// Build the level structure (geometry only: grids, tentative prolongators,
+// near-null spaces).  The finest operator is the context's assembled K.
+void amg_build_structure(vp_ctx c, double* K, int max_coarse) {
+  amg_free(c);
+  c->max_coarse = max_coarse;
+  int nxn = c->ec.nxn, nyn = c->ec.nyn, B = 2;
+  int l = 0;
+  for (;; ++l) {
+    Level& L = c->lev[l];
+    L.nxn = nxn; L.nyn = nyn; L.B = B;
+    L.nn = (size_t)nxn * nyn;
+    L.A64 = (l == 0) ? K : dalloc<double>((size_t)5 * B * B * L.nn);
+    L.lmax = dalloc<double>(1);
+    const bool last = (size_t)B * L.nn <= (size_t)max_coarse || nxn < 6 || nyn < 6 || l == kMaxLevels - 1;
+    if (last) break;
+    L.ncx = nxn / 3;
+    L.ncy = nyn / 3;
+    L.Ptent = dalloc<double>((size_t)B * 3 * L.nn);
+    L.P64 = dalloc<double>((size_t)4 * B * 3 * L.nn);
+    Level& Nx = c->lev[l + 1];
+    const size_t ncn = (size_t)L.ncx * L.ncy;
+    Nx.Bnull = dalloc<double>(9 * ncn);
+    const unsigned g = (unsigned)((ncn + 127) / 128);
+    if (B == 2)
+      hipLaunchKernelGGL(k_tentative<2>, dim3(g), dim3(128), 0, c->stream, nxn, nyn, L.ncx, L.ncy,
+                         (const double*)nullptr, L.Ptent, Nx.Bnull);
+    else
+      hipLaunchKernelGGL(k_tentative<3>, dim3(g), dim3(128), 0, c->stream, nxn, nyn, L.ncx, L.ncy,
+                         (const double*)L.Bnull, L.Ptent, Nx.Bnull);
+    VP_LAUNCH_CHECK();
+    nxn = L.ncx;
+    nyn = L.ncy;
+    B = 3;
+  }
+  c->nlev = l + 1;
+  Level& C = c->lev[c->nlev - 1];
+  const size_t nd = (size_t)C.B * C.nn;
+  if (nd > 1024) throw Error(VP_EINVAL, "coarsest level too large for the dense solve");
+  C.Ainv64 = dalloc<double>(nd * nd);
+  c->amg_struct = true;
+}
+
+namespace {
+
+template <typename TV>
+void alloc_vectors(vp_ctx c) {
+  for (int l = 0; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    free_vectors(L);
+    const size_t n = (size_t)L.B * L.nn;
+    L.x = dalloc<TV>(n);
+    L.b = dalloc<TV>(n);
+    L.r = dalloc<TV>(n);
+    L.d0 = dalloc<TV>(n);
+    L.d1 = dalloc<TV>(n);
+  }
+}
+
+}  // namespace
+
+// Numeric setup on the current finest operator.
+void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
+  if (!c->amg_struct) throw Error(VP_ESTATE, "AMG structure missing");
+  hipStream_t s = c->stream;
+  for (int l = 0; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    const unsigned g = (unsigned)((L.nn + kBlock - 1) / kBlock);
+    if (L.B == 2)
+      hipLaunchKernelGGL(k_gershgorin<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, c->partials);
+    else
+      hipLaunchKernelGGL(k_gershgorin<3>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, c->partials);
+    VP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finish_max, dim3(1), dim3(512), 0, s, c->partials, (int)g, L.lmax);
+    VP_LAUNCH_CHECK();
+    if (l == c->nlev - 1) break;
+    // power iteration on D^{-1} A, warm started from the previous setup's vector
+    {
+      const size_t nd = (size_t)L.B * L.nn;
+      int its = c->power_its_warm;
+      if (!L.pv0) {
+        L.pv0 = dalloc<double>(nd);
+        L.pv1 = dalloc<double>(nd);
+        L.pnrm = dalloc<double>(2);
+        hipLaunchKernelGGL(k_power_init, dim3(1024), dim3(256), 0, s, L.pv0, nd);
+        VP_LAUNCH_CHECK();
+        its = c->power_its_cold;
+      }
+      // |x|^2 of the start vector
+      launch_dot(s, L.pv0, L.pv0, nd, c->partials);
+      launch_finish_sum(s, c->partials, kRedBlocks, 1, L.pnrm);
+      for (int k = 0; k < its; ++k) {
+        double* xin = (k & 1) ? L.pv1 : L.pv0;
+        double* yout = (k & 1) ? L.pv0 : L.pv1;
+        if (L.B == 2)
+          hipLaunchKernelGGL(k_power_step<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, xin,
+                             L.pnrm + (k & 1), yout, c->partials);
+        else
+          hipLaunchKernelGGL(k_power_step<3>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, xin,
+                             L.pnrm + (k & 1), yout, c->partials);
+        VP_LAUNCH_CHECK();
+        launch_finish_sum(s, c->partials, (int)g, 1, L.pnrm + ((k + 1) & 1));
+      }
+      hipLaunchKernelGGL(k_power_final, dim3(1), dim3(64), 0, s, L.pnrm + (its & 1), c->power_factor, L.lmax);
+      VP_LAUNCH_CHECK();
+      if (its & 1) std::swap(L.pv0, L.pv1);  // keep the latest iterate in pv0
+    }
+    if (L.B == 2)
+      hipLaunchKernelGGL(k_smooth_p<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         L.Ptent, L.lmax, omega_scale, L.P64);
+    else
+      hipLaunchKernelGGL(k_smooth_p<3>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         L.Ptent, L.lmax, omega_scale, L.P64);
+    VP_LAUNCH_CHECK();
+    Level& N = c->lev[l + 1];
+    const unsigned gc = (unsigned)((N.nn + 127) / 128);
+    if (L.B == 2)
+      hipLaunchKernelGGL(k_galerkin<2>, dim3(gc), dim3(128), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         L.P64, N.A64);
+    else
+      hipLaunchKernelGGL(k_galerkin<3>, dim3(gc), dim3(128), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         L.P64, N.A64);
+    VP_LAUNCH_CHECK();
+  }
+  // coarsest: dense inverse
+  Level& C = c->lev[c->nlev - 1];
+  const int nd = C.B * (int)C.nn;
+  VP_HIP(hipMemsetAsync(C.Ainv64, 0, (size_t)nd * nd * sizeof(double), s));
+  const unsigned gd = (unsigned)((C.nn + 127) / 128);
+  if (C.B == 2)
+    hipLaunchKernelGGL(k_to_dense<2>, dim3(gd), dim3(128), 0, s, C.A64, C.nn, C.nxn, C.nyn, C.Ainv64);
+  else
+    hipLaunchKernelGGL(k_to_dense<3>, dim3(gd), dim3(128), 0, s, C.A64, C.nn, C.nxn, C.nyn, C.Ainv64);
+  VP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, C.Ainv64, nd);
+  VP_LAUNCH_CHECK();
+  // reduced-precision copies
+  if (precision != VP_PREC_FP64) {
+    for (int l = 0; l < c->nlev; ++l) {
+      Level& L = c->lev[l];
+      const size_t na = (size_t)5 * L.B * L.B * L.nn;
+      if (!L.A32) L.A32 = dalloc<float>(na);
+      convert(s, L.A64, L.A32, na);
+      if (L.P64) {
+        const size_t np = (size_t)4 * L.B * 3 * L.nn;
+        if (!L.P32) L.P32 = dalloc<float>(np);
+        convert(s, L.P64, L.P32, np);
+      }
+      if (L.Ainv64) {
+        if (!L.Ainv32) L.Ainv32 = dalloc<float>((size_t)nd * nd);
+        convert(s, L.Ainv64, L.Ainv32, (size_t)nd * nd);
+      }
+    }
+  }
+  if (c->amg_prec != precision || c->lev[0].x == nullptr) {
+    if (precision == VP_PREC_FP64) alloc_vectors<double>(c);
+    else alloc_vectors<float>(c);
+    c->amg_prec = precision;
+  }
+  // spectral bounds to the host (one synchronisation per setup)
+  for (int l = 0; l < c->nlev; ++l)
+    VP_HIP(hipMemcpyAsync(c->hscal + l, c->lev[l].lmax, sizeof(double), hipMemcpyDeviceToHost, s));
+  VP_HIP(hipStreamSynchronize(s));
+  for (int l = 0; l < c->nlev; ++l) {
+    c->lev[l].lmax_h = c->hscal[l];
+    if (!(c->hscal[l] > 0.0) || !std::isfinite(c->hscal[l]))
+      throw Error(VP_ENONFINITE, "AMG setup: non-finite or non-positive spectral bound");
+  }
+  c->amg_ready = true;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int B, typename TM, typename TV>
+void sten_resid(hipStream_t s, const Level& L, const TM* A, const TV* x, const TV* b, TV* r) {
+  hipLaunchKernelGGL((k_sten_resid<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A, L.nn, L.nxn,
+                     L.nyn, x, b, r);
+  VP_LAUNCH_CHECK();
+}
+
+template <int B, typename TM, typename TV>
+void smooth(hipStream_t s, const Level& L, const TM* A, const TV* src, TV* x, bool zero_start,
+            int degree, double ratio) {
+  using TA = typename Acc<TV>::type;
+  TV* r = (TV*)L.r;
+  TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
+  const double lmax = L.lmax_h, lmin = lmax / ratio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A, L.nn, src, r,
+                     d[0], x, (TA)(1.0 / theta), zero_start ? 0 : 1, zero_start ? 1 : 0);
+  VP_LAUNCH_CHECK();
+  for (int k = 1; k < degree; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    const double cdd = rn * rho, cdr = 2.0 * rn / delta;
+    hipLaunchKernelGGL((k_cheb_step<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A, L.nn, L.nxn,
+                       L.nyn, d[(k - 1) & 1], r, d[k & 1], x, (TA)cdd, (TA)cdr);
+    VP_LAUNCH_CHECK();
+    rho = rn;
+  }
+  // leave r = b - A x after pre-smoothing (used by the restriction)
+  if (zero_start) sten_resid<B>(s, L, A, (const TV*)d[(degree - 1) & 1], (const TV*)r, r);
+}
+
+template <typename TV>
+void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
+  hipStream_t s = c->stream;
+  Level& L = c->lev[l];
+  const bool fp64 = std::is_same<TV, double>::value;
+  if (l == c->nlev - 1) {
+    const int nd = L.B * (int)L.nn;
+    if (fp64)
+      hipLaunchKernelGGL((k_dense_apply<double, TV>), dim3((nd + 127) / 128), dim3(128), 0, s, L.Ainv64, nd, b, x);
+    else
+      hipLaunchKernelGGL((k_dense_apply<float, TV>), dim3((nd + 127) / 128), dim3(128), 0, s, L.Ainv32, nd, b, x);
+    VP_LAUNCH_CHECK();
+    return;
+  }
+  Level& N = c->lev[l + 1];
+  auto run = [&](auto bconst, auto tm_tag) {
+    constexpr int B = decltype(bconst)::value;
+    using TM = decltype(tm_tag);
+    const TM* A = fp64 ? (const TM*)L.A64 : (const TM*)L.A32;
+    const TM* P = fp64 ? (const TM*)L.P64 : (const TM*)L.P32;
+    smooth<B, TM, TV>(s, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
+    hipLaunchKernelGGL((k_restrict<B, TM, TV>), dim3((unsigned)((N.nn + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, P, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)L.r, (TV*)N.b);
+    VP_LAUNCH_CHECK();
+    vcycle_level<TV>(c, l + 1, (const TV*)N.b, (TV*)N.x);
+    hipLaunchKernelGGL((k_prolong_add<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
+                       L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
+    VP_LAUNCH_CHECK();
+    sten_resid<B>(s, L, A, (const TV*)x, b, (TV*)L.r);
+    smooth<B, TM, TV>(s, L, A, (const TV*)L.r, x, false, c->cheb_degree, c->cheb_ratio);
+  };
+  using TMT = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+  if (L.B == 2) run(std::integral_constant<int, 2>(), TMT());
+  else run(std::integral_constant<int, 3>(), TMT());
+}
+
+}  // namespace
+
+// z = M^{-1} r (FP64 in/out; V-cycle in the setup's precision)
+void amg_apply(vp_ctx c, const double* r, double* z) {
+  if (!c->amg_ready) throw Error(VP_ESTATE, "AMG not set up");
+  Level& L = c->lev[0];
+  const size_t n = (size_t)L.B * L.nn;
+  if (c->amg_prec == VP_PREC_FP64) {
+    vcycle_level<double>(c, 0, r, z);
+  } else {
+    launch_cast(c->stream, r, (float*)L.b, n);
+    // level-0 x must not alias L.b; the cycle writes L.x
+    vcycle_level<float>(c, 0, (const float*)L.b, (float*)L.x);
+    launch_cast(c->stream, (const float*)L.x, z, n);
+  }
+}
+
+void launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials) {
+  hipLaunchKernelGGL(k_apply_fine, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, x, y,
+                     partials);
+  VP_LAUNCH_CHECK();
+}
+
+}  // namespace vp

@@ -1,0 +1,436 @@
+// Element kernels on the structured Q1 mesh: per-step precompute, residual and
+// energy, linearised-operator assembly, dual (pi) update.
+//
+// Every quadrature-point quantity is computed in Mandel form: for a symmetric
+// 2x2 tensor X, m(X) = (X11, X22, sqrt2 X12), so m(X).m(Y) = X:Y.  With e the
+// ellipse ratio, tau(v) = e^-1 eps'(v) + tr(eps)/2 I (Sec. 4) becomes
+//   m(tau) = (c1 ux + c2 vy, c2 ux + c1 vy, s2e (uy + vx)),
+//   c1 = (1 + 1/e)/2, c2 = (1 - 1/e)/2, s2e = 1/(sqrt2 e),
+// and Delta = sqrt(Delta_min^2 + 2 m(tau).m(tau)).
+//
+// Node-centred kernels gather the contributions of the (up to) four cells around
+// their node, so no two threads write the same output and results are
+// deterministic without atomics.
+#include "vp_internal.h"
+
+namespace vp {
+
+namespace {
+
+constexpr double kG0 = 0.21132486540518711775;  // 1/2 - 1/(2 sqrt 3)
+constexpr double kG1 = 0.78867513459481288225;  // 1/2 + 1/(2 sqrt 3)
+constexpr double kSqrt2 = 1.41421356237309504880;
+
+struct Shape {
+  double N[4], gx[4], gy[4];
+};
+
+// Q1 shape functions on the cell at Gauss point q = qx + 2 qy; corners SW, SE, NW, NE.
+__device__ __forceinline__ Shape shape_at(int q, double ihx, double ihy) {
+  const double xi = (q & 1) ? kG1 : kG0, eta = (q & 2) ? kG1 : kG0;
+  Shape s;
+  s.N[0] = (1 - xi) * (1 - eta); s.N[1] = xi * (1 - eta);
+  s.N[2] = (1 - xi) * eta;       s.N[3] = xi * eta;
+  s.gx[0] = -(1 - eta) * ihx; s.gx[1] = (1 - eta) * ihx; s.gx[2] = -eta * ihx; s.gx[3] = eta * ihx;
+  s.gy[0] = -(1 - xi) * ihy;  s.gy[1] = -xi * ihy;       s.gy[2] = (1 - xi) * ihy; s.gy[3] = xi * ihy;
+  return s;
+}
+
+struct CellVel {
+  double x[4], y[4];
+};
+
+__device__ __forceinline__ void load_cell(const ElemConst& c, const double* __restrict__ v,
+                                          const double* __restrict__ dv, double alpha, int ci,
+                                          int cj, CellVel& out) {
+  const size_t sw = (size_t)cj * c.nxn + ci;
+  const size_t id[4] = {sw, sw + 1, sw + c.nxn, sw + c.nxn + 1};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const double2 t = reinterpret_cast<const double2*>(v)[id[a]];
+    out.x[a] = t.x;
+    out.y[a] = t.y;
+    if (dv) {
+      const double2 d = reinterpret_cast<const double2*>(dv)[id[a]];
+      out.x[a] = fma(alpha, d.x, out.x[a]);
+      out.y[a] = fma(alpha, d.y, out.y[a]);
+    }
+  }
+}
+
+struct Kin {
+  double u, w;       // velocity at the point
+  double ux, uy, wx, wy;
+  double t1, t2, t3; // m(tau(v))
+  double delta;
+};
+
+__device__ __forceinline__ Kin kinematics(const ElemConst& c, const Shape& s, const CellVel& v) {
+  Kin k;
+  k.u = k.w = k.ux = k.uy = k.wx = k.wy = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    k.u = fma(s.N[a], v.x[a], k.u);
+    k.w = fma(s.N[a], v.y[a], k.w);
+    k.ux = fma(s.gx[a], v.x[a], k.ux);
+    k.uy = fma(s.gy[a], v.x[a], k.uy);
+    k.wx = fma(s.gx[a], v.y[a], k.wx);
+    k.wy = fma(s.gy[a], v.y[a], k.wy);
+  }
+  k.t1 = c.c1 * k.ux + c.c2 * k.wy;
+  k.t2 = c.c2 * k.ux + c.c1 * k.wy;
+  k.t3 = c.s2e * (k.uy + k.wx);
+  k.delta = sqrt(c.dmin2 + 2.0 * (k.t1 * k.t1 + k.t2 * k.t2 + k.t3 * k.t3));
+  return k;
+}
+
+__device__ __forceinline__ double interp(const Shape& s, const double f[4]) {
+  return s.N[0] * f[0] + s.N[1] * f[1] + s.N[2] * f[2] + s.N[3] * f[3];
+}
+
+__device__ __forceinline__ bool is_boundary(const ElemConst& c, int i, int j) {
+  return i == 0 || j == 0 || i == c.nx || j == c.ny;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// per-step precompute: P, rho*H per cell; load vector F per node (eq. F)
+// ---------------------------------------------------------------------------
+__global__ void k_cell_coeffs(ElemConst c, const double* __restrict__ H, const double* __restrict__ A,
+                              double* __restrict__ P, double* __restrict__ rhoH) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)c.nx * c.ny) return;
+  const double h = H[e];
+  P[e] = c.P_star * h * exp(-c.C_strength * (1.0 - A[e]));
+  rhoH[e] = c.rho_ice * h;
+}
+
+__global__ void k_load_vector(ElemConst c, const double* __restrict__ rhoH,
+                              const double* __restrict__ va, const double* __restrict__ vo,
+                              const double* __restrict__ vn, double* __restrict__ F) {
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= (size_t)c.nxn * c.nyn) return;
+  const int i = (int)(n % c.nxn), j = (int)(n / c.nxn);
+  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  double fx = 0.0, fy = 0.0;
+  for (int dyc = 0; dyc < 2; ++dyc)
+    for (int dxc = 0; dxc < 2; ++dxc) {
+      const int ci = i - 1 + dxc, cj = j - 1 + dyc;
+      if (ci < 0 || cj < 0 || ci >= c.nx || cj >= c.ny) continue;
+      const int a = (dxc ? 0 : 1) + (dyc ? 0 : 2);
+      CellVel A_, O_, Nv;
+      load_cell(c, va, nullptr, 0.0, ci, cj, A_);
+      load_cell(c, vo, nullptr, 0.0, ci, cj, O_);
+      load_cell(c, vn, nullptr, 0.0, ci, cj, Nv);
+      const double rh = rhoH[(size_t)cj * c.nx + ci];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const Shape s = shape_at(q, ihx, ihy);
+        const double ax = interp(s, A_.x), ay = interp(s, A_.y);
+        const double ox = interp(s, O_.x), oy = interp(s, O_.y);
+        const double nxq = interp(s, Nv.x), nyq = interp(s, Nv.y);
+        const double sa = c.cda * sqrt(ax * ax + ay * ay);
+        // rhoH v^n - dt rhoH f_c e_r x (v^n - v_o) + dt tau_atm,  e_r x u = (-u_y, u_x)
+        const double gx_ = rh * nxq + c.dt * rh * c.fc * (nyq - oy) + c.dt * sa * ax;
+        const double gy_ = rh * nyq - c.dt * rh * c.fc * (nxq - ox) + c.dt * sa * ay;
+        fx = fma(c.wq * s.N[a], gx_, fx);
+        fy = fma(c.wq * s.N[a], gy_, fy);
+      }
+    }
+  reinterpret_cast<double2*>(F)[n] = make_double2(fx, fy);
+}
+
+void launch_precompute(vp_ctx c, const double* H, const double* A, const double* va,
+                       const double* vo, const double* vprev) {
+  const size_t nc = c->ncell;
+  hipLaunchKernelGGL(k_cell_coeffs, dim3((unsigned)((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     c->stream, c->ec, H, A, c->P, c->rhoH);
+  VP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_load_vector, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec,
+                     c->rhoH, va, vo, vprev, c->F);
+  VP_LAUNCH_CHECK();
+  VP_HIP(hipMemcpyAsync(c->vo, vo, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+}
+
+// ---------------------------------------------------------------------------
+// residual R(v) = A(v, phi) - F(phi) (eq. A with eq. sigma) and energy Phi (eq. energy)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_residual(ElemConst c, const double* __restrict__ v, const double* __restrict__ dv, double alpha,
+           const double* __restrict__ vo, const double* __restrict__ F,
+           const double* __restrict__ P, const double* __restrict__ rhoH,
+           double* __restrict__ r, double* __restrict__ partials) {
+  __shared__ double lds[16 * 3];
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (n < (size_t)c.nxn * c.nyn) {
+    const int i = (int)(n % c.nxn), j = (int)(n / c.nxn);
+    const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+    double rx = 0.0, ry = 0.0, ecell = 0.0, eabs = 0.0;
+    for (int dyc = 0; dyc < 2; ++dyc)
+      for (int dxc = 0; dxc < 2; ++dxc) {
+        const int ci = i - 1 + dxc, cj = j - 1 + dyc;
+        if (ci < 0 || cj < 0 || ci >= c.nx || cj >= c.ny) continue;
+        const int a = (dxc ? 0 : 1) + (dyc ? 0 : 2);
+        const bool owner = dxc && dyc;  // this node is the cell's SW corner
+        CellVel V, O;
+        load_cell(c, v, dv, alpha, ci, cj, V);
+        load_cell(c, vo, nullptr, 0.0, ci, cj, O);
+        const size_t e = (size_t)cj * c.nx + ci;
+        const double Pc = P[e], rh = rhoH[e];
+        double en = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const Shape s = shape_at(q, ihx, ihy);
+          const Kin k = kinematics(c, s, V);
+          // (P/Delta) tau(v):tau(phi) - (P/2) tr eps(phi), times dt
+          const double kd = c.dt * Pc / k.delta, hp = 0.5 * c.dt * Pc;
+          const double Sx = kd * (c.c1 * k.t1 + c.c2 * k.t2) - hp;
+          const double Sy = kd * (c.c2 * k.t1 + c.c1 * k.t2) - hp;
+          const double Sxy = kd * c.s2e * k.t3;
+          // mass and ocean drag: rhoH v - dt tau_ocean(v)
+          const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
+          const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
+          const double fx = rh * k.u - c.dt * c.cdo * wn * wx_;
+          const double fy = rh * k.w - c.dt * c.cdo * wn * wy_;
+          rx += c.wq * (Sx * s.gx[a] + Sxy * s.gy[a] + fx * s.N[a]);
+          ry += c.wq * (Sy * s.gy[a] + Sxy * s.gx[a] + fy * s.N[a]);
+          if (owner) {
+            en += c.wq * (0.5 * rh * (k.u * k.u + k.w * k.w) +
+                          c.dt * (0.5 * Pc * (k.delta - (k.ux + k.wy)) + c.cdo * wn * wn * wn / 3.0));
+          }
+        }
+        if (owner) { ecell += en; eabs += fabs(en); }
+      }
+    const double2 Fn = reinterpret_cast<const double2*>(F)[n];
+    double2 vn = reinterpret_cast<const double2*>(v)[n];
+    if (dv) {
+      const double2 d = reinterpret_cast<const double2*>(dv)[n];
+      vn.x = fma(alpha, d.x, vn.x);
+      vn.y = fma(alpha, d.y, vn.y);
+    }
+    rx -= Fn.x;
+    ry -= Fn.y;
+    if (is_boundary(c, i, j)) rx = ry = 0.0;
+    if (r) reinterpret_cast<double2*>(r)[n] = make_double2(rx, ry);
+    const double fv = Fn.x * vn.x + Fn.y * vn.y;
+    acc[0] = rx * rx + ry * ry;
+    acc[1] = ecell - fv;
+    acc[2] = eabs + fabs(fv);
+  }
+  block_sum<3>(acc, lds);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 3 + 0] = acc[0];
+    partials[blockIdx.x * 3 + 1] = acc[1];
+    partials[blockIdx.x * 3 + 2] = acc[2];
+  }
+}
+
+void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, double* r,
+                     double* partials, unsigned* nblocks) {
+  const unsigned g = grid_for(c->nn);
+  hipLaunchKernelGGL(k_residual, dim3(g), dim3(kBlock), 0, c->stream, c->ec, v, dv, alpha, c->vo,
+                     c->F, c->P, c->rhoH, r, partials);
+  VP_LAUNCH_CHECK();
+  *nblocks = g;
+}
+
+// ---------------------------------------------------------------------------
+// operator assembly (eq. linearSVNewton + eq. modification; eq. standardNewton1/2)
+// ---------------------------------------------------------------------------
+// Per Gauss point the viscous part is a symmetric 3x3 Mandel matrix C:
+//   svN : C = dt P/Delta [I - (a p^T + p a^T)/(Delta s)], a = m(tau(v_l)), p = m(pi_l),
+//         s = max(1, sqrt(2 p.p))
+//   stdN: C = dt P/Delta [I - 2 a a^T / Delta^2]
+// and the mass/drag part is the symmetric 2x2 matrix
+//   M = rhoH I + dt C_o rho_o (|w| I + w w^T / |w|),  w = v_o - v_l.
+// The element block of nodes (a, b) is sum_q wq [B_a^T C B_b + N_a N_b M], where
+// B_a maps the two nodal dofs of node a to m(tau(N_a e_d)).
+__global__ void __launch_bounds__(kBlock)
+k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__ pi, int variant,
+           const double* __restrict__ vo, const double* __restrict__ P,
+           const double* __restrict__ rhoH, double* __restrict__ K) {
+  const size_t nn = (size_t)c.nxn * c.nyn;
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % c.nxn), j = (int)(n / c.nxn);
+  const size_t ncell = (size_t)c.nx * c.ny;
+  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  double blk[5][4];
+#pragma unroll
+  for (int b = 0; b < 5; ++b)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) blk[b][k] = 0.0;
+
+  for (int dyc = 0; dyc < 2; ++dyc)
+    for (int dxc = 0; dxc < 2; ++dxc) {
+      const int ci = i - 1 + dxc, cj = j - 1 + dyc;
+      if (ci < 0 || cj < 0 || ci >= c.nx || cj >= c.ny) continue;
+      const int a = (dxc ? 0 : 1) + (dyc ? 0 : 2);
+      const int ax = a & 1, ay = a >> 1;
+      CellVel V, O;
+      load_cell(c, v, nullptr, 0.0, ci, cj, V);
+      load_cell(c, vo, nullptr, 0.0, ci, cj, O);
+      const size_t e = (size_t)cj * c.nx + ci;
+      const double Pc = P[e], rh = rhoH[e];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const Shape s = shape_at(q, ihx, ihy);
+        const Kin k = kinematics(c, s, V);
+        const double d = k.delta;
+        const double base = c.dt * Pc / d;
+        double C11, C12, C13, C22, C23, C33;
+        if (variant == VP_SVN) {
+          const double p1 = pi[(size_t)(q * 3 + 0) * ncell + e];
+          const double p2 = pi[(size_t)(q * 3 + 1) * ncell + e];
+          const double p3 = kSqrt2 * pi[(size_t)(q * 3 + 2) * ncell + e];
+          const double sn = fmax(1.0, sqrt(2.0 * (p1 * p1 + p2 * p2 + p3 * p3)));
+          const double f = base / (d * sn);
+          C11 = base - f * 2.0 * k.t1 * p1;
+          C22 = base - f * 2.0 * k.t2 * p2;
+          C33 = base - f * 2.0 * k.t3 * p3;
+          C12 = -f * (k.t1 * p2 + p1 * k.t2);
+          C13 = -f * (k.t1 * p3 + p1 * k.t3);
+          C23 = -f * (k.t2 * p3 + p2 * k.t3);
+        } else {
+          const double f = 2.0 * base / (d * d);
+          C11 = base - f * k.t1 * k.t1;
+          C22 = base - f * k.t2 * k.t2;
+          C33 = base - f * k.t3 * k.t3;
+          C12 = -f * k.t1 * k.t2;
+          C13 = -f * k.t1 * k.t3;
+          C23 = -f * k.t2 * k.t3;
+        }
+        const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
+        const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
+        const double dr = c.dt * c.cdo;
+        double Mxx = rh + dr * wn, Myy = Mxx, Mxy = 0.0;
+        if (wn > 0.0) {
+          Mxx += dr * wx_ * wx_ / wn;
+          Myy += dr * wy_ * wy_ / wn;
+          Mxy = dr * wx_ * wy_ / wn;
+        }
+        // X = B_a^T C (2x3), B_a columns: dof x (c1 gx, c2 gx, s2e gy), dof y (c2 gy, c1 gy, s2e gx)
+        const double gxa = s.gx[a], gya = s.gy[a];
+        const double bx0 = c.c1 * gxa, bx1 = c.c2 * gxa, bx2 = c.s2e * gya;
+        const double by0 = c.c2 * gya, by1 = c.c1 * gya, by2 = c.s2e * gxa;
+        const double X00 = bx0 * C11 + bx1 * C12 + bx2 * C13;
+        const double X01 = bx0 * C12 + bx1 * C22 + bx2 * C23;
+        const double X02 = bx0 * C13 + bx1 * C23 + bx2 * C33;
+        const double X10 = by0 * C11 + by1 * C12 + by2 * C13;
+        const double X11 = by0 * C12 + by1 * C22 + by2 * C23;
+        const double X12 = by0 * C13 + by1 * C23 + by2 * C33;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int ox = (b & 1) - ax, oy = (b >> 1) - ay;
+          int dir;
+          if (ox == 0 && oy == 0) dir = 0;
+          else if (ox == 1 && oy == 0) dir = 1;
+          else if (ox == 0 && oy == 1) dir = 2;
+          else if (ox == 1 && oy == 1) dir = 3;
+          else if (ox == -1 && oy == 1) dir = 4;
+          else continue;
+          const double gxb = s.gx[b], gyb = s.gy[b];
+          const double cx0 = c.c1 * gxb, cx1 = c.c2 * gxb, cx2 = c.s2e * gyb;
+          const double cy0 = c.c2 * gyb, cy1 = c.c1 * gyb, cy2 = c.s2e * gxb;
+          const double nn_ = s.N[a] * s.N[b];
+          blk[dir][0] += c.wq * (X00 * cx0 + X01 * cx1 + X02 * cx2 + nn_ * Mxx);
+          blk[dir][1] += c.wq * (X00 * cy0 + X01 * cy1 + X02 * cy2 + nn_ * Mxy);
+          blk[dir][2] += c.wq * (X10 * cx0 + X11 * cx1 + X12 * cx2 + nn_ * Mxy);
+          blk[dir][3] += c.wq * (X10 * cy0 + X11 * cy1 + X12 * cy2 + nn_ * Myy);
+        }
+      }
+    }
+  // Dirichlet rows and columns: identity at boundary nodes, no coupling to them.
+  const bool bn = is_boundary(c, i, j);
+  const int nbi[5] = {i, i + 1, i, i + 1, i - 1};
+  const int nbj[5] = {j, j, j + 1, j + 1, j + 1};
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    bool zero;
+    if (b == 0) zero = bn;
+    else zero = bn || nbi[b] < 0 || nbi[b] > c.nx || nbj[b] > c.ny || is_boundary(c, nbi[b], nbj[b]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double val = zero ? 0.0 : blk[b][k];
+      if (b == 0 && bn) val = (k == 0 || k == 3) ? 1.0 : 0.0;
+      K[(size_t)(b * 4 + k) * nn + n] = val;
+    }
+  }
+}
+
+void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, double* K) {
+  hipLaunchKernelGGL(k_assemble, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec, v, pi,
+                     variant, c->vo, c->P, c->rhoH, K);
+  VP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// dual update (eq. tautilde with eq. modification) and consistent initialisation (eq. pi)
+// ---------------------------------------------------------------------------
+//   pi~ = -p + a/D + t~/D - [(a.t~) p + (p.t~) a] / (D^2 s)   (Mandel vectors)
+__global__ void k_pi_update(ElemConst c, const double* __restrict__ v, const double* __restrict__ dv,
+                            double* __restrict__ pi, double alpha) {
+  const size_t ncell = (size_t)c.nx * c.ny;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncell) return;
+  const int ci = (int)(e % c.nx), cj = (int)(e / c.nx);
+  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  CellVel V, D;
+  load_cell(c, v, nullptr, 0.0, ci, cj, V);
+  load_cell(c, dv, nullptr, 0.0, ci, cj, D);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const Shape s = shape_at(q, ihx, ihy);
+    const Kin k = kinematics(c, s, V);
+    const Kin kd = kinematics(c, s, D);
+    double* pq = pi + (size_t)(q * 3) * ncell + e;
+    const double p1 = pq[0], p2 = pq[ncell], p3 = kSqrt2 * pq[2 * ncell];
+    const double sn = fmax(1.0, sqrt(2.0 * (p1 * p1 + p2 * p2 + p3 * p3)));
+    const double id = 1.0 / k.delta;
+    const double at = k.t1 * kd.t1 + k.t2 * kd.t2 + k.t3 * kd.t3;
+    const double pt = p1 * kd.t1 + p2 * kd.t2 + p3 * kd.t3;
+    const double g = id * id / sn;
+    const double d1 = -p1 + (k.t1 + kd.t1) * id - g * (at * p1 + pt * k.t1);
+    const double d2 = -p2 + (k.t2 + kd.t2) * id - g * (at * p2 + pt * k.t2);
+    const double d3 = -p3 + (k.t3 + kd.t3) * id - g * (at * p3 + pt * k.t3);
+    pq[0] = p1 + alpha * d1;
+    pq[ncell] = p2 + alpha * d2;
+    pq[2 * ncell] = (p3 + alpha * d3) / kSqrt2;
+  }
+}
+
+__global__ void k_pi_init(ElemConst c, const double* __restrict__ v, double* __restrict__ pi) {
+  const size_t ncell = (size_t)c.nx * c.ny;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncell) return;
+  const int ci = (int)(e % c.nx), cj = (int)(e / c.nx);
+  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  CellVel V;
+  load_cell(c, v, nullptr, 0.0, ci, cj, V);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const Shape s = shape_at(q, ihx, ihy);
+    const Kin k = kinematics(c, s, V);
+    const double id = 1.0 / k.delta;
+    double* pq = pi + (size_t)(q * 3) * ncell + e;
+    pq[0] = k.t1 * id;
+    pq[ncell] = k.t2 * id;
+    pq[2 * ncell] = k.t3 * id / kSqrt2;
+  }
+}
+
+void launch_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha) {
+  hipLaunchKernelGGL(k_pi_update, dim3((unsigned)((c->ncell + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, c->stream, c->ec, v, dv, pi, alpha);
+  VP_LAUNCH_CHECK();
+}
+
+void launch_pi_init(vp_ctx c, const double* v, double* pi) {
+  hipLaunchKernelGGL(k_pi_init, dim3((unsigned)((c->ncell + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     c->stream, c->ec, v, pi);
+  VP_LAUNCH_CHECK();
+}
+
+}  // namespace vp

@@ -1,0 +1,229 @@
+// Internal declarations shared by the libvp translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <type_traits>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/vp.h"
+
+namespace vp {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define VP_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::vp::Error(e_ == hipErrorOutOfMemory ? VP_ENOMEM : VP_EHIP,          \
+                        std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define VP_LAUNCH_CHECK() VP_HIP(hipGetLastError())
+
+constexpr int kBlock = 256;     // threads per workgroup for node/vector kernels
+constexpr int kRedBlocks = 512; // workgroups of a grid-stride reduction
+constexpr int kMaxLevels = 16;
+constexpr int kMaxRestart = 64;
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum K values over the workgroup (blockDim.x a multiple of 64, <= 1024); the
+// result is valid in thread 0.  Fixed order => deterministic.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* lds /* >= 16*K */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[wid * K + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += lds[w * K + k];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Remap the linear workgroup id so that each of the 8 XCDs (which receive
+// workgroups round-robin) processes one contiguous eighth of the index range;
+// neighbouring rows of a structured grid then share that XCD's L2.
+// Requires gridDim.x % 8 == 0 (launchers round the grid up).
+__device__ __forceinline__ unsigned xcd_block() {
+  const unsigned b = blockIdx.x, g = gridDim.x;
+  return (b & 7u) * (g >> 3) + (b >> 3);
+}
+
+inline unsigned grid_for(size_t n, int block = kBlock) {
+  size_t g = (n + block - 1) / block;
+  g = (g + 7) / 8 * 8;
+  if (g == 0) g = 8;
+  return (unsigned)g;
+}
+
+// bf16 storage helpers (round to nearest even)
+__device__ __forceinline__ float ld(const float* p) { return *p; }
+__device__ __forceinline__ double ld(const double* p) { return *p; }
+__device__ __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+
+// ---------------------------------------------------------------------------
+// element constants (uniform structured mesh, 2x2 Gauss)
+// ---------------------------------------------------------------------------
+struct ElemConst {
+  int nx, ny, nxn, nyn;
+  double hx, hy, wq;             // wq = hx*hy/4, the weight of each Gauss point
+  double dt, dmin2;              // dt, Delta_min^2
+  double c1, c2, s2e;            // tau map: c1 = (1+1/e)/2, c2 = (1-1/e)/2, s2e = 1/(sqrt2 e)
+  double rho_ice, cdo, cda, fc;  // rho_ice, C_o rho_o, C_a rho_a, f_c
+  double P_star, C_strength;
+};
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Level {
+  int nxn = 0, nyn = 0, B = 2;   // node grid and dofs per node
+  size_t nn = 0;                 // nodes
+  // operator: 5*B*B planes of nn values (self, E, N, NE, NW blocks)
+  double* A64 = nullptr;
+  float* A32 = nullptr;
+  __hip_bfloat16* Abf = nullptr; // Jacobi-scaled values (mixed+bf16 mode, levels >= 1)
+  float* dsc = nullptr;          // D^{1/2} scaling per dof (bf16 mode)
+  bool own_A64 = true;
+  // transfer to the next level (aggregation of 3x3 nodes)
+  int ncx = 0, ncy = 0;
+  double* Ptent = nullptr;       // [B*3][nn]  own-aggregate tentative block per node
+  double* P64 = nullptr;         // [4 slots][B*3][nn] smoothed prolongator
+  float* P32 = nullptr;
+  double* Bnull = nullptr;       // near-null space at this level [B*3][nn] (levels >= 1)
+  double* lmax = nullptr;        // device scalar: bound on lmax(D^-1 A)
+  double* pv0 = nullptr;         // power-iteration vectors (FP64, B*nn), warm across setups
+  double* pv1 = nullptr;
+  double* pnrm = nullptr;        // device [2]: squared norms of the power iterates
+  double lmax_h = 0.0;
+  // V-cycle vectors, B*nn each, in the V-cycle precision
+  void* x = nullptr; void* b = nullptr; void* r = nullptr; void* d0 = nullptr; void* d1 = nullptr;
+  // coarsest level: dense inverse (row-major, ndof x ndof)
+  double* Ainv64 = nullptr;
+  float* Ainv32 = nullptr;
+};
+
+}  // namespace vp
+
+struct vp_ctx_s {
+  vp_problem_desc desc{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  vp::ElemConst ec{};
+  size_t nn = 0, ncell = 0, ndof = 0;
+  std::string err;
+  // state
+  double* P = nullptr;      // [ncell]
+  double* rhoH = nullptr;   // [ncell]
+  double* F = nullptr;      // [ndof]
+  double* vo = nullptr;     // [ndof]
+  bool have_state = false;
+  double rnorm_zero = -1.0;
+  // operator
+  bool have_K = false;
+  // AMG
+  int nlev = 0;
+  vp::Level lev[vp::kMaxLevels];
+  bool amg_ready = false;
+  bool amg_struct = false;
+  int amg_prec = 0;
+  int cheb_degree = 3;
+  double cheb_ratio = 30.0;
+  int max_coarse = 300;
+  int power_its_cold = 12, power_its_warm = 4;
+  double power_factor = 1.1;
+  // scratch
+  double* partials = nullptr;      // [kRedBlocks * 64]
+  double* dscal = nullptr;         // device scalars [256]
+  double* hscal = nullptr;         // pinned host scalars [256]
+  double* work = nullptr;          // [6*ndof] Newton/line-search temporaries
+  double* kv = nullptr;            // Krylov bases [(2*restart+1 + 4) * ndof]
+  int kv_restart = 0;
+  double* dense = nullptr;         // coarse dense matrix scratch
+  // Newton history (Eisenstat-Walker state)
+  double ew_rn_prev = -1.0, ew_eta_prev = 0.1;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+namespace vp {
+void launch_precompute(vp_ctx c, const double* H, const double* A, const double* va,
+                       const double* vo, const double* vprev);
+// residual/energy at v + alpha*dv (dv may be null); writes r (nullable) and
+// 3 partial sums per workgroup: |R|^2, Phi, sum|Phi terms|
+void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, double* r,
+                     double* partials, unsigned* nblocks);
+void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, double* K);
+void launch_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
+void launch_pi_init(vp_ctx c, const double* v, double* pi);
+
+// reductions / BLAS-1 (vector length n doubles)
+void launch_finish_sum(hipStream_t s, const double* partials, int nblocks, int K, double* out);
+void launch_dot(hipStream_t s, const double* x, const double* y, size_t n, double* partials);
+void launch_mdot(hipStream_t s, const double* V, size_t ld, int nv, const double* w, size_t n,
+                 double* partials);
+void launch_maxpy_mdot(hipStream_t s, const double* V, size_t ld, int nv, const double* h,
+                       double* w, size_t n, double* partials);
+void launch_maxpy_scale(hipStream_t s, const double* V, size_t ld, int nv, const double* h,
+                        const double* w, const double* nrm2, double* out, size_t n);
+void launch_gemv_add(hipStream_t s, const double* Z, size_t ld, int nz, const double* y,
+                     double* x, size_t n);
+void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, size_t n);
+void launch_scale_copy(hipStream_t s, const double* x, const double* scal, int invert,
+                       double* y, size_t n);
+void launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, const double* p,
+                       const double* q, size_t n, double* partials);
+void launch_fcg_dir(hipStream_t s, double* dev, const double* z, double* p, size_t n, int first);
+void launch_cast(hipStream_t s, const double* x, float* y, size_t n);
+void launch_cast(hipStream_t s, const float* x, double* y, size_t n);
+void launch_fill(hipStream_t s, double* x, double v, size_t n);
+
+// structured stencil operators (AMG levels)
+template <typename TM, typename TV>
+void launch_stencil_residual(hipStream_t s, const Level& L, const TM* A, const TV* x, const TV* b,
+                             TV* r);
+void launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials);
+}  // namespace vp

@@ -167,14 +167,20 @@ class Workload:
 
 def synthetic(n: int, seed: int, h_range=(0.1, 2.0), a_range=(0.7, 1.0),
               wind_max: float = 15.0, delta_min: float = 2e-9, t: float = 0.0,
-              name: str = "synthetic", f_coriolis: float = 1.46e-4) -> Workload:
-    desc = ProblemDesc(nx=n, ny=n, delta_min=delta_min, f_coriolis=f_coriolis)
-    H = smooth_field(seed, n, n, desc.Lx, desc.Ly, *h_range)
-    A = smooth_field(seed + 1000, n, n, desc.Lx, desc.Ly, *a_range)
+              name: str = "synthetic", f_coriolis: float = 1.46e-4, ny: int | None = None,
+              Ly: float | None = None) -> Workload:
+    """Seeded workload on an n x ny mesh (ny defaults to n) of a 512 km x Ly domain."""
+    nx = n
+    ny = n if ny is None else ny
+    desc = ProblemDesc(nx=nx, ny=ny, delta_min=delta_min, f_coriolis=f_coriolis)
+    if Ly is not None:
+        desc = desc.replace(Ly=Ly)
+    H = smooth_field(seed, nx, ny, desc.Lx, desc.Ly, *h_range)
+    A = smooth_field(seed + 1000, nx, ny, desc.Lx, desc.Ly, *a_range)
     vs = make_vortices(seed + 2000, desc.Lx, desc.Ly)
-    va = vortex_wind(vs, n, n, desc.Lx, desc.Ly, wind_max, t)
-    vo = ocean_gyre(n, n, desc.Lx, desc.Ly, 0.1)
-    vp = np.zeros((n + 1, n + 1, 2))
+    va = vortex_wind(vs, nx, ny, desc.Lx, desc.Ly, wind_max, t)
+    vo = ocean_gyre(nx, ny, desc.Lx, desc.Ly, 0.1)
+    vp = np.zeros((ny + 1, nx + 1, 2))
     return Workload(name, desc, H, A, va, vo, vp, vs, wind_max)
 
 

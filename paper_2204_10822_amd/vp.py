@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libvp (C ABI in include/vp.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Functions keep the C names; arrays are torch CUDA float64 tensors whose shapes
+and placement are checked here before any kernel is launched.  If the library
+is missing the import fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libvp.so")
+
+VP_OK, VP_NOT_CONVERGED, VP_LINESEARCH_FAIL, VP_KRYLOV_MAXIT = 0, 1, 2, 3
+VP_EINVAL, VP_EHIP, VP_ENOMEM, VP_ESTATE, VP_ENONFINITE, VP_EBREAKDOWN = -1, -2, -3, -4, -5, -6
+VP_SVN, VP_STDN = 0, 1
+VP_PREC_FP64, VP_PREC_FP32, VP_PREC_FP32_BF16COARSE = 0, 1, 2
+VP_KRYLOV_FGMRES, VP_KRYLOV_FCG = 0, 1
+VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
+
+EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_residual",
+            "vp_newton_assemble", "vp_operator_apply", "vp_operator_export", "vp_amg_setup",
+            "vp_amg_apply", "vp_amg_info", "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
+            "vp_newton_step", "vp_newton_solve", "vp_default_opts"]
+
+
+class vp_problem_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("Lx", C.c_double), ("Ly", C.c_double),
+                ("rho_ice", C.c_double), ("rho_air", C.c_double), ("rho_ocean", C.c_double),
+                ("C_air", C.c_double), ("C_ocean", C.c_double), ("P_star", C.c_double),
+                ("C_strength", C.c_double), ("e_ratio", C.c_double), ("f_coriolis", C.c_double),
+                ("dt", C.c_double), ("delta_min", C.c_double)]
+
+
+class vp_amg_opts(C.Structure):
+    _fields_ = [("cheb_degree", C.c_int), ("max_coarse", C.c_int), ("precision", C.c_int),
+                ("cheb_ratio", C.c_double), ("omega_scale", C.c_double)]
+
+
+class vp_krylov_opts(C.Structure):
+    _fields_ = [("method", C.c_int), ("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double)]
+
+
+class vp_krylov_info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("rel_resid", C.c_double)]
+
+
+class vp_newton_opts(C.Structure):
+    _fields_ = [("variant", C.c_int), ("tol", C.c_double), ("eta_max", C.c_double),
+                ("max_backtracks", C.c_int), ("ls_mode", C.c_int)]
+
+
+class vp_newton_info(C.Structure):
+    _fields_ = [("rnorm", C.c_double), ("rnorm0", C.c_double), ("rnorm_new", C.c_double),
+                ("energy", C.c_double), ("energy_new", C.c_double), ("alpha", C.c_double),
+                ("eta", C.c_double), ("backtracks", C.c_int), ("krylov_iters", C.c_int)]
+
+
+class vp_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("krylov_iters", C.c_int), ("rnorm0", C.c_double),
+                ("rel_resid", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libvp.so not built at {_LIB_PATH}; run __graft_entry__.build()")
+    lib = C.CDLL(_LIB_PATH)
+    P, D, I = C.c_void_p, C.c_double, C.c_int
+    sig = {
+        "vp_create": (I, [C.POINTER(vp_problem_desc), P, C.POINTER(P)]),
+        "vp_destroy": (None, [P]),
+        "vp_last_error": (C.c_char_p, [P]),
+        "vp_set_state": (I, [P, P, P, P, P, P]),
+        "vp_residual": (I, [P, P, P, C.POINTER(D), C.POINTER(D)]),
+        "vp_newton_assemble": (I, [P, P, P, I]),
+        "vp_operator_apply": (I, [P, P, P]),
+        "vp_operator_export": (I, [P, P]),
+        "vp_amg_setup": (I, [P, C.POINTER(vp_amg_opts)]),
+        "vp_amg_apply": (I, [P, P, P]),
+        "vp_amg_info": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+        "vp_krylov_solve": (I, [P, P, P, C.POINTER(vp_krylov_opts), C.POINTER(vp_krylov_info)]),
+        "vp_pi_update": (I, [P, P, P, P, D]),
+        "vp_pi_init": (I, [P, P, P]),
+        "vp_newton_step": (I, [P, P, P, C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
+                               C.POINTER(vp_krylov_opts), C.POINTER(vp_newton_info)]),
+        "vp_newton_solve": (I, [P, P, P, I, C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
+                                C.POINTER(vp_krylov_opts), C.POINTER(vp_solve_info), P]),
+        "vp_default_opts": (None, [C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
+                                   C.POINTER(vp_krylov_opts)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+class VPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libvp error {code}: {msg}")
+        self.code = code
+
+
+def default_opts():
+    n, a, k = vp_newton_opts(), vp_amg_opts(), vp_krylov_opts()
+    LIB.vp_default_opts(C.byref(n), C.byref(a), C.byref(k))
+    return n, a, k
+
+
+def _ptr(t, shape, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name}: expected float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if t.numel() != int(torch.Size(shape).numel()):
+        raise ValueError(f"{name}: expected {tuple(shape)} elements, got shape {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def desc_from(d) -> vp_problem_desc:
+    return vp_problem_desc(d.nx, d.ny, d.Lx, d.Ly, d.rho_ice, d.rho_air, d.rho_ocean, d.C_air,
+                           d.C_ocean, d.P_star, d.C_strength, d.e_ratio, d.f_coriolis, d.dt,
+                           d.delta_min)
+
+
+class Context:
+    """One libvp context bound to the current torch stream of the current device."""
+
+    def __init__(self, desc, stream=None):
+        self.desc = desc
+        self.nx, self.ny = desc.nx, desc.ny
+        self.node_shape = ((desc.ny + 1) * (desc.nx + 1), 2)
+        self.cell_shape = (desc.ny, desc.nx)
+        self.pi_shape = (4, 3, desc.ny, desc.nx)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        self._d = desc_from(desc)
+        rc = LIB.vp_create(C.byref(self._d), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise VPError(rc, LIB.vp_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.vp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, soft_ok=True):
+        if rc < 0 or (rc > 0 and not soft_ok):
+            raise VPError(rc, LIB.vp_last_error(self.h).decode())
+        return rc
+
+    # --- the C ABI, one method per entry point --------------------------------------
+    def vp_set_state(self, H, A, v_air, v_ocean, v_prev):
+        return self._check(LIB.vp_set_state(
+            self.h, _ptr(H, self.cell_shape, "H"), _ptr(A, self.cell_shape, "A"),
+            _ptr(v_air, self.node_shape, "v_air"), _ptr(v_ocean, self.node_shape, "v_ocean"),
+            _ptr(v_prev, self.node_shape, "v_prev")))
+
+    def vp_residual(self, v, r=None, want_scalars=True):
+        rn, en = C.c_double(), C.c_double()
+        rc = LIB.vp_residual(self.h, _ptr(v, self.node_shape, "v"), _ptr(r, self.node_shape, "r"),
+                             C.byref(rn) if want_scalars else None,
+                             C.byref(en) if want_scalars else None)
+        self._check(rc)
+        return (rn.value, en.value) if want_scalars else None
+
+    def vp_newton_assemble(self, v, pi, variant=VP_SVN):
+        return self._check(LIB.vp_newton_assemble(
+            self.h, _ptr(v, self.node_shape, "v"),
+            _ptr(pi, self.pi_shape, "pi") if pi is not None else None, variant))
+
+    def vp_operator_apply(self, x, y):
+        return self._check(LIB.vp_operator_apply(self.h, _ptr(x, self.node_shape, "x"),
+                                                 _ptr(y, self.node_shape, "y")))
+
+    def vp_operator_export(self, blocks):
+        n = (self.nx + 1) * (self.ny + 1)
+        return self._check(LIB.vp_operator_export(self.h, _ptr(blocks, (20, n), "blocks")))
+
+    def vp_amg_setup(self, opts=None):
+        if opts is None:
+            opts = default_opts()[1]
+        return self._check(LIB.vp_amg_setup(self.h, C.byref(opts)))
+
+    def vp_amg_apply(self, r, z):
+        return self._check(LIB.vp_amg_apply(self.h, _ptr(r, self.node_shape, "r"),
+                                            _ptr(z, self.node_shape, "z")))
+
+    def vp_amg_info(self):
+        lv = C.c_int()
+        nx = (C.c_int * 16)()
+        ny = (C.c_int * 16)()
+        b = (C.c_int * 16)()
+        self._check(LIB.vp_amg_info(self.h, C.byref(lv), nx, ny, b))
+        return [(nx[i], ny[i], b[i]) for i in range(lv.value)]
+
+    def vp_krylov_solve(self, b, x, opts=None):
+        if opts is None:
+            opts = default_opts()[2]
+        info = vp_krylov_info()
+        rc = self._check(LIB.vp_krylov_solve(self.h, _ptr(b, self.node_shape, "b"),
+                                             _ptr(x, self.node_shape, "x"), C.byref(opts),
+                                             C.byref(info)))
+        return rc, info
+
+    def vp_pi_update(self, v, dv, pi, alpha):
+        return self._check(LIB.vp_pi_update(self.h, _ptr(v, self.node_shape, "v"),
+                                            _ptr(dv, self.node_shape, "dv"),
+                                            _ptr(pi, self.pi_shape, "pi"), float(alpha)))
+
+    def vp_pi_init(self, v, pi):
+        return self._check(LIB.vp_pi_init(self.h, _ptr(v, self.node_shape, "v"),
+                                          _ptr(pi, self.pi_shape, "pi")))
+
+    def vp_newton_step(self, v, pi, nopts=None, aopts=None, kopts=None):
+        dn, da, dk = default_opts()
+        info = vp_newton_info()
+        rc = self._check(LIB.vp_newton_step(
+            self.h, _ptr(v, self.node_shape, "v"),
+            _ptr(pi, self.pi_shape, "pi") if pi is not None else None,
+            C.byref(nopts or dn), C.byref(aopts or da), C.byref(kopts or dk), C.byref(info)))
+        return rc, info
+
+    def vp_newton_solve(self, v, pi, maxit=200, nopts=None, aopts=None, kopts=None, history=True):
+        dn, da, dk = default_opts()
+        info = vp_solve_info()
+        hist = (C.c_double * (maxit + 1))() if history else None
+        rc = self._check(LIB.vp_newton_solve(
+            self.h, _ptr(v, self.node_shape, "v"),
+            _ptr(pi, self.pi_shape, "pi") if pi is not None else None, int(maxit),
+            C.byref(nopts or dn), C.byref(aopts or da), C.byref(kopts or dk), C.byref(info),
+            hist))
+        h = list(hist[: info.iterations + 1]) if history else None
+        return rc, info, h
+
+
+def to_device(arr, device="cuda"):
+    return torch.as_tensor(arr, dtype=torch.float64).contiguous().to(device)
+
+
+def context_for(workload, device="cuda"):
+    """Create a context for a seeded workload and upload its state."""
+    ctx = Context(workload.desc)
+    f = workload.fields()
+    ts = {k: to_device(v.reshape(-1, 2) if v.ndim == 3 else v, device) for k, v in f.items()}
+    ctx.vp_set_state(ts["H"], ts["A"], ts["v_air"], ts["v_ocean"], ts["v_prev"])
+    ctx._state = ts
+    return ctx

@@ -1,0 +1,220 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+FP64 kernels must agree with the oracle to 1e-12 in the normwise relative sense;
+the Newton solve must reach the oracle's velocity to 1e-6 relative l2 at a
+nonlinear residual of 1e-8 relative to ||R(0)||.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import vp_oracle as O
+from paper_2204_10822_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_10822_amd import vp as _vp
+    return _vp
+
+
+def _case(vp, nx, ny, seed, **kw):
+    w = inputs.synthetic(nx, seed, ny=ny, Ly=512e3 * ny / nx, **kw)
+    rng = np.random.default_rng(seed)
+    w.v_prev = 0.05 * rng.standard_normal(w.v_prev.shape)
+    print(f"[case] nx={nx} ny={ny} seed={seed}", flush=True)
+    prob = O.problem_from_workload(w)
+    ctx = vp.context_for(w)
+    return w, prob, ctx
+
+
+def _rand_v(prob, seed, scale=0.1):
+    rng = np.random.default_rng(seed)
+    v = scale * rng.standard_normal(2 * prob.mesh.nnode)
+    v[~prob.mesh.free_dof] = 0.0
+    return v
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _relerr(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def export_matrix(vp, ctx, nx, ny):
+    """Build a scipy CSR matrix from the 5-block symmetric stencil storage."""
+    nxn, nyn = nx + 1, ny + 1
+    nn = nxn * nyn
+    blocks = torch.zeros(20, nn, dtype=torch.float64, device="cuda")
+    ctx.vp_operator_export(blocks)
+    B = _host(blocks).reshape(5, 2, 2, nn)
+    jj, ii = np.divmod(np.arange(nn), nxn)
+    offs = [(0, 0), (1, 0), (0, 1), (1, 1), (-1, 1)]
+    rows, cols, vals = [], [], []
+    for b, (di, dj) in enumerate(offs):
+        ok = (ii + di >= 0) & (ii + di < nxn) & (jj + dj < nyn)
+        n = np.nonzero(ok)[0]
+        m = (jj[n] + dj) * nxn + ii[n] + di
+        for r in range(2):
+            for c in range(2):
+                rows.append(2 * n + r); cols.append(2 * m + c); vals.append(B[b, r, c, n])
+                if b > 0:
+                    rows.append(2 * m + c); cols.append(2 * n + r); vals.append(B[b, r, c, n])
+    K = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(2 * nn, 2 * nn)).tocsr()
+    K.sum_duplicates()
+    return K
+
+
+SHAPES = [(8, 6, 1), (23, 17, 2), (64, 64, 3), (100, 37, 4)]
+
+
+@pytest.mark.parametrize("nx,ny,seed", SHAPES)
+def test_residual_energy_parity(vp, nx, ny, seed):
+    w, prob, ctx = _case(vp, nx, ny, seed)
+    for k, v in enumerate([np.zeros(2 * prob.mesh.nnode), _rand_v(prob, 10 + seed)]):
+        r = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+        rn, en = ctx.vp_residual(_dev(v.reshape(-1, 2)), r)
+        R = prob.residual(v)
+        e, eabs = prob.energy(v)
+        assert _relerr(_host(r), R) < 1e-12
+        assert abs(rn - np.linalg.norm(R)) <= 1e-12 * np.linalg.norm(R)
+        assert abs(en - e) <= 1e-12 * eabs
+
+
+@pytest.mark.parametrize("nx,ny,seed", SHAPES)
+@pytest.mark.parametrize("variant", ["svn", "std"])
+def test_operator_parity(vp, nx, ny, seed, variant):
+    w, prob, ctx = _case(vp, nx, ny, seed)
+    v = _rand_v(prob, 20 + seed)
+    rng = np.random.default_rng(seed)
+    pi = 0.8 * rng.standard_normal((4, 3, ny, nx))       # includes |pi| > 1/sqrt2
+    vt = _dev(v.reshape(-1, 2))
+    ctx.vp_newton_assemble(vt, _dev(pi), vp.VP_SVN if variant == "svn" else vp.VP_STDN)
+    Kg = export_matrix(vp, ctx, nx, ny)
+    Ko = prob.jacobian_svn(v, pi) if variant == "svn" else prob.jacobian_std(v)
+    assert spla.norm(Kg - Ko) <= 1e-12 * spla.norm(Ko)
+    # operator apply (FP64 stencil SpMV)
+    x = rng.standard_normal(2 * prob.mesh.nnode)
+    y = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+    ctx.vp_operator_apply(_dev(x.reshape(-1, 2)), y)
+    assert _relerr(_host(y), Ko @ x) < 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,seed", SHAPES[:3])
+def test_pi_update_and_init_parity(vp, nx, ny, seed):
+    w, prob, ctx = _case(vp, nx, ny, seed)
+    v = _rand_v(prob, 30 + seed)
+    dv = _rand_v(prob, 31 + seed, 0.02)
+    rng = np.random.default_rng(seed)
+    pi = 0.8 * rng.standard_normal((4, 3, ny, nx))
+    pt = _dev(pi)
+    ctx.vp_pi_update(_dev(v.reshape(-1, 2)), _dev(dv.reshape(-1, 2)), pt, 0.37)
+    ref = pi + 0.37 * prob.pi_step(v, dv, pi)
+    assert _relerr(_host(pt), ref) < 1e-12
+    ctx.vp_pi_init(_dev(v.reshape(-1, 2)), pt)
+    assert _relerr(_host(pt), prob.pi_consistent(v)) < 1e-12
+
+
+@pytest.mark.parametrize("method", ["fgmres", "fcg"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_krylov_solves_assembled_system(vp, method, prec):
+    nx, ny, seed = 64, 48, 5
+    w, prob, ctx = _case(vp, nx, ny, seed)
+    v = O.newton_solve(prob, maxit=2).v
+    pi = prob.pi_consistent(v)
+    ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(pi), vp.VP_SVN)
+    n, a, k = vp.default_opts()
+    a.precision = prec
+    ctx.vp_amg_setup(a)
+    b = -prob.residual(v)
+    x = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+    k.method = vp.VP_KRYLOV_FGMRES if method == "fgmres" else vp.VP_KRYLOV_FCG
+    k.rtol, k.maxit = 1e-10, 400
+    rc, info = ctx.vp_krylov_solve(_dev(b.reshape(-1, 2)), x, k)
+    print(f"[krylov] {method} prec={prec} its={info.iters} rel={info.rel_resid:.2e}", flush=True)
+    assert rc == 0
+    K = prob.jacobian_svn(v, pi)
+    xd = spla.spsolve(K.tocsc(), b)
+    assert _relerr(_host(x), xd) < 1e-6
+    assert info.iters < 120
+
+
+def test_vcycle_is_symmetric_fp64(vp):
+    """With pre- and post-smoothing by the same Chebyshev polynomial and an exact
+    coarse solve the FP64 V-cycle is a symmetric operator."""
+    nx, ny, seed = 40, 33, 6
+    w, prob, ctx = _case(vp, nx, ny, seed)
+    v = _rand_v(prob, 40)
+    ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
+    ctx.vp_amg_setup()
+    rng = np.random.default_rng(7)
+    x, y = rng.standard_normal((2, 2 * prob.mesh.nnode))
+    x[~prob.mesh.free_dof] = 0.0
+    y[~prob.mesh.free_dof] = 0.0
+    zx = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+    zy = torch.zeros_like(zx)
+    ctx.vp_amg_apply(_dev(x.reshape(-1, 2)), zx)
+    ctx.vp_amg_apply(_dev(y.reshape(-1, 2)), zy)
+    a, b = y @ _host(zx).ravel(), x @ _host(zy).ravel()
+    assert abs(a - b) <= 1e-10 * max(abs(a), abs(b))
+    assert a > 0
+
+
+def test_determinism_bitwise(vp):
+    """Two contexts on the same inputs give bitwise-equal residuals, energies and
+    V-cycle outputs: reductions use fixed orders and no floating-point atomics."""
+    nx, ny, seed = 64, 64, 8
+    outs = []
+    for _ in range(2):
+        w, prob, ctx = _case(vp, nx, ny, seed)
+        v = _rand_v(prob, 41)
+        vt = _dev(v.reshape(-1, 2))
+        r = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+        rn, en = ctx.vp_residual(vt, r)
+        ctx.vp_newton_assemble(vt, _dev(prob.pi_consistent(v)), vp.VP_SVN)
+        ctx.vp_amg_setup()
+        z = torch.zeros_like(r)
+        ctx.vp_amg_apply(r, z)
+        outs.append((_host(r).copy(), rn, en, _host(z).copy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1] and outs[0][2] == outs[1][2]
+    assert np.array_equal(outs[0][3], outs[1][3])
+
+
+@pytest.mark.parametrize("nx,ny,seed,variant", [(32, 32, 1, "svn"), (64, 64, 1, "svn"), (48, 40, 2, "std")])
+def test_newton_solve_parity(vp, nx, ny, seed, variant):
+    if (nx, ny, seed) == (64, 64, 1):
+        w = inputs.small_step(64)
+        prob = O.problem_from_workload(w)
+        ctx = vp.context_for(w)
+    else:
+        w, prob, ctx = _case(vp, nx, ny, seed)
+    ref = O.newton_solve(prob, variant=variant, tol=1e-8, maxit=200)
+    assert ref.converged
+    v = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(4, 3, ny, nx, dtype=torch.float64, device="cuda")
+    n, a, k = vp.default_opts()
+    n.variant = vp.VP_SVN if variant == "svn" else vp.VP_STDN
+    rc, info, hist = ctx.vp_newton_solve(v, pi, 200, n, a, k)
+    print(f"[newton] {nx}x{ny} {variant}: gpu its={info.iterations} krylov={info.krylov_iters} "
+          f"rel={info.rel_resid:.2e}; oracle its={ref.iterations}", flush=True)
+    assert rc == 0
+    assert info.rel_resid <= 1e-8
+    assert _relerr(_host(v).ravel(), ref.v) < 1e-6
+    if variant == "svn":
+        assert abs(info.iterations - ref.iterations) <= 4
+        assert _relerr(_host(pi), prob.pi_consistent(ref.v)) < 1e-4
