@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Time to a 1e-8 relative nonlinear residual for one implicit VP momentum step.
+
+One "step" is a whole stress-velocity Newton solve (residual, assembly, AMG
+setup, AMG-preconditioned Krylov, energy backtracking, dual update; Sec. 4.2,
+5.1, 5.4) from v = 0, pi = 0 on the 2048 x 2048 Q1 workload (8,396,802
+unknowns; wind to 25 m/s, H in [0.05, 1.5] m, Delta_min = 2e-10).  Inputs are
+resident in HBM before the timed region.  The plain FP64 path and the mixed
+path (FP32 V-cycle and preconditioner SpMV, FP64 residual, tau/Delta,
+orthogonalisation and update) are both timed; `value` is the faster one.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 residual, 2048^2 mesh: plain FP64 vs mixed+learned; SpMV GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_sample: int, gpu_newton_its: int, n_full: int):
+    """The CPU oracle on a bounded sample: a full Newton solve of the same recipe
+    on an n_sample^2 mesh, one thread; scaled to the full mesh by unknowns and by
+    the ratio of Newton iterations."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import vp_oracle as O
+    from paper_2204_10822_amd import inputs
+
+    w = inputs.sharp_step(n_sample)
+    prob = O.problem_from_workload(w)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        res = O.newton_solve(prob, tol=1e-8, maxit=200)
+        t = time.perf_counter() - t0
+    dofs_s, dofs_f = 2 * (n_sample + 1) ** 2, 2 * (n_full + 1) ** 2
+    scaled = t * (dofs_f / dofs_s) * (gpu_newton_its / max(res.iterations, 1))
+    return dict(value=scaled, unit="s", cores=1, kind="oracle",
+                sample=(f"oracle Newton solve (direct inner solves) of the same recipe on a "
+                        f"{n_sample}x{n_sample} mesh: {t:.2f} s, {res.iterations} Newton its, "
+                        f"converged={res.converged}; scaled by unknowns x{dofs_f / dofs_s:.0f} and "
+                        f"by Newton its {gpu_newton_its}/{res.iterations}"),
+                sample_seconds=t)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--paths", default="fp64,fp32", help="comma list of fp64, fp32")
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the domain-decomposition design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2204_10822_amd import inputs, vp
+
+    torch.cuda.set_device(0)
+    n = args.n
+    t0 = time.time()
+    w = inputs.sharp_step(n)
+    ctx = vp.context_for(w)
+    log(f"workload {w.name}: {2 * (n + 1) ** 2} unknowns, inputs ready in {time.time() - t0:.1f}s")
+    nn = (n + 1) ** 2
+    v = torch.zeros(nn, 2, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(4, 3, n, n, dtype=torch.float64, device="cuda")
+
+    def opts(path):
+        no, ao, ko = vp.default_opts()
+        ao.precision = vp.VP_PREC_FP64 if path == "fp64" else vp.VP_PREC_FP32
+        return no, ao, ko
+
+    def solve(path):
+        v.zero_()
+        pi.zero_()
+        no, ao, ko = opts(path)
+        rc, info, _ = ctx.vp_newton_solve(v, pi, 200, no, ao, ko, history=False)
+        return rc, info
+
+    results = {}
+    for path in [p for p in args.paths.split(",") if p]:
+        for k in range(args.warmup):
+            rc, info = solve(path)
+            log(f"{path} warmup {k}: rc={rc} newton={info.iterations} krylov={info.krylov_iters} "
+                f"rel={info.rel_resid:.2e}")
+        torch.cuda.synchronize()
+        ctx.vp_profile(1)
+        times, infos = [], []
+        torch.cuda.synchronize()
+        tstart = time.perf_counter()
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            rc, info = solve(path)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+            infos.append(info)
+            if rc != 0 or info.rel_resid > 1e-8:
+                raise SystemExit(f"{path} solve failed: rc={rc} rel={info.rel_resid:.2e}")
+            log(f"{path} step {k}: {times[-1]:.3f}s newton={info.iterations} "
+                f"krylov={info.krylov_iters} rel={info.rel_resid:.2e}")
+        torch.cuda.synchronize()
+        total = time.perf_counter() - tstart
+        ctx.vp_profile(0)
+        kern = {}
+        for name, kid in vp.VP_KID.items():
+            ms, cnt, b = ctx.vp_profile_read(kid)
+            if cnt:
+                kern[name] = dict(total_ms=ms, launches=cnt, avg_us=1e3 * ms / cnt,
+                                  bytes_per_launch=b,
+                                  gbs=(b / (ms / cnt * 1e-3) / 1e9) if b > 0 and ms > 0 else None)
+        results[path] = dict(total=total, times=times, median=statistics.median(times),
+                             newton=[i.iterations for i in infos],
+                             krylov=[i.krylov_iters for i in infos], kernels=kern)
+
+    best = min(results, key=lambda p: results[p]["median"])
+    R = results[best]
+    # dominant single kernel (by summed time) of the headline path
+    single = {k: d for k, d in R["kernels"].items() if k != "vcycle" and d["bytes_per_launch"] > 0}
+    dom = max(single, key=lambda k: single[k]["total_ms"])
+    D = single[dom]
+    roof = dict(kernel=dom, bound="hbm", achieved=D["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=D["gbs"] / HBM_PEAK_GBS, traffic=None,
+                bytes_per_launch=D["bytes_per_launch"], avg_us=D["avg_us"])
+    spmv = R["kernels"].get("apply_fine")
+    out = {
+        "metric": METRIC,
+        "value": R["median"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * R["total"] / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if best == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "mesh": f"{n}x{n} Q1", "unknowns": 2 * nn,
+                   "tol": 1e-8, "path": best, "newton_its": R["newton"], "krylov_its": R["krylov"]},
+        "paths": {p: dict(median_s=d["median"], times_s=d["times"], newton_its=d["newton"],
+                          krylov_its=d["krylov"]) for p, d in results.items()},
+        "spmv_gbs": spmv["gbs"] if spmv else None,
+        "kernels": R["kernels"],
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log(f"cpu baseline: oracle on a {args.cpu_sample}^2 sample")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, R["newton"][0], n)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,6 +179,24 @@ int vp_newton_solve(vp_ctx ctx, double* v, double* pi, int maxit,
                     const vp_newton_opts* nopts, const vp_amg_opts* aopts,
                     const vp_krylov_opts* kopts, vp_solve_info* info, double* history);
 
+/* Per-kernel timing with HIP events recorded on the context's stream around the
+ * launches of selected kernels (finest level only).  vp_profile(ctx, 1) clears
+ * and starts recording, vp_profile(ctx, 0) stops.  vp_profile_read synchronises
+ * and returns, for kernel id kid, the summed duration [ms], the launch count and
+ * the algorithmic bytes one launch must move (each stored value read once, each
+ * vector read or written once).  VP_EINVAL for an unknown kid. */
+enum {
+  VP_KID_APPLY_FINE = 0,   /* y = K x, FP64, the Krylov operator product            */
+  VP_KID_CHEB_STEP0 = 1,   /* Chebyshev step on the finest level (fused SpMV)       */
+  VP_KID_STEN_RESID0 = 2,  /* r = b - A x on the finest level                        */
+  VP_KID_RESIDUAL = 3,     /* nonlinear residual + energy                            */
+  VP_KID_ASSEMBLE = 4,     /* operator assembly                                      */
+  VP_KID_VCYCLE = 5,       /* one whole V-cycle (composite, not a single kernel)     */
+  VP_KID_COUNT = 6
+};
+int vp_profile(vp_ctx ctx, int enable);
+int vp_profile_read(vp_ctx ctx, int kid, double* total_ms, int* launches, double* bytes_per_launch);
+
 /* Default option sets. */
 void vp_default_opts(vp_newton_opts* n, vp_amg_opts* a, vp_krylov_opts* k);
 

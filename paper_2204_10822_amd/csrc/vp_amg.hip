@@ -69,11 +69,25 @@ __device__ __forceinline__ void load_block(const TM* __restrict__ A, size_t nn, 
   }
 }
 
+// Inverse of a B x B block.  The block is first scaled by its largest entry:
+// operator entries reach ~1e17 and the cofactor products (~1e51 for B = 3) would
+// overflow FP32 otherwise.
 template <int B, typename TA>
-__device__ __forceinline__ void invert_block(const TA (&D)[B][B], TA (&Di)[B][B]) {
+__device__ __forceinline__ void invert_block(const TA (&Din)[B][B], TA (&Di)[B][B]) {
+  TA m = TA(0);
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int c = 0; c < B; ++c) m = fmax(m, fabs(Din[r][c]));
+  const TA is = m > TA(0) ? TA(1) / m : TA(1);
+  TA D[B][B];
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int c = 0; c < B; ++c) D[r][c] = Din[r][c] * is;
   if constexpr (B == 2) {
     const TA det = D[0][0] * D[1][1] - D[0][1] * D[1][0];
-    const TA id = det != TA(0) ? TA(1) / det : TA(0);
+    const TA id = det != TA(0) ? is / det : TA(0);
     Di[0][0] = D[1][1] * id; Di[0][1] = -D[0][1] * id;
     Di[1][0] = -D[1][0] * id; Di[1][1] = D[0][0] * id;
   } else {
@@ -81,7 +95,7 @@ __device__ __forceinline__ void invert_block(const TA (&D)[B][B], TA (&Di)[B][B]
     const TA c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
     const TA c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
     const TA det = D[0][0] * c00 + D[0][1] * c01 + D[0][2] * c02;
-    const TA id = det != TA(0) ? TA(1) / det : TA(0);
+    const TA id = det != TA(0) ? is / det : TA(0);
     Di[0][0] = c00 * id;
     Di[1][0] = c01 * id;
     Di[2][0] = c02 * id;
@@ -922,15 +936,18 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
 namespace {
 
 template <int B, typename TM, typename TV>
-void sten_resid(hipStream_t s, const Level& L, const TM* A, const TV* x, const TV* b, TV* r) {
-  hipLaunchKernelGGL((k_sten_resid<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A, L.nn, L.nxn,
-                     L.nyn, x, b, r);
+void sten_resid(vp_ctx c, int l, const Level& L, const TM* A, const TV* x, const TV* b, TV* r) {
+  const int pr = l == 0 ? prof_begin(c, VP_KID_STEN_RESID0) : -1;
+  hipLaunchKernelGGL((k_sten_resid<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn,
+                     L.nxn, L.nyn, x, b, r);
   VP_LAUNCH_CHECK();
+  prof_end(c, pr);
 }
 
 template <int B, typename TM, typename TV>
-void smooth(hipStream_t s, const Level& L, const TM* A, const TV* src, TV* x, bool zero_start,
+void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* src, TV* x, bool zero_start,
             int degree, double ratio) {
+  hipStream_t s = c->stream;
   using TA = typename Acc<TV>::type;
   TV* r = (TV*)L.r;
   TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
@@ -944,13 +961,15 @@ void smooth(hipStream_t s, const Level& L, const TM* A, const TV* src, TV* x, bo
   for (int k = 1; k < degree; ++k) {
     const double rn = 1.0 / (2.0 * sigma - rho);
     const double cdd = rn * rho, cdr = 2.0 * rn / delta;
+    const int pr = l == 0 ? prof_begin(c, VP_KID_CHEB_STEP0) : -1;
     hipLaunchKernelGGL((k_cheb_step<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A, L.nn, L.nxn,
                        L.nyn, d[(k - 1) & 1], r, d[k & 1], x, (TA)cdd, (TA)cdr);
     VP_LAUNCH_CHECK();
+    prof_end(c, pr);
     rho = rn;
   }
   // leave r = b - A x after pre-smoothing (used by the restriction)
-  if (zero_start) sten_resid<B>(s, L, A, (const TV*)d[(degree - 1) & 1], (const TV*)r, r);
+  if (zero_start) sten_resid<B>(c, l, L, A, (const TV*)d[(degree - 1) & 1], (const TV*)r, r);
 }
 
 template <typename TV>
@@ -973,7 +992,7 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     using TM = decltype(tm_tag);
     const TM* A = fp64 ? (const TM*)L.A64 : (const TM*)L.A32;
     const TM* P = fp64 ? (const TM*)L.P64 : (const TM*)L.P32;
-    smooth<B, TM, TV>(s, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
+    smooth<B, TM, TV>(c, l, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
     hipLaunchKernelGGL((k_restrict<B, TM, TV>), dim3((unsigned)((N.nn + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, P, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)L.r, (TV*)N.b);
     VP_LAUNCH_CHECK();
@@ -981,8 +1000,8 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     hipLaunchKernelGGL((k_prolong_add<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
                        L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
     VP_LAUNCH_CHECK();
-    sten_resid<B>(s, L, A, (const TV*)x, b, (TV*)L.r);
-    smooth<B, TM, TV>(s, L, A, (const TV*)L.r, x, false, c->cheb_degree, c->cheb_ratio);
+    sten_resid<B>(c, l, L, A, (const TV*)x, b, (TV*)L.r);
+    smooth<B, TM, TV>(c, l, L, A, (const TV*)L.r, x, false, c->cheb_degree, c->cheb_ratio);
   };
   using TMT = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
   if (L.B == 2) run(std::integral_constant<int, 2>(), TMT());
@@ -996,6 +1015,13 @@ void amg_apply(vp_ctx c, const double* r, double* z) {
   if (!c->amg_ready) throw Error(VP_ESTATE, "AMG not set up");
   Level& L = c->lev[0];
   const size_t n = (size_t)L.B * L.nn;
+  struct End {
+    vp_ctx c;
+    int idx;
+    ~End() {
+      try { prof_end(c, idx); } catch (...) {}
+    }
+  } end_{c, prof_begin(c, VP_KID_VCYCLE)};
   if (c->amg_prec == VP_PREC_FP64) {
     vcycle_level<double>(c, 0, r, z);
   } else {

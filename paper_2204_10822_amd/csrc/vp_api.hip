@@ -68,7 +68,9 @@ struct ResidOut {
 
 ResidOut residual_eval(vp_ctx c, const double* v, const double* dv, double alpha, double* r) {
   unsigned g = 0;
+  const int pr = prof_begin(c, VP_KID_RESIDUAL);
   launch_residual(c, v, dv, alpha, r, c->partials, &g);
+  prof_end(c, pr);
   finish(c, (int)g, 3, 0);
   fetch(c, 0, 3);
   ResidOut o{std::sqrt(std::max(c->hscal[0], 0.0)), c->hscal[1], c->hscal[2]};
@@ -137,7 +139,9 @@ int fgmres(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_kry
       double* vj = V + (size_t)j * n;
       double* zj = Z + (size_t)j * n;
       amg_apply(c, vj, zj);
+      const int pr = prof_begin(c, VP_KID_APPLY_FINE);
       launch_apply_fine(s, c->lev[0], zj, w, nullptr);
+      prof_end(c, pr);
       const int nv = j + 1;
       // pass 1: h1 = V^T w
       launch_mdot(s, V, n, nv, w, n, c->partials);
@@ -234,7 +238,9 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
     finish(c, kRedBlocks, 1, 0);
     launch_fcg_dir(s, c->dscal, z, p, n, 1);
     while (it < o.maxit) {
+      const int pr = prof_begin(c, VP_KID_APPLY_FINE);
       launch_apply_fine(s, c->lev[0], p, q, c->partials);  // q = K p, p.q
+      prof_end(c, pr);
       finish(c, (int)grid_for(c->lev[0].nn), 1, 1);
       launch_fcg_update(s, c->dscal, x, r, p, q, n, c->partials);
       finish(c, kRedBlocks, 1, 4);
@@ -313,7 +319,9 @@ int newton_step(vp_ctx c, double* v, double* pi, const vp_newton_opts& no, const
   double* Rt = c->work + 3 * n;
   const double r0 = rnorm_zero(c);
   ResidOut o = rcache && cur ? *cur : residual_eval(c, v, nullptr, 0.0, R);
+  const int pr = prof_begin(c, VP_KID_ASSEMBLE);
   launch_assemble(c, v, pi, no.variant, c->lev[0].A64);
+  prof_end(c, pr);
   c->have_K = true;
   amg_setup(c, ao);
   const double eta = ew_eta(c, o.rnorm, no.tol * r0, no.eta_max);
@@ -431,6 +439,7 @@ void vp_destroy(vp_ctx c) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->hscal) (void)hipHostFree(c->hscal);
+  for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -547,6 +556,47 @@ int vp_pi_init(vp_ctx c, const double* v, double* pi) {
   return guarded(c, [&] {
     require(c != nullptr && v && pi, VP_EINVAL, "null argument");
     launch_pi_init(c, v, pi);
+    return VP_OK;
+  });
+}
+
+int vp_profile(vp_ctx c, int enable) {
+  return guarded(c, [&] {
+    require(c != nullptr, VP_EINVAL, "null context");
+    if (enable) c->prof.used = 0;
+    c->prof.on = enable != 0;
+    return VP_OK;
+  });
+}
+
+int vp_profile_read(vp_ctx c, int kid, double* total_ms, int* launches, double* bytes) {
+  return guarded(c, [&] {
+    require(c != nullptr, VP_EINVAL, "null context");
+    require(kid >= 0 && kid < VP_KID_COUNT, VP_EINVAL, "unknown kernel id");
+    VP_HIP(hipStreamSynchronize(c->stream));
+    double ms = 0.0;
+    int cnt = 0;
+    for (size_t k = 0; k < c->prof.used; ++k) {
+      if (c->prof.kid[k] != kid) continue;
+      float t = 0.0f;
+      VP_HIP(hipEventElapsedTime(&t, c->prof.ev[2 * k], c->prof.ev[2 * k + 1]));
+      ms += t;
+      ++cnt;
+    }
+    const double nn = (double)c->nn, nc = (double)c->ncell;
+    const bool f32 = c->amg_prec != VP_PREC_FP64;
+    double b = 0.0;
+    switch (kid) {
+      case VP_KID_APPLY_FINE: b = nn * (20 * 8 + 2 * 16); break;
+      case VP_KID_CHEB_STEP0: b = f32 ? nn * (20 * 4 + 6 * 8) : nn * (20 * 8 + 6 * 16); break;
+      case VP_KID_STEN_RESID0: b = f32 ? nn * (20 * 4 + 3 * 8) : nn * (20 * 8 + 3 * 16); break;
+      case VP_KID_RESIDUAL: b = nn * 64 + nc * 16; break;
+      case VP_KID_ASSEMBLE: b = nn * (32 + 160) + nc * (16 + 96); break;
+      default: b = 0.0;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = cnt;
+    if (bytes) *bytes = b;
     return VP_OK;
   });
 }

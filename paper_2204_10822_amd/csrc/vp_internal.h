@@ -147,7 +147,18 @@ struct Level {
 
 }  // namespace vp
 
+namespace vp {
+// HIP-event timing of selected launches (see vp_profile)
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;   // pool, two events per record
+  std::vector<int> kid;         // kernel id per record
+  size_t used = 0;
+};
+}  // namespace vp
+
 struct vp_ctx_s {
+  vp::Prof prof;
   vp_problem_desc desc{};
   hipStream_t stream = nullptr;
   int device = 0;
@@ -172,8 +183,8 @@ struct vp_ctx_s {
   int cheb_degree = 3;
   double cheb_ratio = 30.0;
   int max_coarse = 300;
-  int power_its_cold = 12, power_its_warm = 4;
-  double power_factor = 1.1;
+  int power_its_cold = 16, power_its_warm = 6;
+  double power_factor = 1.15;
   // scratch
   double* partials = nullptr;      // [kRedBlocks * 64]
   double* dscal = nullptr;         // device scalars [256]
@@ -190,6 +201,26 @@ struct vp_ctx_s {
 // launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 namespace vp {
+// Bracket a launch (or a nested group of launches) with events when profiling is
+// on.  prof_begin returns the record index for prof_end (-1 when off).
+inline int prof_begin(vp_ctx c, int kid) {
+  Prof& p = c->prof;
+  if (!p.on) return -1;
+  const size_t idx = p.used++;
+  while (p.ev.size() < 2 * p.used) {
+    hipEvent_t e;
+    VP_HIP(hipEventCreate(&e));
+    p.ev.push_back(e);
+  }
+  if (p.kid.size() < p.used) p.kid.resize(p.used);
+  p.kid[idx] = kid;
+  VP_HIP(hipEventRecord(p.ev[2 * idx], c->stream));
+  return (int)idx;
+}
+inline void prof_end(vp_ctx c, int idx) {
+  if (idx < 0) return;
+  VP_HIP(hipEventRecord(c->prof.ev[2 * (size_t)idx + 1], c->stream));
+}
 void launch_precompute(vp_ctx c, const double* H, const double* A, const double* va,
                        const double* vo, const double* vprev);
 // residual/energy at v + alpha*dv (dv may be null); writes r (nullable) and

@@ -25,7 +25,9 @@ VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_residual",
             "vp_newton_assemble", "vp_operator_apply", "vp_operator_export", "vp_amg_setup",
             "vp_amg_apply", "vp_amg_info", "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
-            "vp_newton_step", "vp_newton_solve", "vp_default_opts"]
+            "vp_newton_step", "vp_newton_solve", "vp_default_opts", "vp_profile",
+            "vp_profile_read"]
+VP_KID = dict(apply_fine=0, cheb_step0=1, sten_resid0=2, residual=3, assemble=4, vcycle=5)
 
 
 class vp_problem_desc(C.Structure):
@@ -89,6 +91,8 @@ def _load():
                                C.POINTER(vp_krylov_opts), C.POINTER(vp_newton_info)]),
         "vp_newton_solve": (I, [P, P, P, I, C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
                                 C.POINTER(vp_krylov_opts), C.POINTER(vp_solve_info), P]),
+        "vp_profile": (I, [P, I]),
+        "vp_profile_read": (I, [P, I, C.POINTER(D), C.POINTER(I), C.POINTER(D)]),
         "vp_default_opts": (None, [C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
                                    C.POINTER(vp_krylov_opts)]),
     }
@@ -240,6 +244,14 @@ class Context:
             _ptr(pi, self.pi_shape, "pi") if pi is not None else None,
             C.byref(nopts or dn), C.byref(aopts or da), C.byref(kopts or dk), C.byref(info)))
         return rc, info
+
+    def vp_profile(self, enable):
+        return self._check(LIB.vp_profile(self.h, int(bool(enable))))
+
+    def vp_profile_read(self, kid):
+        ms, n, b = C.c_double(), C.c_int(), C.c_double()
+        self._check(LIB.vp_profile_read(self.h, int(kid), C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, n.value, b.value
 
     def vp_newton_solve(self, v, pi, maxit=200, nopts=None, aopts=None, kopts=None, history=True):
         dn, da, dk = default_opts()

@@ -218,3 +218,26 @@ def test_newton_solve_parity(vp, nx, ny, seed, variant):
     if variant == "svn":
         assert abs(info.iterations - ref.iterations) <= 4
         assert _relerr(_host(pi), prob.pi_consistent(ref.v)) < 1e-4
+
+
+def test_vcycle_fp32_close_to_fp64(vp):
+    """The FP32 V-cycle applies the same operator as the FP64 one up to FP32
+    rounding.  Fresh contexts give both the same spectral estimates."""
+    nx, ny, seed = 64, 48, 5
+    outs = {}
+    for prec in (0, 1):
+        w, prob, ctx = _case(vp, nx, ny, seed)
+        v = O.newton_solve(prob, maxit=2).v
+        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
+        rng = np.random.default_rng(9)
+        r = rng.standard_normal(2 * prob.mesh.nnode)
+        r[~prob.mesh.free_dof] = 0.0
+        n, a, k = vp.default_opts()
+        a.precision = prec
+        ctx.vp_amg_setup(a)
+        z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+        ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
+        outs[prec] = _host(z).ravel()
+    d32 = _relerr(outs[1], outs[0])
+    print(f"[vcycle] fp32 vs fp64 {d32:.2e}", flush=True)
+    assert d32 < 1e-4
