@@ -56,6 +56,33 @@ def cpu_baseline(n_sample: int, gpu_newton_its: int, n_full: int):
                 sample_seconds=t)
 
 
+def kernel_sequence(args, ctx, v, pi, torch, vp):
+    """Short fixed launch sequence for profiler passes: three Newton steps (to get
+    a non-trivial operator), then per path 10 V-cycles and 10 FP64 operator
+    products, and a 1 GiB device copy whose counters calibrate the byte counters."""
+    no, ao, ko = vp.default_opts()
+    for k in range(3):
+        rc, info = ctx.vp_newton_step(v, pi, no, ao, ko)
+        log(f"newton step {k}: rc={rc} rel={info.rnorm_new / info.rnorm0:.2e}")
+    r = torch.randn_like(v)
+    z = torch.zeros_like(v)
+    for path in [p for p in args.paths.split(",") if p]:
+        ao.precision = vp.VP_PREC_FP64 if path == "fp64" else vp.VP_PREC_FP32
+        ctx.vp_amg_setup(ao)
+        for _ in range(10):
+            ctx.vp_amg_apply(r, z)
+        for _ in range(10):
+            ctx.vp_operator_apply(r, z)
+        torch.cuda.synchronize()
+        log(f"{path}: 10 V-cycles and 10 operator products done")
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration copy of 1 GiB done")
+    print(json.dumps({"mode": "kernels", "paths": args.paths, "n": args.n}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +92,8 @@ def main():
     ap.add_argument("--paths", default="fp64,fp32", help="comma list of fp64, fp32")
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels"],
+                    help="kernels: a short fixed sequence (for profiler counter passes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -84,6 +113,9 @@ def main():
     nn = (n + 1) ** 2
     v = torch.zeros(nn, 2, dtype=torch.float64, device="cuda")
     pi = torch.zeros(4, 3, n, n, dtype=torch.float64, device="cuda")
+
+    if args.mode == "kernels":
+        return kernel_sequence(args, ctx, v, pi, torch, vp)
 
     def opts(path):
         no, ao, ko = vp.default_opts()

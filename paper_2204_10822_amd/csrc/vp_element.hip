@@ -263,7 +263,11 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
 #pragma unroll
     for (int k = 0; k < 4; ++k) blk[b][k] = 0.0;
 
+  // the cell loops are unrolled so that every block index below is a
+  // compile-time constant and the accumulators stay in registers
+#pragma unroll
   for (int dyc = 0; dyc < 2; ++dyc)
+#pragma unroll
     for (int dxc = 0; dxc < 2; ++dxc) {
       const int ci = i - 1 + dxc, cj = j - 1 + dyc;
       if (ci < 0 || cj < 0 || ci >= c.nx || cj >= c.ny) continue;

@@ -1,0 +1,56 @@
+"""Reduce rocprofv3 CSV output to short text summaries.
+
+    python -m paper_2204_10822_amd.profsum stats  <kernel_stats.csv>  [top]
+    python -m paper_2204_10822_amd.profsum counter <counter_collection.csv> <COUNTER>
+
+`stats` prints the top kernels by summed duration.  `counter` prints, per kernel
+name, the dispatch count and the mean value of one counter per dispatch (for
+FETCH_SIZE / WRITE_SIZE this is KiB per dispatch), plus the values seen for the
+device copy kernels used as a calibration of known size.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import re
+import sys
+
+
+def _short(name: str) -> str:
+    name = re.sub(r"\(.*$", "", name)           # drop the argument list
+    name = name.replace("void ", "").replace("vp::", "")
+    return name
+
+
+def stats(path: str, top: int = 25) -> None:
+    rows = list(csv.DictReader(open(path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print(f"{'kernel':58s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}")
+    for r in rows[:top]:
+        t = float(r["TotalDurationNs"])
+        print(f"{_short(r['Name'])[:58]:58s} {int(r['Calls']):7d} {t / 1e6:10.3f} "
+              f"{float(r['AverageNs']) / 1e3:10.2f} {100 * t / tot:6.2f}")
+    print(f"total kernel time {tot / 1e6:.3f} ms over {sum(int(r['Calls']) for r in rows)} dispatches")
+
+
+def counter(path: str, cname: str) -> None:
+    acc = collections.defaultdict(list)
+    grids = {}
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != cname:
+            continue
+        k = _short(r["Kernel_Name"])
+        acc[k].append(float(r["Counter_Value"]))
+        grids[k] = r.get("Grid_Size", "")
+    print(f"{cname}: mean per dispatch (KiB for FETCH_SIZE/WRITE_SIZE)")
+    print(f"{'kernel':58s} {'n':>5s} {'mean':>14s} {'grid':>10s}")
+    for k, v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+        print(f"{k[:58]:58s} {len(v):5d} {sum(v) / len(v):14.1f} {grids[k]:>10s}")
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25)
+    else:
+        counter(sys.argv[2], sys.argv[3])
