@@ -23,6 +23,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}   # V-cycle precision modes of vp_amg_opts
 METRIC = "time-to-1e-8 residual, 2048^2 mesh: plain FP64 vs mixed+learned; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
 
@@ -67,7 +68,7 @@ def kernel_sequence(args, ctx, v, pi, torch, vp):
     r = torch.randn_like(v)
     z = torch.zeros_like(v)
     for path in [p for p in args.paths.split(",") if p]:
-        ao.precision = vp.VP_PREC_FP64 if path == "fp64" else vp.VP_PREC_FP32
+        ao.precision = PREC[path]
         ctx.vp_amg_setup(ao)
         for _ in range(10):
             ctx.vp_amg_apply(r, z)
@@ -89,7 +90,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--paths", default="fp64,fp32", help="comma list of fp64, fp32")
+    ap.add_argument("--paths", default="fp64,fp32,bf16", help="comma list of fp64, fp32, bf16")
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels"],
@@ -119,7 +120,7 @@ def main():
 
     def opts(path):
         no, ao, ko = vp.default_opts()
-        ao.precision = vp.VP_PREC_FP64 if path == "fp64" else vp.VP_PREC_FP32
+        ao.precision = PREC[path]
         return no, ao, ko
 
     def solve(path):
@@ -185,7 +186,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if best == "fp64" else "f64+f32",
+        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+f32+bf16"}[best],
         "data": "synthetic",
         "config": {"workload": w.name, "mesh": f"{n}x{n} Q1", "unknowns": 2 * nn,
                    "tol": 1e-8, "path": best, "newton_its": R["newton"], "krylov_its": R["krylov"]},

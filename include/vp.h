@@ -168,7 +168,9 @@ int vp_newton_step(vp_ctx ctx, double* v, double* pi, const vp_newton_opts* nopt
                    vp_newton_info* info);
 
 /* Newton loop (Sec. 5.1 stopping rule with a relative target): iterate
- * vp_newton_step until ||R(v)|| <= tol ||R(0)|| or maxit iterations.  Returns
+ * vp_newton_step until ||R(v)|| <= tol ||R(0)|| or maxit iterations.  The AMG
+ * spectral estimates restart from a fixed vector, so the result depends only on
+ * the inputs (kernels are deterministic).  Returns
  * VP_OK, VP_NOT_CONVERGED or VP_LINESEARCH_FAIL.  history (host, nullable,
  * maxit+1 entries) receives ||R||/||R(0)|| per iterate. */
 typedef struct {

@@ -642,6 +642,70 @@ k_galerkin(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
   }
 }
 
+// ---- BF16 coarse storage: Jacobi-scaled operators --------------------------
+// dsc = sqrt(diag(A)) per dof (point diagonal of the self block)
+template <int B>
+__global__ void k_diag_sqrt(const double* __restrict__ A, size_t nn, double* __restrict__ dsc) {
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  for (int r = 0; r < B; ++r) {
+    const double d = A[(size_t)(r * B + r) * nn + n];
+    dsc[n * B + r] = d > 0.0 ? sqrt(d) : 1.0;
+  }
+}
+
+// S = D^{-1/2} A D^{-1/2} stored in BF16 (same 5-block layout)
+template <int B>
+__global__ void k_scale_to_bf16(const double* __restrict__ A, size_t nn, int nxn, int nyn,
+                                const double* __restrict__ dsc, __hip_bfloat16* __restrict__ S) {
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  for (int blk = 0; blk < 5; ++blk) {
+    const int ii = i + kDI[blk], jj = j + kDJ[blk];
+    const bool ok = ii >= 0 && jj >= 0 && ii < nxn && jj < nyn;
+    const size_t m = ok ? (size_t)jj * nxn + ii : n;
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < B; ++c) {
+        const size_t k = (size_t)(blk * B * B + r * B + c) * nn + n;
+        const double v = ok ? A[k] / (dsc[n * B + r] * dsc[m * B + c]) : 0.0;
+        S[k] = __float2bfloat16((float)v);
+      }
+  }
+}
+
+// P^ = diag(dsc_f) P diag(1/dsc_c) in FP32 (dsc_f = null: no row scaling, finest level)
+template <int B>
+__global__ void k_scale_p(const double* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
+                          const double* __restrict__ dsc_f, const double* __restrict__ dsc_c,
+                          float* __restrict__ Ps) {
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  const int ax[2] = {agg_of(i, ncx), agg_other(i, nxn, ncx)};
+  const int ay[2] = {agg_of(j, ncy), agg_other(j, nyn, ncy)};
+  for (int s = 0; s < 4; ++s) {
+    const int Jx = ax[s & 1], Jy = ay[s >> 1];
+    const bool ok = Jx >= 0 && Jy >= 0;
+    const size_t J = ok ? (size_t)Jy * ncx + Jx : 0;
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const size_t k = ((size_t)(s * B + r) * 3 + c) * nn + n;
+        const double fr = dsc_f ? dsc_f[n * B + r] : 1.0;
+        Ps[k] = ok ? (float)(fr * P[k] / dsc_c[J * 3 + c]) : 0.0f;
+      }
+  }
+}
+
+// (D^{1/2} A^{-1} D^{1/2}) of the coarsest level in FP32 (inverse of the scaled operator)
+__global__ void k_scale_dense(const double* __restrict__ M, int nd, const double* __restrict__ dsc,
+                              float* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)nd * nd) return;
+  const int r = (int)(e / nd), c = (int)(e % nd);
+  out[e] = (float)(dsc[r] * M[e] * dsc[c]);
+}
+
 // Dense matrix (row-major nd x nd, nd = B*nn) of a stencil level.  Zero-filled by caller.
 template <int B>
 __global__ void k_to_dense(const double* __restrict__ A, size_t nn, int nxn, int nyn, double* __restrict__ M) {
@@ -751,6 +815,8 @@ void amg_free(vp_ctx c) {
     dfree(L.pnrm);
     dfree(L.Ainv64);
     dfree(L.Ainv32);
+    dfree(L.Abf);
+    dfree(L.dsc64);
     free_vectors(L);
     L = Level();
   }
@@ -820,6 +886,58 @@ void alloc_vectors(vp_ctx c) {
 
 }  // namespace
 
+// BF16-coarse mode: level 0 keeps an FP32 operator; every coarser level l stores
+// S_l = D_l^{-1/2} A_l D_l^{-1/2} in BF16 and the V-cycle works there in the
+// scaled variables, with prolongators P^_l = D_l^{1/2} P_l D_{l+1}^{-1/2} (FP32;
+// D_0 = I) and the coarsest inverse D^{1/2} A^{-1} D^{1/2} (FP32).
+void bf16_copies(vp_ctx c, hipStream_t s) {
+  for (int l = 0; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    const size_t na = (size_t)5 * L.B * L.B * L.nn;
+    const unsigned g = (unsigned)((L.nn + 255) / 256);
+    if (l == 0) {
+      if (!L.A32) L.A32 = dalloc<float>(na);
+      convert(s, L.A64, L.A32, na);
+    } else {
+      if (!L.dsc64) L.dsc64 = dalloc<double>((size_t)L.B * L.nn);
+      if (!L.Abf) L.Abf = dalloc<__hip_bfloat16>(na);
+      hipLaunchKernelGGL(k_diag_sqrt<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
+      VP_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_scale_to_bf16<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64, L.Abf);
+      VP_LAUNCH_CHECK();
+    }
+  }
+  for (int l = 0; l + 1 < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    Level& N = c->lev[l + 1];
+    const size_t np = (size_t)4 * L.B * 3 * L.nn;
+    if (!L.P32) L.P32 = dalloc<float>(np);
+    const unsigned g = (unsigned)((L.nn + 255) / 256);
+    if (L.B == 2)
+      hipLaunchKernelGGL(k_scale_p<2>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         (const double*)nullptr, (const double*)N.dsc64, L.P32);
+    else
+      hipLaunchKernelGGL(k_scale_p<3>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         (const double*)L.dsc64, (const double*)N.dsc64, L.P32);
+    VP_LAUNCH_CHECK();
+  }
+  Level& C = c->lev[c->nlev - 1];
+  const int nd = C.B * (int)C.nn;
+  if (!C.Ainv32) C.Ainv32 = dalloc<float>((size_t)nd * nd);
+  if (c->nlev == 1) {
+    convert(s, C.Ainv64, C.Ainv32, (size_t)nd * nd);
+  } else {
+    hipLaunchKernelGGL(k_scale_dense, dim3((unsigned)(((size_t)nd * nd + 255) / 256)), dim3(256), 0, s, C.Ainv64, nd,
+                       (const double*)C.dsc64, C.Ainv32);
+    VP_LAUNCH_CHECK();
+  }
+}
+
+// Restart the spectral estimates from the fixed start vector at the next setup.
+void amg_reset_estimates(vp_ctx c) {
+  for (int l = 0; l < kMaxLevels; ++l) c->lev[l].pv_warm = false;
+}
+
 // Numeric setup on the current finest operator.
 void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   if (!c->amg_struct) throw Error(VP_ESTATE, "AMG structure missing");
@@ -843,9 +961,12 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
         L.pv0 = dalloc<double>(nd);
         L.pv1 = dalloc<double>(nd);
         L.pnrm = dalloc<double>(2);
+      }
+      if (!L.pv_warm) {
         hipLaunchKernelGGL(k_power_init, dim3(1024), dim3(256), 0, s, L.pv0, nd);
         VP_LAUNCH_CHECK();
         its = c->power_its_cold;
+        L.pv_warm = true;
       }
       // |x|^2 of the start vector
       launch_dot(s, L.pv0, L.pv0, nd, c->partials);
@@ -896,7 +1017,9 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, C.Ainv64, nd);
   VP_LAUNCH_CHECK();
   // reduced-precision copies
-  if (precision != VP_PREC_FP64) {
+  if (precision == VP_PREC_FP32_BF16COARSE) {
+    bf16_copies(c, s);
+  } else if (precision != VP_PREC_FP64) {
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
       const size_t na = (size_t)5 * L.B * L.B * L.nn;
@@ -913,11 +1036,13 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       }
     }
   }
-  if (c->amg_prec != precision || c->lev[0].x == nullptr) {
-    if (precision == VP_PREC_FP64) alloc_vectors<double>(c);
+  const bool vec64 = precision == VP_PREC_FP64;
+  const bool have64 = c->amg_prec == VP_PREC_FP64;
+  if (c->lev[0].x == nullptr || vec64 != have64) {
+    if (vec64) alloc_vectors<double>(c);
     else alloc_vectors<float>(c);
-    c->amg_prec = precision;
   }
+  c->amg_prec = precision;
   // spectral bounds to the host (one synchronisation per setup)
   for (int l = 0; l < c->nlev; ++l)
     VP_HIP(hipMemcpyAsync(c->hscal + l, c->lev[l].lmax, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -987,25 +1112,32 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     return;
   }
   Level& N = c->lev[l + 1];
-  auto run = [&](auto bconst, auto tm_tag) {
+  auto run = [&](auto bconst, auto tm_tag, auto tp_tag, const void* Av, const void* Pv) {
     constexpr int B = decltype(bconst)::value;
     using TM = decltype(tm_tag);
-    const TM* A = fp64 ? (const TM*)L.A64 : (const TM*)L.A32;
-    const TM* P = fp64 ? (const TM*)L.P64 : (const TM*)L.P32;
+    using TP = decltype(tp_tag);
+    const TM* A = (const TM*)Av;
+    const TP* P = (const TP*)Pv;
     smooth<B, TM, TV>(c, l, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
-    hipLaunchKernelGGL((k_restrict<B, TM, TV>), dim3((unsigned)((N.nn + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((k_restrict<B, TP, TV>), dim3((unsigned)((N.nn + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, P, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)L.r, (TV*)N.b);
     VP_LAUNCH_CHECK();
     vcycle_level<TV>(c, l + 1, (const TV*)N.b, (TV*)N.x);
-    hipLaunchKernelGGL((k_prolong_add<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
+    hipLaunchKernelGGL((k_prolong_add<B, TP, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
                        L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
     VP_LAUNCH_CHECK();
     sten_resid<B>(c, l, L, A, (const TV*)x, b, (TV*)L.r);
     smooth<B, TM, TV>(c, l, L, A, (const TV*)L.r, x, false, c->cheb_degree, c->cheb_ratio);
   };
-  using TMT = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
-  if (L.B == 2) run(std::integral_constant<int, 2>(), TMT());
-  else run(std::integral_constant<int, 3>(), TMT());
+  if constexpr (std::is_same<TV, double>::value) {
+    if (L.B == 2) run(std::integral_constant<int, 2>(), double(), double(), L.A64, L.P64);
+    else run(std::integral_constant<int, 3>(), double(), double(), L.A64, L.P64);
+  } else {
+    const bool bf = c->amg_prec == VP_PREC_FP32_BF16COARSE && l > 0;
+    if (L.B == 2) run(std::integral_constant<int, 2>(), float(), float(), L.A32, L.P32);
+    else if (bf) run(std::integral_constant<int, 3>(), __hip_bfloat16(), float(), L.Abf, L.P32);
+    else run(std::integral_constant<int, 3>(), float(), float(), L.A32, L.P32);
+  }
 }
 
 }  // namespace

@@ -10,6 +10,7 @@ void amg_free(vp_ctx c);
 void amg_build_structure(vp_ctx c, double* K, int max_coarse);
 void amg_setup_numeric(vp_ctx c, int precision, double omega_scale);
 void amg_apply(vp_ctx c, const double* r, double* z);
+void amg_reset_estimates(vp_ctx c);
 }  // namespace vp
 
 using namespace vp;
@@ -618,6 +619,7 @@ int vp_newton_solve(vp_ctx c, double* v, double* pi, int maxit, const vp_newton_
     require(c->have_state, VP_ESTATE, "vp_set_state not called");
     c->ew_rn_prev = -1.0;
     c->ew_eta_prev = no->eta_max;
+    amg_reset_estimates(c);  // a solve is a function of its inputs only
     const double r0 = rnorm_zero(c);
     ResidOut cur = residual_eval(c, v, nullptr, 0.0, c->work);
     int it = 0, kits = 0, st = VP_NOT_CONVERGED;

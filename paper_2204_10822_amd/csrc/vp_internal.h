@@ -125,7 +125,7 @@ struct Level {
   double* A64 = nullptr;
   float* A32 = nullptr;
   __hip_bfloat16* Abf = nullptr; // Jacobi-scaled values (mixed+bf16 mode, levels >= 1)
-  float* dsc = nullptr;          // D^{1/2} scaling per dof (bf16 mode)
+  double* dsc64 = nullptr;       // sqrt(diag A) per dof (bf16 mode, levels >= 1)
   bool own_A64 = true;
   // transfer to the next level (aggregation of 3x3 nodes)
   int ncx = 0, ncy = 0;
@@ -137,6 +137,7 @@ struct Level {
   double* pv0 = nullptr;         // power-iteration vectors (FP64, B*nn), warm across setups
   double* pv1 = nullptr;
   double* pnrm = nullptr;        // device [2]: squared norms of the power iterates
+  bool pv_warm = false;          // pv0 holds the previous setup's iterate
   double lmax_h = 0.0;
   // V-cycle vectors, B*nn each, in the V-cycle precision
   void* x = nullptr; void* b = nullptr; void* r = nullptr; void* d0 = nullptr; void* d1 = nullptr;

@@ -131,7 +131,7 @@ def test_pi_update_and_init_parity(vp, nx, ny, seed):
 
 
 @pytest.mark.parametrize("method", ["fgmres", "fcg"])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_krylov_solves_assembled_system(vp, method, prec):
     nx, ny, seed = 64, 48, 5
     w, prob, ctx = _case(vp, nx, ny, seed)
@@ -220,12 +220,13 @@ def test_newton_solve_parity(vp, nx, ny, seed, variant):
         assert _relerr(_host(pi), prob.pi_consistent(ref.v)) < 1e-4
 
 
-def test_vcycle_fp32_close_to_fp64(vp):
+def test_vcycle_reduced_precision_close_to_fp64(vp):
     """The FP32 V-cycle applies the same operator as the FP64 one up to FP32
-    rounding.  Fresh contexts give both the same spectral estimates."""
+    rounding; with BF16 coarse operators (Jacobi-scaled) the difference is of the
+    order of BF16 rounding.  Fresh contexts give all the same spectral estimates."""
     nx, ny, seed = 64, 48, 5
     outs = {}
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         w, prob, ctx = _case(vp, nx, ny, seed)
         v = O.newton_solve(prob, maxit=2).v
         ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
@@ -239,5 +240,7 @@ def test_vcycle_fp32_close_to_fp64(vp):
         ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
         outs[prec] = _host(z).ravel()
     d32 = _relerr(outs[1], outs[0])
-    print(f"[vcycle] fp32 vs fp64 {d32:.2e}", flush=True)
+    dbf = _relerr(outs[2], outs[0])
+    print(f"[vcycle] fp32 vs fp64 {d32:.2e}  bf16-coarse vs fp64 {dbf:.2e}", flush=True)
     assert d32 < 1e-4
+    assert dbf < 5e-2
