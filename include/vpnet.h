@@ -1,0 +1,73 @@
+/*
+ * vpnet.h - C ABI of the learned warm start in libvp: a 4-level convolutional
+ * U-Net (channels 16/32/64/128, two 3x3 convolutions per level, 2x2 stride-2
+ * down-sampling, 2x2 stride-2 transposed-convolution up-sampling, skip
+ * concatenation, 1x1 output head) that maps 8 input channels (thickness,
+ * concentration, wind, ocean current, previous velocity) to 5 output channels
+ * (velocity and the dual stress pi of Sec. 4.2, eq. pi).  The network only
+ * proposes the starting point of the Newton iteration of vp.h; Newton finishes
+ * the solve and decides its accuracy.
+ *
+ * Arithmetic: BF16 activations and weights on the matrix cores (MFMA), FP32
+ * accumulation; FP32 master weights, output head, loss and Adam.
+ * Layouts: NHWC, input [B][H][W][8] FP32, output/target [B][H][W][5] FP32, all
+ * device pointers on the stream given to vpnet_create.  H and W multiples of 8.
+ * Return codes as in vp.h (0 OK, < 0 error; vpnet_last_error for text).
+ */
+#ifndef VPNET_H
+#define VPNET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vpnet_s* vpnet;
+
+/* Network for a fixed batch and spatial size.  VP_EINVAL if batch < 1 or H, W not
+ * positive multiples of 8. */
+int vpnet_create(int batch, int height, int width, void* hip_stream, vpnet* out);
+void vpnet_destroy(vpnet net);
+const char* vpnet_last_error(vpnet net);
+/* Number of parameters (flat FP32 vector: per layer weights then bias). */
+int64_t vpnet_param_count(vpnet net);
+/* Copy parameters in/out (device FP32, vpnet_param_count entries); set resets Adam. */
+int vpnet_set_params(vpnet net, const float* src);
+int vpnet_get_params(vpnet net, float* dst);
+/* Gradient of the last vpnet_backward (device FP32, flat like the parameters). */
+int vpnet_get_grads(vpnet net, float* dst);
+/* output = net(input). */
+int vpnet_forward(vpnet net, const float* input, float* output);
+/* Forward, mean-squared-error loss against target, backward (gradients kept in the
+ * net).  loss (host, nullable) receives the loss; synchronises when requested. */
+int vpnet_backward(vpnet net, const float* input, const float* target, float* loss);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) with learning rate lr on the last gradients. */
+int vpnet_adam(vpnet net, float lr);
+/* vpnet_backward followed by vpnet_adam. */
+int vpnet_train_step(vpnet net, const float* input, const float* target, float lr, float* loss);
+
+/* Solver <-> network glue (device arrays in the layouts of vp.h):
+ * features: the 8 normalised input channels on the (nx/f) x (ny/f) grid of f x f
+ *   cell blocks (node fields averaged to cells first): H/2, (A-0.85)/0.15,
+ *   v_air/25, v_ocean/0.1, v_prev/0.3.  f must divide nx and ny.
+ * targets:  training targets on the cell grid: cell mean of v / 0.3 and the mean
+ *   of pi over the cell's 4 Gauss points.
+ * guess:    v0 at the nodes (0 on the boundary) and pi0 at the Gauss points
+ *   (nullable) by bilinear sampling of a (wc x hc) cell-centred network output. */
+int vpnet_features(int nx, int ny, int f, const double* H, const double* A, const double* v_air,
+                   const double* v_ocean, const double* v_prev, float* out, void* hip_stream);
+int vpnet_targets(int nx, int ny, const double* v, const double* pi, float* out, void* hip_stream);
+int vpnet_guess(int nx, int ny, const float* net_out, int wc, int hc, double* v0, double* pi0,
+                void* hip_stream);
+
+/* The network's matrix-core GEMM, exposed for verification: C[M][N] (FP32) =
+ * op(A) op(B) with BF16 A ([M][K], or [K][M] if a_trans) and B ([K][N], or [N][K]
+ * if b_trans). */
+int vpnet_gemm(const void* A, const void* B, float* C, int M, int N, int K, int a_trans,
+               int b_trans, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VPNET_H */

@@ -27,6 +27,10 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_resi
             "vp_amg_apply", "vp_amg_info", "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
             "vp_newton_step", "vp_newton_solve", "vp_default_opts", "vp_profile",
             "vp_profile_read"]
+EXPORTED_NET = ["vpnet_create", "vpnet_destroy", "vpnet_last_error", "vpnet_param_count",
+                "vpnet_set_params", "vpnet_get_params", "vpnet_get_grads", "vpnet_forward",
+                "vpnet_backward", "vpnet_adam", "vpnet_train_step", "vpnet_features",
+                "vpnet_targets", "vpnet_guess", "vpnet_gemm"]
 VP_KID = dict(apply_fine=0, cheb_step0=1, sten_resid0=2, residual=3, assemble=4, vcycle=5)
 
 
@@ -95,6 +99,21 @@ def _load():
         "vp_profile_read": (I, [P, I, C.POINTER(D), C.POINTER(I), C.POINTER(D)]),
         "vp_default_opts": (None, [C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
                                    C.POINTER(vp_krylov_opts)]),
+        "vpnet_create": (I, [I, I, I, P, C.POINTER(P)]),
+        "vpnet_destroy": (None, [P]),
+        "vpnet_last_error": (C.c_char_p, [P]),
+        "vpnet_param_count": (C.c_int64, [P]),
+        "vpnet_set_params": (I, [P, P]),
+        "vpnet_get_params": (I, [P, P]),
+        "vpnet_get_grads": (I, [P, P]),
+        "vpnet_forward": (I, [P, P, P]),
+        "vpnet_backward": (I, [P, P, P, C.POINTER(C.c_float)]),
+        "vpnet_adam": (I, [P, C.c_float]),
+        "vpnet_train_step": (I, [P, P, P, C.c_float, C.POINTER(C.c_float)]),
+        "vpnet_features": (I, [I, I, I, P, P, P, P, P, P, P]),
+        "vpnet_targets": (I, [I, I, P, P, P, P]),
+        "vpnet_guess": (I, [I, I, P, I, I, P, P, P]),
+        "vpnet_gemm": (I, [P, P, P, I, I, I, I, I, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -278,3 +297,120 @@ def context_for(workload, device="cuda"):
     ctx.vp_set_state(ts["H"], ts["A"], ts["v_air"], ts["v_ocean"], ts["v_prev"])
     ctx._state = ts
     return ctx
+
+
+# ---------------------------------------------------------------------------
+# learned warm start (include/vpnet.h)
+# ---------------------------------------------------------------------------
+def _fptr(t, numel, name, dtype=torch.float32):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name}: expected a contiguous CUDA {dtype} tensor")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Net:
+    """One U-Net instance for a fixed batch and spatial size (NHWC tensors)."""
+
+    def __init__(self, batch, height, width):
+        self.B, self.H, self.W = batch, height, width
+        h = C.c_void_p()
+        rc = LIB.vpnet_create(batch, height, width, _stream(), C.byref(h))
+        if rc != 0:
+            raise VPError(rc, "vpnet_create failed (batch >= 1, H and W multiples of 8)")
+        self.h = h
+        self.nparam = int(LIB.vpnet_param_count(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.vpnet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise VPError(rc, LIB.vpnet_last_error(self.h).decode())
+        return rc
+
+    def vpnet_set_params(self, theta):
+        return self._check(LIB.vpnet_set_params(self.h, _fptr(theta, self.nparam, "theta")))
+
+    def vpnet_get_params(self, out):
+        return self._check(LIB.vpnet_get_params(self.h, _fptr(out, self.nparam, "out")))
+
+    def vpnet_get_grads(self, out):
+        return self._check(LIB.vpnet_get_grads(self.h, _fptr(out, self.nparam, "out")))
+
+    def vpnet_forward(self, x, out):
+        P = self.B * self.H * self.W
+        return self._check(LIB.vpnet_forward(self.h, _fptr(x, P * 8, "x"), _fptr(out, P * 5, "out")))
+
+    def vpnet_backward(self, x, target):
+        P = self.B * self.H * self.W
+        loss = C.c_float()
+        self._check(LIB.vpnet_backward(self.h, _fptr(x, P * 8, "x"), _fptr(target, P * 5, "target"),
+                                       C.byref(loss)))
+        return loss.value
+
+    def vpnet_adam(self, lr):
+        return self._check(LIB.vpnet_adam(self.h, C.c_float(lr)))
+
+    def vpnet_train_step(self, x, target, lr, want_loss=True):
+        P = self.B * self.H * self.W
+        loss = C.c_float()
+        self._check(LIB.vpnet_train_step(self.h, _fptr(x, P * 8, "x"), _fptr(target, P * 5, "target"),
+                                         C.c_float(lr), C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+
+def vpnet_features(nx, ny, f, H, A, v_air, v_ocean, v_prev, out):
+    nn = (nx + 1) * (ny + 1)
+    if nx % f or ny % f:
+        raise ValueError("pool factor must divide the mesh")
+    rc = LIB.vpnet_features(nx, ny, f, _fptr(H, nx * ny, "H", torch.float64),
+                            _fptr(A, nx * ny, "A", torch.float64),
+                            _fptr(v_air, 2 * nn, "v_air", torch.float64),
+                            _fptr(v_ocean, 2 * nn, "v_ocean", torch.float64),
+                            _fptr(v_prev, 2 * nn, "v_prev", torch.float64),
+                            _fptr(out, (nx // f) * (ny // f) * 8, "out"), _stream())
+    if rc != 0:
+        raise VPError(rc, "vpnet_features")
+
+
+def vpnet_targets(nx, ny, v, pi, out):
+    rc = LIB.vpnet_targets(nx, ny, _fptr(v, 2 * (nx + 1) * (ny + 1), "v", torch.float64),
+                           _fptr(pi, 12 * nx * ny, "pi", torch.float64),
+                           _fptr(out, nx * ny * 5, "out"), _stream())
+    if rc != 0:
+        raise VPError(rc, "vpnet_targets")
+
+
+def vpnet_guess(nx, ny, net_out, wc, hc, v0, pi0):
+    rc = LIB.vpnet_guess(nx, ny, _fptr(net_out, wc * hc * 5, "net_out"), wc, hc,
+                         _fptr(v0, 2 * (nx + 1) * (ny + 1), "v0", torch.float64),
+                         _fptr(pi0, 12 * nx * ny, "pi0", torch.float64) if pi0 is not None else None,
+                         _stream())
+    if rc != 0:
+        raise VPError(rc, "vpnet_guess")
+
+
+def vpnet_gemm(A, B, C_out, M, N, K, a_trans=False, b_trans=False):
+    for t, nme, n in ((A, "A", M * K), (B, "B", K * N)):
+        if t.dtype != torch.bfloat16 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise TypeError(f"{nme}: expected a contiguous CUDA bfloat16 tensor of {n} elements")
+    rc = LIB.vpnet_gemm(C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
+                        _fptr(C_out, M * N, "C"), M, N, K, int(a_trans), int(b_trans), _stream())
+    if rc != 0:
+        raise VPError(rc, "vpnet_gemm")
