@@ -23,7 +23,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}   # V-cycle precision modes of vp_amg_opts
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16+learned": 2}   # V-cycle precision per path
 METRIC = "time-to-1e-8 residual, 2048^2 mesh: plain FP64 vs mixed+learned; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
 
@@ -90,7 +90,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--paths", default="fp64,fp32,bf16", help="comma list of fp64, fp32, bf16")
+    ap.add_argument("--paths", default="fp64,fp32,bf16,bf16+learned",
+                    help="comma list of fp64, fp32, bf16, bf16+learned")
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels"],
@@ -123,9 +124,26 @@ def main():
         ao.precision = PREC[path]
         return no, ao, ko
 
+    ws = None
+    fields = None
+    if any(p.endswith("learned") for p in args.paths.split(",")):
+        from paper_2204_10822_amd import warmstart
+        if os.path.exists(warmstart.WEIGHTS):
+            ws = warmstart.WarmStart()
+            fields = ctx._state
+        else:
+            log("no trained warm-start weights: skipping the learned path")
+            args.paths = ",".join(p for p in args.paths.split(",") if not p.endswith("learned"))
+    starts = {}
+
     def solve(path):
-        v.zero_()
-        pi.zero_()
+        if path.endswith("learned"):
+            # learned start (U-Net on the pooled 256-cell grid) with the energy
+            # fallback to the zero start; inside the timed region
+            starts[path] = warmstart.start_with_fallback(ctx, ws, fields, n, n, v, pi, ("learned", "zero"))
+        else:
+            v.zero_()
+            pi.zero_()
         no, ao, ko = opts(path)
         rc, info, _ = ctx.vp_newton_solve(v, pi, 200, no, ao, ko, history=False)
         return rc, info
@@ -186,12 +204,13 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+f32+bf16"}[best],
+        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+f32+bf16",
+                  "bf16+learned": "f64+f32+bf16"}[best],
         "data": "synthetic",
         "config": {"workload": w.name, "mesh": f"{n}x{n} Q1", "unknowns": 2 * nn,
                    "tol": 1e-8, "path": best, "newton_its": R["newton"], "krylov_its": R["krylov"]},
         "paths": {p: dict(median_s=d["median"], times_s=d["times"], newton_its=d["newton"],
-                          krylov_its=d["krylov"]) for p, d in results.items()},
+                          krylov_its=d["krylov"], start=starts.get(p, "zero")) for p, d in results.items()},
         "spmv_gbs": spmv["gbs"] if spmv else None,
         "kernels": R["kernels"],
         "roofline": roof,

@@ -106,9 +106,9 @@ int vp_residual(vp_ctx ctx, const double* v, double* r, double* rnorm, double* e
 int vp_newton_assemble(vp_ctx ctx, const double* v, const double* pi, int variant);
 /* y = K x with the last assembled operator (FP64).  VP_ESTATE before assembly. */
 int vp_operator_apply(vp_ctx ctx, const double* x, double* y);
-/* Copy the assembled operator to a device buffer of 20*(nx+1)*(ny+1) doubles:
- * plane k = 4*blk + 2*r + c holds entry (r,c) of the 2x2 block coupling node n
- * (row dofs) to node n+off(blk), blk 0..4 = self, east (+1,0), north (0,+1),
+/* Copy the assembled operator to a device buffer of 20*(nx+1)*(ny+1) doubles,
+ * layout [blk][node n][r][c]: entry (r,c) of the 2x2 block coupling node n (row
+ * dofs) to node n+off(blk), blk 0..4 = self, east (+1,0), north (0,+1),
  * north-east (+1,+1), north-west (-1,+1); the other four neighbours are the
  * transposes held by those nodes (the operator is symmetric). */
 int vp_operator_export(vp_ctx ctx, double* blocks);

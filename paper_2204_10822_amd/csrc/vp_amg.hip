@@ -4,7 +4,7 @@
 // (B = 2 on the finest level, 3 on coarse levels: the rigid-body modes), and its
 // operator is a symmetric block 9-point stencil stored as five B x B blocks per
 // node (self, E, N, NE, NW; the W, S, SW, SE couplings are the transposes held by
-// the neighbours), plane-major: A[(blk*B*B + r*B + c)*nn + node].
+// the neighbours), block-interleaved: A[aidx(B, nn, blk, node, r, c)].
 //
 // Aggregates are 3x3 node blocks (the last one per direction takes the 3..5
 // remaining nodes).  One block-Jacobi smoothing step of the tentative
@@ -48,24 +48,70 @@ __device__ __forceinline__ int slot1(int i, int n, int nagg, int J) {
 __constant__ int kDI[9] = {0, 1, 0, 1, -1, -1, 0, -1, 1};
 __constant__ int kDJ[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
 
+// Raw B*B values of one stored block (contiguous), widened to TA.  2x2 FP32 and
+// FP64 blocks use 16-byte vector loads.
+template <int B, typename TM, typename TA>
+__device__ __forceinline__ void load_raw(const TM* __restrict__ p, TA (&v)[B * B]) {
+  if constexpr (B == 2 && std::is_same<TM, float>::value) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = (TA)t.x; v[1] = (TA)t.y; v[2] = (TA)t.z; v[3] = (TA)t.w;
+  } else if constexpr (B == 2 && std::is_same<TM, double>::value) {
+    const double2 t0 = reinterpret_cast<const double2*>(p)[0];
+    const double2 t1 = reinterpret_cast<const double2*>(p)[1];
+    v[0] = (TA)t0.x; v[1] = (TA)t0.y; v[2] = (TA)t1.x; v[3] = (TA)t1.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < B * B; ++k) v[k] = (TA)ld(p + k);
+  }
+}
+
+// B values of one node of a vector (2-dof nodes as one 8/16-byte load or store)
+template <int B, typename TV, typename TA>
+__device__ __forceinline__ void load_node(const TV* __restrict__ x, size_t n, TA (&v)[B]) {
+  if constexpr (B == 2 && std::is_same<TV, float>::value) {
+    const float2 t = reinterpret_cast<const float2*>(x)[n];
+    v[0] = (TA)t.x; v[1] = (TA)t.y;
+  } else if constexpr (B == 2 && std::is_same<TV, double>::value) {
+    const double2 t = reinterpret_cast<const double2*>(x)[n];
+    v[0] = (TA)t.x; v[1] = (TA)t.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < B; ++k) v[k] = (TA)x[n * B + k];
+  }
+}
+template <int B, typename TV, typename TA>
+__device__ __forceinline__ void store_node(TV* __restrict__ x, size_t n, const TA (&v)[B]) {
+  if constexpr (B == 2 && std::is_same<TV, float>::value) {
+    reinterpret_cast<float2*>(x)[n] = make_float2((float)v[0], (float)v[1]);
+  } else if constexpr (B == 2 && std::is_same<TV, double>::value) {
+    reinterpret_cast<double2*>(x)[n] = make_double2((double)v[0], (double)v[1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < B; ++k) x[n * B + k] = (TV)v[k];
+  }
+}
+
 // Load the B x B block coupling node (i,j) (rows) to its neighbour in direction d
 // (columns).  Caller guarantees the neighbour exists.
 template <int B, typename TM, typename TA>
 __device__ __forceinline__ void load_block(const TM* __restrict__ A, size_t nn, int nxn, int i, int j,
                                            int d, TA (&out)[B][B]) {
   const size_t n = (size_t)j * nxn + i;
+  TA v[B * B];
   if (d <= 4) {
+    load_raw<B>(A + aidx(B, nn, d, n, 0, 0), v);
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < B; ++c) out[r][c] = (TA)ld(A + (size_t)(d * B * B + r * B + c) * nn + n);
+      for (int c = 0; c < B; ++c) out[r][c] = v[r * B + c];
   } else {
     const int blk = d - 4;  // W->E(1), S->N(2), SW->NE(3), SE->NW(4)
     const size_t m = (size_t)(j + kDJ[d]) * nxn + (i + kDI[d]);
+    load_raw<B>(A + aidx(B, nn, blk, m, 0, 0), v);
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < B; ++c) out[r][c] = (TA)ld(A + (size_t)(blk * B * B + c * B + r) * nn + m);
+      for (int c = 0; c < B; ++c) out[r][c] = v[c * B + r];
   }
 }
 
@@ -129,8 +175,7 @@ __device__ __forceinline__ void stencil_row(const TM* __restrict__ A, size_t nn,
     }
     const size_t m = (size_t)jj * nxn + ii;
     TA xm[B];
-#pragma unroll
-    for (int c = 0; c < B; ++c) xm[c] = (TA)x[m * B + c];
+    load_node<B>(x, m, xm);
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
@@ -152,10 +197,12 @@ k_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
-  TA y[B], D[B][B];
+  TA y[B], D[B][B], bb[B];
   stencil_row<B>(A, nn, nxn, nyn, i, j, x, y, D);
+  if (b) load_node<B>(b, n, bb);
 #pragma unroll
-  for (int k = 0; k < B; ++k) r[n * B + k] = (TV)((b ? (TA)b[n * B + k] : TA(0)) - y[k]);
+  for (int k = 0; k < B; ++k) bb[k] = (b ? bb[k] : TA(0)) - y[k];
+  store_node<B>(r, n, bb);
 }
 
 // y = A x (FP64 finest level), partial sums of x.y per workgroup (for CG)
@@ -192,7 +239,7 @@ k_cheb_first(const TM* __restrict__ A, size_t nn, const TV* __restrict__ src, TV
 #pragma unroll
   for (int rr = 0; rr < B; ++rr)
 #pragma unroll
-    for (int c = 0; c < B; ++c) D[rr][c] = (TA)ld(A + (size_t)(rr * B + c) * nn + n);
+    for (int c = 0; c < B; ++c) D[rr][c] = (TA)ld(A + aidx(B, nn, 0, n, rr, c));
   invert_block<B>(D, Di);
 #pragma unroll
   for (int k = 0; k < B; ++k) s[k] = (TA)src[n * B + k];
@@ -218,28 +265,30 @@ k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __r
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
-  TA y[B], D[B][B], Di[B][B], rn[B];
+  TA y[B], D[B][B], Di[B][B], rn[B], dpn[B], xn[B], dk[B];
   stencil_row<B>(A, nn, nxn, nyn, i, j, dp, y, D);
   invert_block<B>(D, Di);
+  load_node<B>(r, n, rn);
+  load_node<B>(dp, n, dpn);
+  load_node<B>(x, n, xn);
 #pragma unroll
-  for (int k = 0; k < B; ++k) {
-    rn[k] = (TA)r[n * B + k] - y[k];
-    r[n * B + k] = (TV)rn[k];
-  }
+  for (int k = 0; k < B; ++k) rn[k] -= y[k];
+  store_node<B>(r, n, rn);
 #pragma unroll
   for (int k = 0; k < B; ++k) {
     TA t = TA(0);
 #pragma unroll
     for (int c = 0; c < B; ++c) t += Di[k][c] * rn[c];
-    const TA dk = cdd * (TA)dp[n * B + k] + cdr * t;
-    dn[n * B + k] = (TV)dk;
-    x[n * B + k] = (TV)((TA)x[n * B + k] + dk);
+    dk[k] = cdd * dpn[k] + cdr * t;
+    xn[k] += dk[k];
   }
+  store_node<B>(dn, n, dk);
+  store_node<B>(x, n, xn);
 }
 
 // ---------------------------------------------------------------------------
 // transfers: P stored per fine node as 4 slots x (B x 3), plane-major
-//   P[((slot*B + r)*3 + c)*nn + node]
+//   P[pidx(B, slot, node, r, c)]  (node-major: a node's 4 slots are contiguous)
 // slot = sx + 2 sy, sx = 0: own aggregate in x, 1: the adjacent one (agg_other)
 // ---------------------------------------------------------------------------
 template <int B, typename TP, typename TV>
@@ -265,7 +314,7 @@ k_restrict(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int n
       for (int rr = 0; rr < B; ++rr) {
         const TA rv = (TA)r[n * B + rr];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += (TA)ld(P + ((size_t)(s * B + rr) * 3 + c) * nn + n) * rv;
+        for (int c = 0; c < 3; ++c) acc[c] += (TA)ld(P + pidx(B, s, n, rr, c)) * rv;
       }
     }
   }
@@ -297,7 +346,7 @@ k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, in
 #pragma unroll
     for (int rr = 0; rr < B; ++rr)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[rr] += (TA)ld(P + ((size_t)(s * B + rr) * 3 + c) * nn + n) * xj[c];
+      for (int c = 0; c < 3; ++c) acc[rr] += (TA)ld(P + pidx(B, s, n, rr, c)) * xj[c];
   }
 #pragma unroll
   for (int rr = 0; rr < B; ++rr) x[n * B + rr] = (TV)acc[rr];
@@ -563,82 +612,112 @@ k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
         double val = -omega * t;
         if (s == 0) val += Ptent[(size_t)(r * 3 + c) * nn + n];
         if (Jx < 0 || Jy < 0) val = 0.0;
-        P[((size_t)(s * B + r) * 3 + c) * nn + n] = val;
+        P[pidx(B, s, n, r, c)] = val;
       }
   }
 }
 
-// Galerkin coarse operator Ac = P^T A P in the 5-block symmetric storage (B = 3)
+// Galerkin coarse operator Ac = P^T A P in the 5-block symmetric storage (3x3
+// blocks).  One wavefront per coarse node I: lane l takes fine node l of the
+// (<= 7 x 7) window that holds the support of I's prolongator columns, adds its
+// terms P(i,I)^T A(i,k) P(k,J) for its 9 stencil neighbours k and the 5 stored
+// targets J, and the 45 entries are summed across the wave (fixed order).
 template <int B>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(256)
 k_galerkin(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
            const double* __restrict__ P, double* __restrict__ Ac) {
   const size_t ncn = (size_t)ncx * ncy;
-  const size_t I = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= ncn) return;
+  const size_t I = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (I >= ncn) return;  // whole wave exits together
   const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
   const int tJx[5] = {Ix, Ix + 1, Ix, Ix + 1, Ix - 1};
   const int tJy[5] = {Iy, Iy, Iy + 1, Iy + 1, Iy + 1};
   double acc[5][3][3];
+#pragma unroll
   for (int t = 0; t < 5; ++t)
+#pragma unroll
     for (int a = 0; a < 3; ++a)
+#pragma unroll
       for (int c = 0; c < 3; ++c) acc[t][a][c] = 0.0;
   const int i0 = max(3 * Ix - 1, 0), i1 = min(agg_last(Ix, nxn, ncx) + 1, nxn - 1);
   const int j0 = max(3 * Iy - 1, 0), j1 = min(agg_last(Iy, nyn, ncy) + 1, nyn - 1);
-  for (int j = j0; j <= j1; ++j) {
-    const int syI = slot1(j, nyn, ncy, Iy);
-    if (syI < 0) continue;
-    for (int i = i0; i <= i1; ++i) {
-      const int sxI = slot1(i, nxn, ncx, Ix);
-      if (sxI < 0) continue;
-      const int sI = sxI + 2 * syI;
-      const size_t n = (size_t)j * nxn + i;
-      double PI[B][3];
-      for (int r = 0; r < B; ++r)
-        for (int c = 0; c < 3; ++c) PI[r][c] = P[((size_t)(sI * B + r) * 3 + c) * nn + n];
-      for (int d = 0; d < 9; ++d) {
-        const int ii = i + kDI[d], jj = j + kDJ[d];
-        if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
-        double blk[B][B];
-        load_block<B>(A, nn, nxn, i, j, d, blk);
-        // Y = PI^T blk  (3 x B)
-        double Y[3][B];
-        for (int a = 0; a < 3; ++a)
-          for (int k = 0; k < B; ++k) {
-            double t = 0.0;
-            for (int r = 0; r < B; ++r) t += PI[r][a] * blk[r][k];
-            Y[a][k] = t;
-          }
-        const size_t m = (size_t)jj * nxn + ii;
-        for (int t = 0; t < 5; ++t) {
-          const int Jx = tJx[t], Jy = tJy[t];
-          if (Jx < 0 || Jx >= ncx || Jy >= ncy) continue;
-          const int sx = slot1(ii, nxn, ncx, Jx), sy = slot1(jj, nyn, ncy, Jy);
-          if (sx < 0 || sy < 0) continue;
-          const int sJ = sx + 2 * sy;
-          for (int k = 0; k < B; ++k)
-            for (int c = 0; c < 3; ++c) {
-              const double pv = P[((size_t)(sJ * B + k) * 3 + c) * nn + m];
-              for (int a = 0; a < 3; ++a) acc[t][a][c] += Y[a][k] * pv;
-            }
+  const int i = i0 + lane % 7, j = j0 + lane / 7;
+  bool active = lane < 49 && i <= i1 && j <= j1;
+  int sI = 0;
+  if (active) {
+    const int sx = slot1(i, nxn, ncx, Ix), sy = slot1(j, nyn, ncy, Iy);
+    active = sx >= 0 && sy >= 0;
+    sI = sx + 2 * sy;
+  }
+  if (active) {
+    const size_t n = (size_t)j * nxn + i;
+    double PI[B][3];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) PI[r][c] = P[pidx(B, sI, n, r, c)];
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+      double blk[B][B];
+      load_block<B>(A, nn, nxn, i, j, d, blk);
+      double Y[3][B];  // PI^T blk
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          double s = 0.0;
+#pragma unroll
+          for (int r = 0; r < B; ++r) s += PI[r][a] * blk[r][k];
+          Y[a][k] = s;
         }
+      const size_t m = (size_t)jj * nxn + ii;
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        const int Jx = tJx[t], Jy = tJy[t];
+        if (Jx < 0 || Jx >= ncx || Jy >= ncy) continue;
+        const int sx = slot1(ii, nxn, ncx, Jx), sy = slot1(jj, nyn, ncy, Jy);
+        if (sx < 0 || sy < 0) continue;
+        const int sJ = sx + 2 * sy;
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double pv = P[pidx(B, sJ, m, k, c)];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[t][a][c] += Y[a][k] * pv;
+          }
       }
     }
   }
+#pragma unroll
+  for (int t = 0; t < 5; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[t][a][c] = wave_sum(acc[t][a][c]);
+  if (lane != 0) return;
   // symmetrise the diagonal block; guard empty coarse dofs
+#pragma unroll
   for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int c = a + 1; c < 3; ++c) {
       const double s = 0.5 * (acc[0][a][c] + acc[0][c][a]);
       acc[0][a][c] = acc[0][c][a] = s;
     }
+#pragma unroll
   for (int a = 0; a < 3; ++a)
     if (acc[0][a][a] == 0.0) acc[0][a][a] = 1.0;
+#pragma unroll
   for (int t = 0; t < 5; ++t) {
     const int Jx = tJx[t], Jy = tJy[t];
     const bool valid = !(Jx < 0 || Jx >= ncx || Jy >= ncy);
+#pragma unroll
     for (int a = 0; a < 3; ++a)
-      for (int c = 0; c < 3; ++c)
-        Ac[(size_t)(t * 9 + a * 3 + c) * ncn + I] = valid ? acc[t][a][c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Ac[aidx(3, ncn, t, I, a, c)] = valid ? acc[t][a][c] : 0.0;
   }
 }
 
@@ -649,7 +728,7 @@ __global__ void k_diag_sqrt(const double* __restrict__ A, size_t nn, double* __r
   const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   for (int r = 0; r < B; ++r) {
-    const double d = A[(size_t)(r * B + r) * nn + n];
+    const double d = A[aidx(B, nn, 0, n, r, r)];
     dsc[n * B + r] = d > 0.0 ? sqrt(d) : 1.0;
   }
 }
@@ -667,7 +746,7 @@ __global__ void k_scale_to_bf16(const double* __restrict__ A, size_t nn, int nxn
     const size_t m = ok ? (size_t)jj * nxn + ii : n;
     for (int r = 0; r < B; ++r)
       for (int c = 0; c < B; ++c) {
-        const size_t k = (size_t)(blk * B * B + r * B + c) * nn + n;
+        const size_t k = aidx(B, nn, blk, n, r, c);
         const double v = ok ? A[k] / (dsc[n * B + r] * dsc[m * B + c]) : 0.0;
         S[k] = __float2bfloat16((float)v);
       }
@@ -690,7 +769,7 @@ __global__ void k_scale_p(const double* __restrict__ P, size_t nn, int nxn, int 
     const size_t J = ok ? (size_t)Jy * ncx + Jx : 0;
     for (int r = 0; r < B; ++r)
       for (int c = 0; c < 3; ++c) {
-        const size_t k = ((size_t)(s * B + r) * 3 + c) * nn + n;
+        const size_t k = pidx(B, s, n, r, c);
         const double fr = dsc_f ? dsc_f[n * B + r] : 1.0;
         Ps[k] = ok ? (float)(fr * P[k] / dsc_c[J * 3 + c]) : 0.0f;
       }
@@ -747,6 +826,38 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(double* __restrict__ M, i
     }
     __syncthreads();
   }
+}
+
+// Same inversion with the whole matrix resident in LDS (nd <= kLdsGJ; gfx950 has
+// 160 KB of LDS per CU): one global read and write instead of nd passes.
+constexpr int kLdsGJ = 140;
+__global__ void __launch_bounds__(1024) k_gauss_jordan_lds(double* __restrict__ M, int nd) {
+  __shared__ double S[kLdsGJ * kLdsGJ];
+  __shared__ double rowk[kLdsGJ];
+  __shared__ double colk[kLdsGJ];
+  const int n2 = nd * nd;
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) S[e] = M[e];
+  __syncthreads();
+  for (int k = 0; k < nd; ++k) {
+    const double piv = S[k * nd + k];
+    const double ip = piv != 0.0 ? 1.0 / piv : 0.0;
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+      rowk[t] = S[k * nd + t];
+      colk[t] = S[t * nd + k];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+      const int r = e / nd, c = e % nd;
+      double v;
+      if (r == k && c == k) v = ip;
+      else if (r == k) v = rowk[c] * ip;
+      else if (c == k) v = -colk[r] * ip;
+      else v = S[e] - colk[r] * rowk[c] * ip;
+      S[e] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) M[e] = S[e];
 }
 
 template <typename TM, typename TV>
@@ -995,12 +1106,12 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
                          L.Ptent, L.lmax, omega_scale, L.P64);
     VP_LAUNCH_CHECK();
     Level& N = c->lev[l + 1];
-    const unsigned gc = (unsigned)((N.nn + 127) / 128);
+    const unsigned gc = (unsigned)((N.nn + 3) / 4);  // one wavefront per coarse node
     if (L.B == 2)
-      hipLaunchKernelGGL(k_galerkin<2>, dim3(gc), dim3(128), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+      hipLaunchKernelGGL(k_galerkin<2>, dim3(gc), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          L.P64, N.A64);
     else
-      hipLaunchKernelGGL(k_galerkin<3>, dim3(gc), dim3(128), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+      hipLaunchKernelGGL(k_galerkin<3>, dim3(gc), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          L.P64, N.A64);
     VP_LAUNCH_CHECK();
   }
@@ -1014,7 +1125,8 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   else
     hipLaunchKernelGGL(k_to_dense<3>, dim3(gd), dim3(128), 0, s, C.A64, C.nn, C.nxn, C.nyn, C.Ainv64);
   VP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, C.Ainv64, nd);
+  if (nd <= kLdsGJ) hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(1024), 0, s, C.Ainv64, nd);
+  else hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, C.Ainv64, nd);
   VP_LAUNCH_CHECK();
   // reduced-precision copies
   if (precision == VP_PREC_FP32_BF16COARSE) {

@@ -384,7 +384,7 @@ extern "C" {
 
 void vp_default_opts(vp_newton_opts* n, vp_amg_opts* a, vp_krylov_opts* k) {
   if (n) *n = vp_newton_opts{VP_SVN, 1e-8, 0.1, 30, VP_LS_ENERGY};
-  if (a) *a = vp_amg_opts{3, 300, VP_PREC_FP64, 30.0, 1.0};
+  if (a) *a = vp_amg_opts{3, 140, VP_PREC_FP64, 30.0, 1.0};
   if (k) *k = vp_krylov_opts{VP_KRYLOV_FCG, 30, 500, 1e-2};
 }
 

@@ -355,12 +355,16 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
     bool zero;
     if (b == 0) zero = bn;
     else zero = bn || nbi[b] < 0 || nbi[b] > c.nx || nbj[b] > c.ny || is_boundary(c, nbi[b], nbj[b]);
+    double val[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      double val = zero ? 0.0 : blk[b][k];
-      if (b == 0 && bn) val = (k == 0 || k == 3) ? 1.0 : 0.0;
-      K[(size_t)(b * 4 + k) * nn + n] = val;
+      val[k] = zero ? 0.0 : blk[b][k];
+      if (b == 0 && bn) val[k] = (k == 0 || k == 3) ? 1.0 : 0.0;
     }
+    // block-interleaved storage: the block's 4 values are contiguous (32 bytes)
+    double2* dst = reinterpret_cast<double2*>(K + aidx(2, nn, b, n, 0, 0));
+    dst[0] = make_double2(val[0], val[1]);
+    dst[1] = make_double2(val[2], val[3]);
   }
 }
 

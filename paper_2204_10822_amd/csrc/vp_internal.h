@@ -98,6 +98,19 @@ inline unsigned grid_for(size_t n, int block = kBlock) {
   return (unsigned)g;
 }
 
+// Operator storage (every level): block-interleaved, five B x B blocks per node
+// (self, E, N, NE, NW), each block's B*B values contiguous:
+//   A[aidx(B, nn, blk, n, r, c)] = ((blk * nn + n) * B + r) * B + c
+// so a 2x2 FP32 block is one 16-byte load and a wave reads contiguous memory.
+__host__ __device__ __forceinline__ size_t aidx(int B, size_t nn, int blk, size_t n, int r, int c) {
+  return (((size_t)blk * nn + n) * B + r) * B + c;
+}
+// Smoothed prolongator: per fine node 4 slots x (B x 3), node-major:
+//   P[pidx(B, s, n, r, c)] = ((n * 4 + s) * B + r) * 3 + c
+__host__ __device__ __forceinline__ size_t pidx(int B, int s, size_t n, int r, int c) {
+  return (((size_t)n * 4 + s) * B + r) * 3 + c;
+}
+
 // bf16 storage helpers (round to nearest even)
 __device__ __forceinline__ float ld(const float* p) { return *p; }
 __device__ __forceinline__ double ld(const double* p) { return *p; }
@@ -183,7 +196,7 @@ struct vp_ctx_s {
   int amg_prec = 0;
   int cheb_degree = 3;
   double cheb_ratio = 30.0;
-  int max_coarse = 300;
+  int max_coarse = 140;
   int power_its_cold = 16, power_its_warm = 6;
   double power_factor = 1.15;
   // scratch

@@ -61,7 +61,7 @@ def export_matrix(vp, ctx, nx, ny):
     nn = nxn * nyn
     blocks = torch.zeros(20, nn, dtype=torch.float64, device="cuda")
     ctx.vp_operator_export(blocks)
-    B = _host(blocks).reshape(5, 2, 2, nn)
+    B = _host(blocks).reshape(5, nn, 2, 2).transpose(0, 2, 3, 1)   # [blk][r][c][node]
     jj, ii = np.divmod(np.arange(nn), nxn)
     offs = [(0, 0), (1, 0), (0, 1), (1, 1), (-1, 1)]
     rows, cols, vals = [], [], []
