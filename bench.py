@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16+learned": 2}   # V-cycle precision per path
 METRIC = "time-to-1e-8 residual, 2048^2 mesh: plain FP64 vs mixed+learned; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak
 
 
 def log(*a):
@@ -215,6 +216,22 @@ def main():
         "kernels": R["kernels"],
         "roofline": roof,
     }
+    # learned warm start kernels: BF16 MFMA forward and training step on 256^2 inputs
+    try:
+        from paper_2204_10822_amd import warmstart as _ws
+        nb = _ws.bench_net(batch=8, reps=10)
+        nb1 = _ws.bench_net(batch=1, reps=20)
+        out["unet"] = dict(
+            forward_b1_ms=nb1["forward"]["ms"], forward_b8_ms=nb["forward"]["ms"],
+            train_step_b8_ms=nb["train_step"]["ms"],
+            roofline=dict(kernel="unet train step (all layers)", bound="mfma",
+                          achieved=nb["train_step"]["tflops"], peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                          frac=nb["train_step"]["tflops"] / BF16_PEAK_TFLOPS),
+            forward_tflops=nb["forward"]["tflops"])
+        log(f"unet: forward b8 {nb['forward']['ms']:.2f} ms ({nb['forward']['tflops']:.1f} TFLOP/s), "
+            f"train step b8 {nb['train_step']['ms']:.2f} ms")
+    except Exception as e:  # the solver metric stands on its own
+        out["unet"] = dict(error=str(e))
     if not args.no_cpu:
         log(f"cpu baseline: oracle on a {args.cpu_sample}^2 sample")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample, R["newton"][0], n)

@@ -38,13 +38,56 @@ __device__ __forceinline__ short bf_bits(bf16 x) {
   return s;
 }
 
+// Stage one 64 x 32 operand tile into LDS as T[row][k] (row = m for A, n for B).
+// `kmajor` operands are stored [K][rows] (contiguous along rows), the others
+// [rows][K] (contiguous along K).  Each thread moves 8 consecutive elements with
+// one 16-byte load when the ld is a multiple of 8 and the vector is in bounds.
+template <bool KMAJOR>
+__device__ __forceinline__ void stage_tile(const bf16* __restrict__ X, int rows, int kend, int ld, int r0, int k0,
+                                           short (*T)[BK + 4], int tid) {
+  const unsigned short* Xs = reinterpret_cast<const unsigned short*>(X);
+  if (!KMAJOR) {
+    const int r = tid >> 2, c = (tid & 3) * 8;
+    const int gr = r0 + r, gk = k0 + c;
+    if ((ld & 7) == 0 && gr < rows && gk + 8 <= kend) {
+      const uint4 v = *reinterpret_cast<const uint4*>(Xs + (size_t)gr * ld + gk);
+      const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T[r][c + 2 * q] = (short)(w[q] & 0xffff);
+        T[r][c + 2 * q + 1] = (short)(w[q] >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        T[r][c + q] = (gr < rows && gk + q < kend) ? (short)Xs[(size_t)gr * ld + gk + q] : (short)0;
+    }
+  } else {
+    const int c = tid >> 3, r = (tid & 7) * 8;
+    const int gr = r0 + r, gk = k0 + c;
+    if ((ld & 7) == 0 && gk < kend && gr + 8 <= rows) {
+      const uint4 v = *reinterpret_cast<const uint4*>(Xs + (size_t)gk * ld + gr);
+      const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T[r + 2 * q][c] = (short)(w[q] & 0xffff);
+        T[r + 2 * q + 1][c] = (short)(w[q] >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        T[r + q][c] = (gk < kend && gr + q < rows) ? (short)Xs[(size_t)gk * ld + gr + q] : (short)0;
+    }
+  }
+}
+
 template <bool AT, bool BT, bool OUT_BF16>
 __global__ void __launch_bounds__(256)
 k_gemm(const bf16* __restrict__ A, const bf16* __restrict__ B, int M, int N, int K, int lda, int ldb,
        const float* __restrict__ bias, int relu, bf16* __restrict__ Cb, float* __restrict__ C32, int ldc,
        int k_per_split) {
-  __shared__ short As[BM][BK + 4];
-  __shared__ short Bs[BK][BN + 4];
+  __shared__ short As[BM][BK + 4];   // [m][k]
+  __shared__ short Bs[BN][BK + 4];   // [n][k] (B kept transposed: fragments are contiguous)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int kbeg = blockIdx.z * k_per_split;
@@ -57,29 +100,8 @@ k_gemm(const bf16* __restrict__ A, const bf16* __restrict__ B, int M, int N, int
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // stage A (BM x BK) and B (BK x BN): 2048 elements each, 8 per thread
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + t * 256;
-      int r, c;
-      if (!AT) { r = e / BK; c = e % BK; }   // consecutive threads along k (row-major A)
-      else { c = e / BM; r = e % BM; }       // consecutive threads along m (A stored [K][M])
-      const int gm = m0 + r, gk = k0 + c;
-      short v = 0;
-      if (gm < M && gk < kend) v = bf_bits(AT ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk]);
-      As[r][c] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + t * 256;
-      int r, c;
-      if (!BT) { r = e / BN; c = e % BN; }   // along n (B stored [K][N])
-      else { c = e / BK; r = e % BK; }       // along k (B stored [N][K])
-      const int gk = k0 + r, gn = n0 + c;
-      short v = 0;
-      if (gk < kend && gn < N) v = bf_bits(BT ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn]);
-      Bs[r][c] = v;
-    }
+    stage_tile<AT>(A, M, kend, lda, m0, k0, As, tid);
+    stage_tile<!BT>(B, N, kend, ldb, n0, k0, Bs, tid);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
@@ -88,12 +110,12 @@ k_gemm(const bf16* __restrict__ A, const bf16* __restrict__ B, int M, int N, int
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int row = wm + 16 * i + (lane & 15);
-        af[i] = v4s{As[row][kq], As[row][kq + 1], As[row][kq + 2], As[row][kq + 3]};
+        af[i] = *reinterpret_cast<const v4s*>(&As[row][kq]);
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int col = wn + 16 * j + (lane & 15);
-        bfr[j] = v4s{Bs[kq][col], Bs[kq + 1][col], Bs[kq + 2][col], Bs[kq + 3][col]};
+        bfr[j] = *reinterpret_cast<const v4s*>(&Bs[col][kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -127,45 +149,50 @@ k_gemm(const bf16* __restrict__ A, const bf16* __restrict__ B, int M, int N, int
 // ---------------------------------------------------------------------------
 // layout kernels (NHWC)
 // ---------------------------------------------------------------------------
-// col[p][(ky*3+kx)*(C1+C2) + c] = X(p + (ky-1, kx-1), c), X = concat(X1, X2) along channels
+// col[p][(ky*3+kx)*(C1+C2) + c] = X(p + (ky-1, kx-1), c), X = concat(X1, X2) along
+// channels.  One thread per (pixel, tap, 8-channel group): a 16-byte copy (C1, C2
+// are multiples of 8).
 __global__ void k_im2col3(const bf16* __restrict__ X1, int C1, const bf16* __restrict__ X2, int C2,
                           int Bn, int H, int W, bf16* __restrict__ col) {
-  const int C = C1 + C2;
-  const size_t total = (size_t)Bn * H * W * 9 * C;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e % C);
-    const int kp = (int)((e / C) % 9);
-    const size_t p = e / ((size_t)9 * C);
-    const int x = (int)(p % W), y = (int)((p / W) % H), b = (int)(p / ((size_t)W * H));
-    const int yy = y + kp / 3 - 1, xx = x + kp % 3 - 1;
-    bf16 v = __float2bfloat16(0.f);
+  const int C = C1 + C2, G = C >> 3;
+  const unsigned total = (unsigned)Bn * H * W * 9 * G;
+  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const unsigned g = e % G, t = e / G;
+    const unsigned kp = t % 9, p = t / 9;
+    const unsigned x = p % W, y = (p / W) % H, b = p / (W * H);
+    const int yy = (int)y + (int)(kp / 3) - 1, xx = (int)x + (int)(kp % 3) - 1;
+    const int c = 8 * (int)g;
+    uint4 v = make_uint4(0, 0, 0, 0);
     if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
       const size_t q = ((size_t)b * H + yy) * W + xx;
-      v = c < C1 ? X1[q * C1 + c] : X2[q * C2 + (c - C1)];
+      v = c < C1 ? *reinterpret_cast<const uint4*>(X1 + q * C1 + c)
+                 : *reinterpret_cast<const uint4*>(X2 + q * C2 + (c - C1));
     }
-    col[e] = v;
+    *reinterpret_cast<uint4*>(col + ((size_t)p * 9 + kp) * C + c) = v;
   }
 }
 
-// dX(q, c) = sum_{kp} dcol[q - off(kp)][kp*C + c]; split into the two inputs' gradients
+// dX(q, c) = sum_{kp} dcol[q - off(kp)][kp*C + c]; split into the two inputs'
+// gradients.  One thread per (pixel, 4-channel group), float4 accesses.
 __global__ void k_col2im3(const float* __restrict__ dcol, int C1, int C2, int Bn, int H, int W,
                           float* __restrict__ dX1, float* __restrict__ dX2) {
-  const int C = C1 + C2;
-  const size_t total = (size_t)Bn * H * W * C;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e % C);
-    const size_t q = e / C;
-    const int x = (int)(q % W), y = (int)((q / W) % H), b = (int)(q / ((size_t)W * H));
-    float s = 0.f;
+  const int C = C1 + C2, G = C >> 2;
+  const unsigned total = (unsigned)Bn * H * W * G;
+  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const unsigned g = e % G, q = e / G;
+    const unsigned x = q % W, y = (q / W) % H, b = q / (W * H);
+    const int c = 4 * (int)g;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int kp = 0; kp < 9; ++kp) {
-      const int py = y - (kp / 3 - 1), px = x - (kp % 3 - 1);
+      const int py = (int)y - (kp / 3 - 1), px = (int)x - (kp % 3 - 1);
       if (py < 0 || py >= H || px < 0 || px >= W) continue;
       const size_t p = ((size_t)b * H + py) * W + px;
-      s += dcol[p * 9 * C + kp * C + c];
+      const float4 d = *reinterpret_cast<const float4*>(dcol + (p * 9 + kp) * C + c);
+      s.x += d.x; s.y += d.y; s.z += d.z; s.w += d.w;
     }
-    if (c < C1) dX1[q * C1 + c] = s;
-    else if (dX2) dX2[q * C2 + (c - C1)] = s;
+    if (c < C1) *reinterpret_cast<float4*>(dX1 + (size_t)q * C1 + c) = s;
+    else if (dX2) *reinterpret_cast<float4*>(dX2 + (size_t)q * C2 + (c - C1)) = s;
   }
 }
 
@@ -225,19 +252,51 @@ __global__ void k_sum_splits(const float* __restrict__ part, int splits, size_t 
   }
 }
 
-// bias gradient: db[c] = sum_p g[p][c]; one workgroup per channel, fixed order
-__global__ void k_bias_grad(const bf16* __restrict__ g, size_t P, int C, float* __restrict__ db) {
+// Column sums over pixels in two fixed-order stages: workgroup b sums pixels
+// [b*chunk, (b+1)*chunk) for every column (thread t owns columns t, t+256, ...),
+// writing part[b][col]; k_sum_splits then adds the parts in order.
+// Used for bias gradients (BF16 g) and for the head gradients.
+__global__ void k_colsum_bf16(const bf16* __restrict__ g, size_t P, int C, size_t chunk, float* __restrict__ part) {
+  const size_t p0 = (size_t)blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    float s = 0.f;
+    for (size_t p = p0; p < p1; ++p) s += (float)g[p * C + c];
+    part[(size_t)blockIdx.x * C + c] = s;
+  }
+}
+
+// head: part[b][c*O + o] = sum_p X[p][c] G[p][o], part[b][C*O + o] = sum_p G[p][o]
+// over pixel chunk b; one thread per output entry
+// out[col] = sum_k part[k][col] for k < parts: one workgroup per column, fixed order
+__global__ void k_reduce_parts(const float* __restrict__ part, int parts, int ncol, float* __restrict__ out) {
   __shared__ float lds[256];
-  const int c = blockIdx.x;
+  const int col = blockIdx.x;
   float s = 0.f;
-  for (size_t p = threadIdx.x; p < P; p += blockDim.x) s += (float)g[p * C + c];
+  for (int k = threadIdx.x; k < parts; k += blockDim.x) s += part[(size_t)k * ncol + col];
   lds[threadIdx.x] = s;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) db[c] = lds[0];
+  if (threadIdx.x == 0) out[col] = lds[0];
+}
+
+__global__ void k_head_wgrad_part(const bf16* __restrict__ X, const float* __restrict__ G, size_t P, int C,
+                                  int O, size_t chunk, float* __restrict__ part) {
+  const int K = C * O + O;
+  const size_t p0 = (size_t)blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+  for (int e = threadIdx.x; e < K; e += blockDim.x) {
+    float s = 0.f;
+    if (e < C * O) {
+      const int c = e / O, o = e % O;
+      for (size_t p = p0; p < p1; ++p) s += (float)X[p * C + c] * G[p * O + o];
+    } else {
+      const int o = e - C * O;
+      for (size_t p = p0; p < p1; ++p) s += G[p * O + o];
+    }
+    part[(size_t)blockIdx.x * K + e] = s;
+  }
 }
 
 // 1x1 output head in FP32: out[p][o] = sum_c X[p][c] W[c][o] + b[o]
@@ -265,23 +324,6 @@ __global__ void k_mse(const float* __restrict__ out, const float* __restrict__ t
   }
   block_sum<1>(a, lds);
   if (threadIdx.x == 0) partials[blockIdx.x] = a[0];
-}
-
-// head backward: dW[c][o] = sum_p X[p][c] G[p][o] (one thread per (c,o), fixed order);
-__global__ void k_head_wgrad(const bf16* __restrict__ X, const float* __restrict__ G, size_t P, int C, int O,
-                             float* __restrict__ dW, float* __restrict__ db) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < C * O) {
-    const int c = e / O, o = e % O;
-    float s = 0.f;
-    for (size_t p = 0; p < P; ++p) s += (float)X[p * C + c] * G[p * O + o];
-    dW[e] = s;
-  } else if (e < C * O + O) {
-    const int o = e - C * O;
-    float s = 0.f;
-    for (size_t p = 0; p < P; ++p) s += G[p * O + o];
-    db[o] = s;
-  }
 }
 
 // head input grad: dX[p][c] = sum_o G[p][o] W[c][o]
@@ -433,6 +475,7 @@ T* dalloc(size_t n) {
 inline unsigned gs(size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 16384); }
 
 enum Kind { CONV3 = 0, DOWN = 1, UP = 2, HEAD = 3 };
+constexpr int kSumParts = 1024;  // pixel chunks of the two-stage column sums
 
 struct Layer {
   Kind kind;
@@ -580,7 +623,7 @@ void forward(vpnet_s* n) {
       const Act& X2 = L.in2 >= 0 ? n->acts[L.in2] : X;
       const int C = L.cin + L.cin2;
       ensure(n->col, n->col_n, P * 9 * C);
-      hipLaunchKernelGGL(k_im2col3, dim3(gs(P * 9 * C)), dim3(256), 0, s, X.y, L.cin,
+      hipLaunchKernelGGL(k_im2col3, dim3(gs(P * 9 * C / 8)), dim3(256), 0, s, X.y, L.cin,
                          L.in2 >= 0 ? X2.y : nullptr, L.cin2, Bn, L.H, L.W, n->col);
       VP_LAUNCH_CHECK();
       gemm<false, false, true>(s, n->col, Wt, (int)P, L.cout, 9 * C, 9 * C, L.cout, b, 1, n->acts[L.out].y, nullptr,
@@ -621,8 +664,13 @@ void backward(vpnet_s* n) {
     float* dW = n->g + L.woff;
     float* db = n->g + L.boff;
     if (L.kind == HEAD) {
-      hipLaunchKernelGGL(k_head_wgrad, dim3((L.cin * kCout + kCout + 255) / 256), dim3(256), 0, s, X.y, n->gout, P,
-                         L.cin, kCout, dW, db);
+      const int K = L.cin * kCout + kCout;  // dW then db, contiguous in the parameter vector
+      const size_t chunk = (P + kSumParts - 1) / kSumParts;
+      ensure(n->part, n->part_n, (size_t)kSumParts * K);
+      hipLaunchKernelGGL(k_head_wgrad_part, dim3(kSumParts), dim3(128), 0, s, X.y, n->gout, P, L.cin, kCout,
+                         chunk, n->part);
+      VP_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_reduce_parts, dim3(K), dim3(256), 0, s, n->part, kSumParts, K, dW);
       VP_LAUNCH_CHECK();
       ensure(n->tmp, n->tmp_n, P * L.cin);
       hipLaunchKernelGGL(k_head_dgrad, dim3(gs(P * L.cin)), dim3(256), 0, s, n->gout, P, L.cin, n->w + L.woff, kCout,
@@ -637,15 +685,21 @@ void backward(vpnet_s* n) {
     ensure(n->gb, n->gb_n, ny);
     hipLaunchKernelGGL(k_relu_grad, dim3(gs(ny)), dim3(256), 0, s, Y.g, Y.y, ny, 1, n->gb);
     VP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_bias_grad, dim3(L.cout), dim3(256), 0, s, n->gb, P, L.cout, db);
-    VP_LAUNCH_CHECK();
+    {
+      const size_t chunk = (P + kSumParts - 1) / kSumParts;
+      ensure(n->part, n->part_n, (size_t)kSumParts * L.cout);
+      hipLaunchKernelGGL(k_colsum_bf16, dim3(kSumParts), dim3(128), 0, s, n->gb, P, L.cout, chunk, n->part);
+      VP_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_reduce_parts, dim3(L.cout), dim3(256), 0, s, n->part, kSumParts, L.cout, db);
+      VP_LAUNCH_CHECK();
+    }
     const bf16* Wt = n->wb + L.woff;
     if (L.kind == CONV3) {
       const Act& X2 = L.in2 >= 0 ? n->acts[L.in2] : X;
       const int C = L.cin + L.cin2;
       ensure(n->col, n->col_n, P * 9 * C);
-      hipLaunchKernelGGL(k_im2col3, dim3(gs(P * 9 * C)), dim3(256), 0, s, X.y, L.cin, L.in2 >= 0 ? X2.y : nullptr,
-                         L.cin2, Bn, L.H, L.W, n->col);
+      hipLaunchKernelGGL(k_im2col3, dim3(gs(P * 9 * C / 8)), dim3(256), 0, s, X.y, L.cin,
+                         L.in2 >= 0 ? X2.y : nullptr, L.cin2, Bn, L.H, L.W, n->col);
       VP_LAUNCH_CHECK();
       // dW = col^T g  [9C x cout]
       gemm_f32(n, true, false, n->col, n->gb, 9 * C, L.cout, (int)P, 9 * C, L.cout, dW);
@@ -656,7 +710,8 @@ void backward(vpnet_s* n) {
       ensure(n->tmp, n->tmp_n, P * C);
       float* t1 = n->tmp;
       float* t2 = L.in2 >= 0 ? n->tmp + P * L.cin : nullptr;
-      hipLaunchKernelGGL(k_col2im3, dim3(gs(P * C)), dim3(256), 0, s, n->fcol, L.cin, L.cin2, Bn, L.H, L.W, t1, t2);
+      hipLaunchKernelGGL(k_col2im3, dim3(gs(P * C / 4)), dim3(256), 0, s, n->fcol, L.cin, L.cin2, Bn, L.H, L.W, t1,
+                         t2);
       VP_LAUNCH_CHECK();
       if (L.in > 0) {
         hipLaunchKernelGGL(k_add_into, dim3(gs(P * L.cin)), dim3(256), 0, s, X.g, t1, P * L.cin);
