@@ -23,7 +23,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16+learned": 2}   # V-cycle precision per path
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16+learned": 2, "bf16all": 3, "bf16all+learned": 3}
 METRIC = "time-to-1e-8 residual, 2048^2 mesh: plain FP64 vs mixed+learned; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak
@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--paths", default="fp64,fp32,bf16,bf16+learned",
-                    help="comma list of fp64, fp32, bf16, bf16+learned")
+                    help="comma list of fp64, fp32, bf16, bf16+learned, bf16all, bf16all+learned")
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels"],
@@ -205,8 +205,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+f32+bf16",
-                  "bf16+learned": "f64+f32+bf16"}[best],
+        "dtype": {"fp64": "f64", "fp32": "f64+f32"}.get(best, "f64+f32+bf16"),
         "data": "synthetic",
         "config": {"workload": w.name, "mesh": f"{n}x{n} Q1", "unknowns": 2 * nn,
                    "tol": 1e-8, "path": best, "newton_its": R["newton"], "krylov_its": R["krylov"]},
@@ -216,6 +215,26 @@ def main():
         "kernels": R["kernels"],
         "roofline": roof,
     }
+    # achievable streaming bandwidth on this device: a 1 GiB device copy and a triad
+    a_ = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b_ = torch.ones_like(a_)
+    c_ = torch.empty_like(a_)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = {}
+    for name, fn, nbytes in (("copy", lambda: c_.copy_(a_), 2 << 30),
+                             ("triad", lambda: torch.add(a_, b_, alpha=0.5, out=c_), 3 << 30)):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(10):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        stream[name + "_gbs"] = nbytes / (ev0.elapsed_time(ev1) / 10 * 1e-3) / 1e9
+    del a_, b_, c_
+    out["stream"] = stream
+    out["roofline"]["frac_of_measured_triad"] = D["gbs"] / stream["triad_gbs"]
+    log(f"stream: copy {stream['copy_gbs']:.0f} GB/s, triad {stream['triad_gbs']:.0f} GB/s")
     # learned warm start kernels: BF16 MFMA forward and training step on 256^2 inputs
     try:
         from paper_2204_10822_amd import warmstart as _ws

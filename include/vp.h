@@ -70,7 +70,7 @@ enum {
   VP_EBREAKDOWN = -6       /* Krylov breakdown (indefinite or singular operator)    */
 };
 enum { VP_SVN = 0, VP_STDN = 1 };                         /* linearisation          */
-enum { VP_PREC_FP64 = 0, VP_PREC_FP32 = 1, VP_PREC_FP32_BF16COARSE = 2 };
+enum { VP_PREC_FP64 = 0, VP_PREC_FP32 = 1, VP_PREC_FP32_BF16COARSE = 2, VP_PREC_BF16 = 3 };
 enum { VP_KRYLOV_FGMRES = 0, VP_KRYLOV_FCG = 1 };
 enum { VP_LS_ENERGY = 0, VP_LS_RESIDUAL = 1 };
 
@@ -120,7 +120,9 @@ int vp_operator_export(vp_ctx ctx, double* blocks);
 typedef struct {
   int cheb_degree;       /* Chebyshev degree per pre/post smoothing (>= 1)         */
   int max_coarse;        /* coarsest level dof bound (<= 1024)                     */
-  int precision;         /* VP_PREC_*: V-cycle arithmetic and coarse storage       */
+  int precision;         /* VP_PREC_*: V-cycle arithmetic and operator storage:
+                            FP64; FP32; FP32 finest + BF16 Jacobi-scaled coarse levels;
+                            BF16 Jacobi-scaled on every level (FP32 arithmetic)      */
   double cheb_ratio;     /* smoothing interval [lmax/ratio, lmax]                  */
   double omega_scale;    /* prolongator damping scale (1 = 4/(3 lmax))             */
 } vp_amg_opts;

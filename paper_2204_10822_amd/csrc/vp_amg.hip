@@ -55,6 +55,10 @@ __device__ __forceinline__ void load_raw(const TM* __restrict__ p, TA (&v)[B * B
   if constexpr (B == 2 && std::is_same<TM, float>::value) {
     const float4 t = *reinterpret_cast<const float4*>(p);
     v[0] = (TA)t.x; v[1] = (TA)t.y; v[2] = (TA)t.z; v[3] = (TA)t.w;
+  } else if constexpr (B == 2 && std::is_same<TM, __hip_bfloat16>::value) {
+    const uint2 t = *reinterpret_cast<const uint2*>(p);   // 4 BF16 = 8 bytes
+    v[0] = (TA)__uint_as_float(t.x << 16); v[1] = (TA)__uint_as_float(t.x & 0xffff0000u);
+    v[2] = (TA)__uint_as_float(t.y << 16); v[3] = (TA)__uint_as_float(t.y & 0xffff0000u);
   } else if constexpr (B == 2 && std::is_same<TM, double>::value) {
     const double2 t0 = reinterpret_cast<const double2*>(p)[0];
     const double2 t1 = reinterpret_cast<const double2*>(p)[1];
@@ -776,6 +780,19 @@ __global__ void k_scale_p(const double* __restrict__ P, size_t nn, int nxn, int 
   }
 }
 
+// y = (float)(x / dsc) and y = (double)(x) / dsc: the V-cycle's input and output
+// in the Jacobi-scaled variables of a BF16 finest level
+__global__ void k_scale_cast_df(const double* __restrict__ x, const double* __restrict__ dsc, float* __restrict__ y,
+                                size_t n) {
+  for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = (float)(x[e] / dsc[e]);
+}
+__global__ void k_scale_cast_fd(const float* __restrict__ x, const double* __restrict__ dsc, double* __restrict__ y,
+                                size_t n) {
+  for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = (double)x[e] / dsc[e];
+}
+
 // (D^{1/2} A^{-1} D^{1/2}) of the coarsest level in FP32 (inverse of the scaled operator)
 __global__ void k_scale_dense(const double* __restrict__ M, int nd, const double* __restrict__ dsc,
                               float* __restrict__ out) {
@@ -1001,12 +1018,25 @@ void alloc_vectors(vp_ctx c) {
 // S_l = D_l^{-1/2} A_l D_l^{-1/2} in BF16 and the V-cycle works there in the
 // scaled variables, with prolongators P^_l = D_l^{1/2} P_l D_{l+1}^{-1/2} (FP32;
 // D_0 = I) and the coarsest inverse D^{1/2} A^{-1} D^{1/2} (FP32).
-void bf16_copies(vp_ctx c, hipStream_t s) {
+void bf16_copies(vp_ctx c, hipStream_t s, bool finest_bf16) {
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const size_t na = (size_t)5 * L.B * L.B * L.nn;
     const unsigned g = (unsigned)((L.nn + 255) / 256);
-    if (l == 0) {
+    if (l == 0 && finest_bf16) {
+      if (!L.dsc64) L.dsc64 = dalloc<double>((size_t)L.B * L.nn);
+      if (!L.Abf) L.Abf = dalloc<__hip_bfloat16>(na);
+      if (L.B == 2) {
+        hipLaunchKernelGGL(k_diag_sqrt<2>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
+        VP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_scale_to_bf16<2>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64, L.Abf);
+      } else {
+        hipLaunchKernelGGL(k_diag_sqrt<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
+        VP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_scale_to_bf16<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64, L.Abf);
+      }
+      VP_LAUNCH_CHECK();
+    } else if (l == 0) {
       if (!L.A32) L.A32 = dalloc<float>(na);
       convert(s, L.A64, L.A32, na);
     } else {
@@ -1026,7 +1056,7 @@ void bf16_copies(vp_ctx c, hipStream_t s) {
     const unsigned g = (unsigned)((L.nn + 255) / 256);
     if (L.B == 2)
       hipLaunchKernelGGL(k_scale_p<2>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
-                         (const double*)nullptr, (const double*)N.dsc64, L.P32);
+                         (const double*)(finest_bf16 ? L.dsc64 : nullptr), (const double*)N.dsc64, L.P32);
     else
       hipLaunchKernelGGL(k_scale_p<3>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          (const double*)L.dsc64, (const double*)N.dsc64, L.P32);
@@ -1035,7 +1065,7 @@ void bf16_copies(vp_ctx c, hipStream_t s) {
   Level& C = c->lev[c->nlev - 1];
   const int nd = C.B * (int)C.nn;
   if (!C.Ainv32) C.Ainv32 = dalloc<float>((size_t)nd * nd);
-  if (c->nlev == 1) {
+  if (c->nlev == 1 && !finest_bf16) {
     convert(s, C.Ainv64, C.Ainv32, (size_t)nd * nd);
   } else {
     hipLaunchKernelGGL(k_scale_dense, dim3((unsigned)(((size_t)nd * nd + 255) / 256)), dim3(256), 0, s, C.Ainv64, nd,
@@ -1129,8 +1159,8 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   else hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, C.Ainv64, nd);
   VP_LAUNCH_CHECK();
   // reduced-precision copies
-  if (precision == VP_PREC_FP32_BF16COARSE) {
-    bf16_copies(c, s);
+  if (precision == VP_PREC_FP32_BF16COARSE || precision == VP_PREC_BF16) {
+    bf16_copies(c, s, precision == VP_PREC_BF16);
   } else if (precision != VP_PREC_FP64) {
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
@@ -1245,8 +1275,9 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     if (L.B == 2) run(std::integral_constant<int, 2>(), double(), double(), L.A64, L.P64);
     else run(std::integral_constant<int, 3>(), double(), double(), L.A64, L.P64);
   } else {
-    const bool bf = c->amg_prec == VP_PREC_FP32_BF16COARSE && l > 0;
-    if (L.B == 2) run(std::integral_constant<int, 2>(), float(), float(), L.A32, L.P32);
+    const bool bf = (c->amg_prec == VP_PREC_FP32_BF16COARSE && l > 0) || c->amg_prec == VP_PREC_BF16;
+    if (L.B == 2 && bf) run(std::integral_constant<int, 2>(), __hip_bfloat16(), float(), L.Abf, L.P32);
+    else if (L.B == 2) run(std::integral_constant<int, 2>(), float(), float(), L.A32, L.P32);
     else if (bf) run(std::integral_constant<int, 3>(), __hip_bfloat16(), float(), L.Abf, L.P32);
     else run(std::integral_constant<int, 3>(), float(), float(), L.A32, L.P32);
   }
@@ -1268,6 +1299,14 @@ void amg_apply(vp_ctx c, const double* r, double* z) {
   } end_{c, prof_begin(c, VP_KID_VCYCLE)};
   if (c->amg_prec == VP_PREC_FP64) {
     vcycle_level<double>(c, 0, r, z);
+  } else if (c->amg_prec == VP_PREC_BF16) {
+    // finest level in the scaled variables: b^ = D^{-1/2} r, z = D^{-1/2} x^
+    hipLaunchKernelGGL(k_scale_cast_df, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, r, L.dsc64, (float*)L.b, n);
+    VP_LAUNCH_CHECK();
+    vcycle_level<float>(c, 0, (const float*)L.b, (float*)L.x);
+    hipLaunchKernelGGL(k_scale_cast_fd, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, (const float*)L.x, L.dsc64,
+                       z, n);
+    VP_LAUNCH_CHECK();
   } else {
     launch_cast(c->stream, r, (float*)L.b, n);
     // level-0 x must not alias L.b; the cycle writes L.x

@@ -275,7 +275,7 @@ void amg_setup(vp_ctx c, const vp_amg_opts& a) {
   require(c->have_K, VP_ESTATE, "no assembled operator");
   require(a.cheb_degree >= 1 && a.cheb_degree <= 16, VP_EINVAL, "cheb_degree out of range");
   require(a.max_coarse >= 8 && a.max_coarse <= 1024, VP_EINVAL, "max_coarse out of range");
-  require(a.precision >= 0 && a.precision <= 2, VP_EINVAL, "bad precision");
+  require(a.precision >= 0 && a.precision <= 3, VP_EINVAL, "bad precision");
   require(a.cheb_ratio > 1.0 && a.omega_scale > 0.0, VP_EINVAL, "bad smoother options");
   if (!c->amg_struct || c->max_coarse != a.max_coarse) amg_build_structure(c, c->lev[0].A64, a.max_coarse);
   c->cheb_degree = a.cheb_degree;
@@ -589,8 +589,12 @@ int vp_profile_read(vp_ctx c, int kid, double* total_ms, int* launches, double* 
     double b = 0.0;
     switch (kid) {
       case VP_KID_APPLY_FINE: b = nn * (20 * 8 + 2 * 16); break;
-      case VP_KID_CHEB_STEP0: b = f32 ? nn * (20 * 4 + 6 * 8) : nn * (20 * 8 + 6 * 16); break;
-      case VP_KID_STEN_RESID0: b = f32 ? nn * (20 * 4 + 3 * 8) : nn * (20 * 8 + 3 * 16); break;
+      case VP_KID_CHEB_STEP0:
+        b = c->amg_prec == VP_PREC_BF16 ? nn * (20 * 2 + 6 * 8) : f32 ? nn * (20 * 4 + 6 * 8) : nn * (20 * 8 + 6 * 16);
+        break;
+      case VP_KID_STEN_RESID0:
+        b = c->amg_prec == VP_PREC_BF16 ? nn * (20 * 2 + 3 * 8) : f32 ? nn * (20 * 4 + 3 * 8) : nn * (20 * 8 + 3 * 16);
+        break;
       case VP_KID_RESIDUAL: b = nn * 64 + nc * 16; break;
       case VP_KID_ASSEMBLE: b = nn * (32 + 160) + nc * (16 + 96); break;
       default: b = 0.0;

@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(_HERE, "libvp.so")
 VP_OK, VP_NOT_CONVERGED, VP_LINESEARCH_FAIL, VP_KRYLOV_MAXIT = 0, 1, 2, 3
 VP_EINVAL, VP_EHIP, VP_ENOMEM, VP_ESTATE, VP_ENONFINITE, VP_EBREAKDOWN = -1, -2, -3, -4, -5, -6
 VP_SVN, VP_STDN = 0, 1
-VP_PREC_FP64, VP_PREC_FP32, VP_PREC_FP32_BF16COARSE = 0, 1, 2
+VP_PREC_FP64, VP_PREC_FP32, VP_PREC_FP32_BF16COARSE, VP_PREC_BF16 = 0, 1, 2, 3
 VP_KRYLOV_FGMRES, VP_KRYLOV_FCG = 0, 1
 VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
 

@@ -131,7 +131,7 @@ def test_pi_update_and_init_parity(vp, nx, ny, seed):
 
 
 @pytest.mark.parametrize("method", ["fgmres", "fcg"])
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_krylov_solves_assembled_system(vp, method, prec):
     nx, ny, seed = 64, 48, 5
     w, prob, ctx = _case(vp, nx, ny, seed)
@@ -226,7 +226,7 @@ def test_vcycle_reduced_precision_close_to_fp64(vp):
     order of BF16 rounding.  Fresh contexts give all the same spectral estimates."""
     nx, ny, seed = 64, 48, 5
     outs = {}
-    for prec in (0, 1, 2):
+    for prec in (0, 1, 2, 3):
         w, prob, ctx = _case(vp, nx, ny, seed)
         v = O.newton_solve(prob, maxit=2).v
         ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
@@ -241,6 +241,8 @@ def test_vcycle_reduced_precision_close_to_fp64(vp):
         outs[prec] = _host(z).ravel()
     d32 = _relerr(outs[1], outs[0])
     dbf = _relerr(outs[2], outs[0])
-    print(f"[vcycle] fp32 vs fp64 {d32:.2e}  bf16-coarse vs fp64 {dbf:.2e}", flush=True)
+    dba = _relerr(outs[3], outs[0])
+    print(f"[vcycle] fp32 vs fp64 {d32:.2e}  bf16-coarse vs fp64 {dbf:.2e}  bf16-all vs fp64 {dba:.2e}", flush=True)
     assert d32 < 1e-4
     assert dbf < 5e-2
+    assert dba < 1e-1
