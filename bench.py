@@ -58,6 +58,48 @@ def cpu_baseline(n_sample: int, gpu_newton_its: int, n_full: int):
                 sample_seconds=t)
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+CALIB_READ_KIB, CALIB_WRITE_KIB = 2 << 20, 1 << 20   # the triad of kernel_sequence
+
+
+def counter_traffic(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed FETCH_SIZE and
+    WRITE_SIZE summaries, each scaled by the counter's reading for the calibration
+    triad; None if a summary or the kernel is missing."""
+    def table(fname):
+        path = os.path.join(PROFILES, fname)
+        if not os.path.exists(path):
+            return None
+        rows = {}
+        for line in open(path):
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.rsplit(None, 3)
+            if len(parts) == 4 and parts[1].isdigit():
+                try:
+                    rows[parts[0].strip()] = float(parts[2])
+                except ValueError:
+                    pass
+        return rows
+    fetch = table("vp_sharp_2048_kernels_fetch_size.txt")
+    write = table("vp_sharp_2048_kernels_write_size.txt")
+    if not fetch or not write or kernel_name not in fetch or kernel_name not in write:
+        return None
+    cal_f = max(v for k, v in fetch.items() if "elementwise" in k)
+    cal_w = max(v for k, v in write.items() if "elementwise" in k)
+    return 1024.0 * (fetch[kernel_name] * CALIB_READ_KIB / cal_f + write[kernel_name] * CALIB_WRITE_KIB / cal_w)
+
+
+KERNEL_NAMES = {  # profiled kernel id -> kernel name in the rocprofv3 summaries
+    ("cheb_step0", "fp64"): "k_cheb_step<2, double, double>",
+    ("cheb_step0", "fp32"): "k_cheb_step<2, float, float>",
+    ("sten_resid0", "fp64"): "k_sten_resid<2, double, double>",
+    ("sten_resid0", "fp32"): "k_sten_resid<2, float, float>",
+    ("apply_fine", "fp64"): "k_apply_fine",
+    ("apply_fine", "fp32"): "k_apply_fine",
+}
+
+
 def kernel_sequence(args, ctx, v, pi, torch, vp):
     """Short fixed launch sequence for profiler passes: three Newton steps (to get
     a non-trivial operator), then per path 10 V-cycles and 10 FP64 operator
@@ -77,11 +119,14 @@ def kernel_sequence(args, ctx, v, pi, torch, vp):
             ctx.vp_operator_apply(r, z)
         torch.cuda.synchronize()
         log(f"{path}: 10 V-cycles and 10 operator products done")
-    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
+    # calibration for the byte counters: a triad of known size (reads 2 GiB,
+    # writes 1 GiB), the largest elementwise dispatch of this sequence
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    torch.add(a, b, alpha=0.5, out=c)
     torch.cuda.synchronize()
-    log("calibration copy of 1 GiB done")
+    log("calibration triad (2 GiB read, 1 GiB written) done")
     print(json.dumps({"mode": "kernels", "paths": args.paths, "n": args.n}), flush=True)
 
 
@@ -190,8 +235,10 @@ def main():
     single = {k: d for k, d in R["kernels"].items() if k != "vcycle" and d["bytes_per_launch"] > 0}
     dom = max(single, key=lambda k: single[k]["total_ms"])
     D = single[dom]
-    roof = dict(kernel=dom, bound="hbm", achieved=D["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=D["gbs"] / HBM_PEAK_GBS, traffic=None,
+    prec_kind = "fp64" if best == "fp64" else "fp32"
+    kname = KERNEL_NAMES.get((dom, prec_kind))
+    roof = dict(kernel=kname or dom, bound="hbm", achieved=D["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=D["gbs"] / HBM_PEAK_GBS, traffic=counter_traffic(kname) if kname else None,
                 bytes_per_launch=D["bytes_per_launch"], avg_us=D["avg_us"])
     spmv = R["kernels"].get("apply_fine")
     out = {
