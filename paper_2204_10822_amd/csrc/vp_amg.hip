@@ -229,42 +229,83 @@ k_apply_fine(const double* __restrict__ A, size_t nn, int nxn, int nyn, const do
   }
 }
 
-// Chebyshev first step: d = D^{-1} src * inv_theta; x = d (zero start) or x += d.
-// copy_to_r: also r = src (pre-smoothing from a zero initial guess).
+// Chebyshev first step: d = D^{-1} src * inv_theta.  x (if given) = d, or x += d
+// with add; r (if given) = src.
 template <int B, typename TM, typename TV>
 __global__ void __launch_bounds__(kBlock)
 k_cheb_first(const TM* __restrict__ A, size_t nn, const TV* __restrict__ src, TV* __restrict__ r,
-             TV* __restrict__ d, TV* __restrict__ x, typename Acc<TV>::type inv_theta, int add,
-             int copy_to_r) {
+             TV* __restrict__ d, TV* __restrict__ x, typename Acc<TV>::type inv_theta, int add) {
   using TA = typename Acc<TV>::type;
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
   if (n >= nn) return;
-  TA D[B][B], Di[B][B], s[B];
+  TA v[B * B], D[B][B], Di[B][B], sv[B], dk[B];
+  load_raw<B>(A + aidx(B, nn, 0, n, 0, 0), v);
 #pragma unroll
   for (int rr = 0; rr < B; ++rr)
 #pragma unroll
-    for (int c = 0; c < B; ++c) D[rr][c] = (TA)ld(A + aidx(B, nn, 0, n, rr, c));
+    for (int c = 0; c < B; ++c) D[rr][c] = v[rr * B + c];
   invert_block<B>(D, Di);
-#pragma unroll
-  for (int k = 0; k < B; ++k) s[k] = (TA)src[n * B + k];
+  load_node<B>(src, n, sv);
 #pragma unroll
   for (int k = 0; k < B; ++k) {
-    TA dk = TA(0);
+    TA t = TA(0);
 #pragma unroll
-    for (int c = 0; c < B; ++c) dk += Di[k][c] * s[c];
-    dk *= inv_theta;
-    d[n * B + k] = (TV)dk;
-    x[n * B + k] = add ? (TV)((TA)x[n * B + k] + dk) : (TV)dk;
-    if (copy_to_r) r[n * B + k] = (TV)s[k];
+    for (int c = 0; c < B; ++c) t += Di[k][c] * sv[c];
+    dk[k] = t * inv_theta;
   }
+  store_node<B>(d, n, dk);
+  if (x) {
+    TA xn[B];
+    if (add) {
+      load_node<B>(x, n, xn);
+#pragma unroll
+      for (int k = 0; k < B; ++k) xn[k] += dk[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < B; ++k) xn[k] = dk[k];
+    }
+    store_node<B>(x, n, xn);
+  }
+  if (r) store_node<B>(r, n, sv);
 }
 
-// Chebyshev step: r -= A dp; dn = cdd dp + cdr D^{-1} r; x += dn
+// Residual and first Chebyshev step of post-smoothing in one sweep:
+// r = b - A x, d = D^{-1} r * inv_theta.  x itself is not updated here (its
+// neighbours are still being read); the following step adds d (xmode 1).
+template <int B, typename TM, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_resid_first(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ x,
+              const TV* __restrict__ b, TV* __restrict__ r, TV* __restrict__ d,
+              typename Acc<TV>::type inv_theta) {
+  using TA = typename Acc<TV>::type;
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  TA y[B], D[B][B], Di[B][B], rn[B], dk[B];
+  stencil_row<B>(A, nn, nxn, nyn, i, j, x, y, D);
+  invert_block<B>(D, Di);
+  load_node<B>(b, n, rn);
+#pragma unroll
+  for (int k = 0; k < B; ++k) rn[k] -= y[k];
+  store_node<B>(r, n, rn);
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    TA t = TA(0);
+#pragma unroll
+    for (int c = 0; c < B; ++c) t += Di[k][c] * rn[c];
+    dk[k] = t * inv_theta;
+  }
+  store_node<B>(d, n, dk);
+}
+
+// Chebyshev step: r = rin - A dp; dn = cdd dp + cdr D^{-1} r;
+//   xmode 0: x += dn;  1: x = (x + dp) + dn;  2: x = dp + dn (x not read).
+// rin may equal rout.
 template <int B, typename TM, typename TV>
 __global__ void __launch_bounds__(kBlock)
 k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ dp,
-            TV* __restrict__ r, TV* __restrict__ dn, TV* __restrict__ x, typename Acc<TV>::type cdd,
-            typename Acc<TV>::type cdr) {
+            const TV* rin, TV* rout, TV* __restrict__ dn, TV* __restrict__ x, typename Acc<TV>::type cdd,
+            typename Acc<TV>::type cdr, int xmode) {
   using TA = typename Acc<TV>::type;
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
   if (n >= nn) return;
@@ -272,12 +313,21 @@ k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __r
   TA y[B], D[B][B], Di[B][B], rn[B], dpn[B], xn[B], dk[B];
   stencil_row<B>(A, nn, nxn, nyn, i, j, dp, y, D);
   invert_block<B>(D, Di);
-  load_node<B>(r, n, rn);
+  load_node<B>(rin, n, rn);
   load_node<B>(dp, n, dpn);
-  load_node<B>(x, n, xn);
+  if (xmode == 2) {
+#pragma unroll
+    for (int k = 0; k < B; ++k) xn[k] = dpn[k];
+  } else {
+    load_node<B>(x, n, xn);
+    if (xmode == 1) {
+#pragma unroll
+      for (int k = 0; k < B; ++k) xn[k] += dpn[k];
+    }
+  }
 #pragma unroll
   for (int k = 0; k < B; ++k) rn[k] -= y[k];
-  store_node<B>(r, n, rn);
+  store_node<B>(rout, n, rn);
 #pragma unroll
   for (int k = 0; k < B; ++k) {
     TA t = TA(0);
@@ -291,10 +341,12 @@ k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __r
 }
 
 // ---------------------------------------------------------------------------
-// transfers: P stored per fine node as 4 slots x (B x 3), plane-major
-//   P[pidx(B, slot, node, r, c)]  (node-major: a node's 4 slots are contiguous)
+// transfers: P stored per fine node as 4 slots x (B x 3), one plane per component
+//   P[pidx(B, nn, slot, node, r, c)]
 // slot = sx + 2 sy, sx = 0: own aggregate in x, 1: the adjacent one (agg_other)
 // ---------------------------------------------------------------------------
+// One thread per coarse node; its window spans at most 6 fine nodes per
+// direction (the aggregate, one node on each side, a last aggregate of up to 5).
 template <int B, typename TP, typename TV>
 __global__ void __launch_bounds__(kBlock)
 k_restrict(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
@@ -305,21 +357,25 @@ k_restrict(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int n
   const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
   const int i0 = max(3 * Ix - 1, 0), i1 = min(agg_last(Ix, nxn, ncx) + 1, nxn - 1);
   const int j0 = max(3 * Iy - 1, 0), j1 = min(agg_last(Iy, nyn, ncy) + 1, nyn - 1);
+  int sxs[6];
+#pragma unroll
+  for (int di = 0; di < 6; ++di) sxs[di] = i0 + di <= i1 ? slot1(i0 + di, nxn, ncx, Ix) : -1;
   TA acc[3] = {TA(0), TA(0), TA(0)};
   for (int j = j0; j <= j1; ++j) {
     const int sy = slot1(j, nyn, ncy, Iy);
     if (sy < 0) continue;
-    for (int i = i0; i <= i1; ++i) {
-      const int sx = slot1(i, nxn, ncx, Ix);
+#pragma unroll
+    for (int di = 0; di < 6; ++di) {
+      const int sx = sxs[di];
       if (sx < 0) continue;
       const int s = sx + 2 * sy;
-      const size_t n = (size_t)j * nxn + i;
+      const size_t n = (size_t)j * nxn + i0 + di;
+      TA rv[B];
+      load_node<B>(r, n, rv);
 #pragma unroll
-      for (int rr = 0; rr < B; ++rr) {
-        const TA rv = (TA)r[n * B + rr];
+      for (int rr = 0; rr < B; ++rr)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += (TA)ld(P + pidx(B, s, n, rr, c)) * rv;
-      }
+        for (int c = 0; c < 3; ++c) acc[c] += (TA)ld(P + pidx(B, nn, s, n, rr, c)) * rv[rr];
     }
   }
 #pragma unroll
@@ -350,7 +406,7 @@ k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, in
 #pragma unroll
     for (int rr = 0; rr < B; ++rr)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[rr] += (TA)ld(P + pidx(B, s, n, rr, c)) * xj[c];
+      for (int c = 0; c < 3; ++c) acc[rr] += (TA)ld(P + pidx(B, nn, s, n, rr, c)) * xj[c];
   }
 #pragma unroll
   for (int rr = 0; rr < B; ++rr) x[n * B + rr] = (TV)acc[rr];
@@ -616,7 +672,7 @@ k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
         double val = -omega * t;
         if (s == 0) val += Ptent[(size_t)(r * 3 + c) * nn + n];
         if (Jx < 0 || Jy < 0) val = 0.0;
-        P[pidx(B, s, n, r, c)] = val;
+        P[pidx(B, nn, s, n, r, c)] = val;
       }
   }
 }
@@ -660,7 +716,7 @@ k_galerkin(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) PI[r][c] = P[pidx(B, sI, n, r, c)];
+      for (int c = 0; c < 3; ++c) PI[r][c] = P[pidx(B, nn, sI, n, r, c)];
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
       const int ii = i + kDI[d], jj = j + kDJ[d];
@@ -689,7 +745,7 @@ k_galerkin(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
         for (int k = 0; k < B; ++k)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double pv = P[pidx(B, sJ, m, k, c)];
+            const double pv = P[pidx(B, nn, sJ, m, k, c)];
 #pragma unroll
             for (int a = 0; a < 3; ++a) acc[t][a][c] += Y[a][k] * pv;
           }
@@ -773,7 +829,7 @@ __global__ void k_scale_p(const double* __restrict__ P, size_t nn, int nxn, int 
     const size_t J = ok ? (size_t)Jy * ncx + Jx : 0;
     for (int r = 0; r < B; ++r)
       for (int c = 0; c < 3; ++c) {
-        const size_t k = pidx(B, s, n, r, c);
+        const size_t k = pidx(B, nn, s, n, r, c);
         const double fr = dsc_f ? dsc_f[n * B + r] : 1.0;
         Ps[k] = ok ? (float)(fr * P[k] / dsc_c[J * 3 + c]) : 0.0f;
       }
@@ -1211,9 +1267,12 @@ void sten_resid(vp_ctx c, int l, const Level& L, const TM* A, const TV* x, const
   prof_end(c, pr);
 }
 
+// Chebyshev smoothing of degree `degree` on [lmax/ratio, lmax] with the block
+// diagonal as preconditioner.  pre: x = 0 on entry and r = b - A x on exit (for
+// the restriction); otherwise x is updated in place from the residual of b.
 template <int B, typename TM, typename TV>
-void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* src, TV* x, bool zero_start,
-            int degree, double ratio) {
+void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bool pre, int degree,
+            double ratio) {
   hipStream_t s = c->stream;
   using TA = typename Acc<TV>::type;
   TV* r = (TV*)L.r;
@@ -1222,21 +1281,37 @@ void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* src, TV* x, 
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
-  hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A, L.nn, src, r,
-                     d[0], x, (TA)(1.0 / theta), zero_start ? 0 : 1, zero_start ? 1 : 0);
-  VP_LAUNCH_CHECK();
+  const unsigned g = grid_for(L.nn);
+  const TA inv_theta = (TA)(1.0 / theta);
+  if (pre) {
+    // zero initial guess: the residual starts at b, the first correction is D^{-1} b / theta
+    hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, b,
+                       degree == 1 ? r : nullptr, d[0], degree == 1 ? x : nullptr, inv_theta, 0);
+    VP_LAUNCH_CHECK();
+  } else if (degree == 1) {
+    sten_resid<B>(c, l, L, A, (const TV*)x, b, r);
+    hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, (const TV*)r,
+                       (TV*)nullptr, d[0], x, inv_theta, 1);
+    VP_LAUNCH_CHECK();
+  } else {
+    hipLaunchKernelGGL((k_resid_first<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
+                       (const TV*)x, b, r, d[0], inv_theta);
+    VP_LAUNCH_CHECK();
+  }
   for (int k = 1; k < degree; ++k) {
     const double rn = 1.0 / (2.0 * sigma - rho);
     const double cdd = rn * rho, cdr = 2.0 * rn / delta;
-    const int pr = l == 0 ? prof_begin(c, VP_KID_CHEB_STEP0) : -1;
-    hipLaunchKernelGGL((k_cheb_step<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A, L.nn, L.nxn,
-                       L.nyn, d[(k - 1) & 1], r, d[k & 1], x, (TA)cdd, (TA)cdr);
+    const int xmode = k > 1 ? 0 : pre ? 2 : 1;
+    const TV* rin = (pre && k == 1) ? b : (const TV*)r;
+    const int pr = (l == 0 && xmode == 0) ? prof_begin(c, VP_KID_CHEB_STEP0) : -1;
+    hipLaunchKernelGGL((k_cheb_step<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
+                       (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], x, (TA)cdd, (TA)cdr, xmode);
     VP_LAUNCH_CHECK();
     prof_end(c, pr);
     rho = rn;
   }
-  // leave r = b - A x after pre-smoothing (used by the restriction)
-  if (zero_start) sten_resid<B>(c, l, L, A, (const TV*)d[(degree - 1) & 1], (const TV*)r, r);
+  // r = b - A x after pre-smoothing (r holds the residual before the last correction)
+  if (pre) sten_resid<B>(c, l, L, A, (const TV*)d[(degree - 1) & 1], (const TV*)r, r);
 }
 
 template <typename TV>
@@ -1268,8 +1343,7 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     hipLaunchKernelGGL((k_prolong_add<B, TP, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
                        L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
     VP_LAUNCH_CHECK();
-    sten_resid<B>(c, l, L, A, (const TV*)x, b, (TV*)L.r);
-    smooth<B, TM, TV>(c, l, L, A, (const TV*)L.r, x, false, c->cheb_degree, c->cheb_ratio);
+    smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
   };
   if constexpr (std::is_same<TV, double>::value) {
     if (L.B == 2) run(std::integral_constant<int, 2>(), double(), double(), L.A64, L.P64);
@@ -1313,6 +1387,44 @@ void amg_apply(vp_ctx c, const double* r, double* z) {
     vcycle_level<float>(c, 0, (const float*)L.b, (float*)L.x);
     launch_cast(c->stream, (const float*)L.x, z, n);
   }
+}
+
+// FP32 input buffer of the V-cycle (and the finest level's Jacobi scaling when
+// the V-cycle runs in scaled variables), or null for an FP64 V-cycle: callers
+// that produce the residual can write it there directly and pass input_ready.
+float* amg_input32(vp_ctx c, const double** dsc) {
+  if (dsc) *dsc = c->amg_prec == VP_PREC_BF16 ? c->lev[0].dsc64 : nullptr;
+  return c->amg_prec == VP_PREC_FP64 ? nullptr : (float*)c->lev[0].b;
+}
+
+// z = M^{-1} r followed, in the same pass as the V-cycle's output conversion, by
+// the per-workgroup partials of z.r and (q given) z.q.  Returns the number of
+// workgroups (the partials hold 1 or 2 values each).
+int amg_apply_dots(vp_ctx c, const double* r, const double* q, double* z, bool input_ready) {
+  if (!c->amg_ready) throw Error(VP_ESTATE, "AMG not set up");
+  Level& L = c->lev[0];
+  const size_t n = (size_t)L.B * L.nn;
+  hipStream_t s = c->stream;
+  const int pr = prof_begin(c, VP_KID_VCYCLE);
+  int nb;
+  if (c->amg_prec == VP_PREC_FP64) {
+    vcycle_level<double>(c, 0, r, z);
+    nb = launch_out_dots<double>(s, z, nullptr, z, r, q, n, c->partials);
+  } else {
+    const bool scaled = c->amg_prec == VP_PREC_BF16;
+    if (!input_ready) {
+      if (scaled) {
+        hipLaunchKernelGGL(k_scale_cast_df, dim3(grid_for(n)), dim3(kBlock), 0, s, r, L.dsc64, (float*)L.b, n);
+        VP_LAUNCH_CHECK();
+      } else {
+        launch_cast(s, r, (float*)L.b, n);
+      }
+    }
+    vcycle_level<float>(c, 0, (const float*)L.b, (float*)L.x);
+    nb = launch_out_dots<float>(s, (const float*)L.x, scaled ? L.dsc64 : nullptr, z, r, q, n, c->partials);
+  }
+  prof_end(c, pr);
+  return nb;
 }
 
 void launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials) {

@@ -10,6 +10,8 @@ void amg_free(vp_ctx c);
 void amg_build_structure(vp_ctx c, double* K, int max_coarse);
 void amg_setup_numeric(vp_ctx c, int precision, double omega_scale);
 void amg_apply(vp_ctx c, const double* r, double* z);
+int amg_apply_dots(vp_ctx c, const double* r, const double* q, double* z, bool input_ready);
+float* amg_input32(vp_ctx c, const double** dsc);
 void amg_reset_estimates(vp_ctx c);
 }  // namespace vp
 
@@ -234,16 +236,17 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
   double rel = norm2(c, r, n) / bnorm;
   int it = 0;
   if (rel > o.rtol) {
-    amg_apply(c, r, z);
-    launch_mdot(s, r, n, 1, z, n, c->partials);  // r.z
-    finish(c, kRedBlocks, 1, 0);
+    const double* dsc = nullptr;
+    float* r32 = amg_input32(c, &dsc);  // the update writes the V-cycle's FP32 input directly
+    int nb = amg_apply_dots(c, r, nullptr, z, false);  // r.z
+    finish(c, nb, 1, 0);
     launch_fcg_dir(s, c->dscal, z, p, n, 1);
     while (it < o.maxit) {
       const int pr = prof_begin(c, VP_KID_APPLY_FINE);
       launch_apply_fine(s, c->lev[0], p, q, c->partials);  // q = K p, p.q
       prof_end(c, pr);
       finish(c, (int)grid_for(c->lev[0].nn), 1, 1);
-      launch_fcg_update(s, c->dscal, x, r, p, q, n, c->partials);
+      launch_fcg_update(s, c->dscal, x, r, p, q, n, c->partials, r32, dsc);
       finish(c, kRedBlocks, 1, 4);
       fetch(c, 0, 5);
       ++it;
@@ -252,9 +255,8 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
       if (c->hscal[1] <= 0.0) throw Error(VP_EBREAKDOWN, "FCG breakdown: p.Kp <= 0");
       rel = std::sqrt(std::max(c->hscal[4], 0.0)) / bnorm;
       if (rel <= o.rtol) break;
-      amg_apply(c, r, z);
-      launch_mdot(s, r, n, 2, z, n, c->partials);  // z.r, z.q
-      finish(c, kRedBlocks, 2, 5);
+      nb = amg_apply_dots(c, r, q, z, r32 != nullptr);  // z.r, z.q
+      finish(c, nb, 2, 5);
       launch_fcg_dir(s, c->dscal, z, p, n, 0);
     }
   }

@@ -228,11 +228,12 @@ void launch_scale_copy(hipStream_t s, const double* x, const double* scal, int i
 }
 
 // flexible CG, dev = [rz, pq, ...]: alpha = rz/pq; x += alpha p; r -= alpha q;
-// partials: r.r
+// partials: r.r.  r32 (optional): the new r in FP32 for the V-cycle, divided by
+// dsc if that is given.
 __global__ void __launch_bounds__(kBlock)
 k_fcg_update(const double* __restrict__ dev, double* __restrict__ x, double* __restrict__ r,
              const double* __restrict__ p, const double* __restrict__ q, size_t n,
-             double* __restrict__ partials) {
+             double* __restrict__ partials, float* __restrict__ r32, const double* __restrict__ dsc) {
   __shared__ double lds[16];
   const double alpha = dev[1] != 0.0 ? dev[0] / dev[1] : 0.0;
   double a[1] = {0.0};
@@ -240,6 +241,7 @@ k_fcg_update(const double* __restrict__ dev, double* __restrict__ x, double* __r
     x[e] = fma(alpha, p[e], x[e]);
     const double re = fma(-alpha, q[e], r[e]);
     r[e] = re;
+    if (r32) r32[e] = (float)(dsc ? re / dsc[e] : re);
     a[0] = fma(re, re, a[0]);
   }
   block_sum<1>(a, lds);
@@ -247,10 +249,46 @@ k_fcg_update(const double* __restrict__ dev, double* __restrict__ x, double* __r
 }
 
 void launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, const double* p,
-                       const double* q, size_t n, double* partials) {
-  hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kBlock), 0, s, dev, x, r, p, q, n, partials);
+                       const double* q, size_t n, double* partials, float* r32, const double* dsc) {
+  hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kBlock), 0, s, dev, x, r, p, q, n, partials, r32,
+                     dsc);
   VP_LAUNCH_CHECK();
 }
+
+// The V-cycle's output to the Krylov solver: z = x (widened, divided by dsc if
+// given; z may alias x), with per-workgroup partials of z.r and, if q is given,
+// z.q (partials[block*K + k], K = 1 or 2).
+template <typename TX>
+__global__ void __launch_bounds__(kBlock)
+k_out_dots(const TX* x, const double* __restrict__ dsc, double* z, const double* __restrict__ r,
+           const double* __restrict__ q, size_t n, double* __restrict__ partials) {
+  __shared__ double lds[32];
+  double a[2] = {0.0, 0.0};
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double ze = (double)x[e];
+    if (dsc) ze /= dsc[e];
+    if ((const void*)z != (const void*)x) z[e] = ze;
+    a[0] = fma(ze, r[e], a[0]);
+    if (q) a[1] = fma(ze, q[e], a[1]);
+  }
+  block_sum<2>(a, lds);
+  if (threadIdx.x == 0) {
+    partials[(size_t)blockIdx.x * (q ? 2 : 1)] = a[0];
+    if (q) partials[(size_t)blockIdx.x * 2 + 1] = a[1];
+  }
+}
+
+template <typename TX>
+int launch_out_dots(hipStream_t s, const TX* x, const double* dsc, double* z, const double* r, const double* q,
+                    size_t n, double* partials) {
+  hipLaunchKernelGGL((k_out_dots<TX>), dim3(kDotBlocks), dim3(kBlock), 0, s, x, dsc, z, r, q, n, partials);
+  VP_LAUNCH_CHECK();
+  return kDotBlocks;
+}
+template int launch_out_dots<float>(hipStream_t, const float*, const double*, double*, const double*,
+                                    const double*, size_t, double*);
+template int launch_out_dots<double>(hipStream_t, const double*, const double*, double*, const double*,
+                                     const double*, size_t, double*);
 
 // p = z + beta p with beta = -dev[6]/dev[1] (flexible CG: beta = -alpha z.q / r.z_old,
 // alpha = r.z_old / p.q); first: p = z.  Thread 0 of workgroup 0 moves the new r.z

@@ -37,6 +37,7 @@ struct Error : std::runtime_error {
 
 constexpr int kBlock = 256;     // threads per workgroup for node/vector kernels
 constexpr int kRedBlocks = 512; // workgroups of a grid-stride reduction
+constexpr int kDotBlocks = 2048; // workgroups of the V-cycle output + dot products
 constexpr int kMaxLevels = 16;
 constexpr int kMaxRestart = 64;
 
@@ -105,10 +106,11 @@ inline unsigned grid_for(size_t n, int block = kBlock) {
 __host__ __device__ __forceinline__ size_t aidx(int B, size_t nn, int blk, size_t n, int r, int c) {
   return (((size_t)blk * nn + n) * B + r) * B + c;
 }
-// Smoothed prolongator: per fine node 4 slots x (B x 3), node-major:
-//   P[pidx(B, s, n, r, c)] = ((n * 4 + s) * B + r) * 3 + c
-__host__ __device__ __forceinline__ size_t pidx(int B, int s, size_t n, int r, int c) {
-  return (((size_t)n * 4 + s) * B + r) * 3 + c;
+// Smoothed prolongator: per fine node 4 slots x (B x 3), one plane per
+// (slot, row, column) component so consecutive nodes are consecutive in memory:
+//   P[pidx(B, nn, s, n, r, c)] = ((s * B + r) * 3 + c) * nn + n
+__host__ __device__ __forceinline__ size_t pidx(int B, size_t nn, int s, size_t n, int r, int c) {
+  return (size_t)((s * B + r) * 3 + c) * nn + n;
 }
 
 // bf16 storage helpers (round to nearest even)
@@ -260,9 +262,13 @@ void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y,
 void launch_scale_copy(hipStream_t s, const double* x, const double* scal, int invert,
                        double* y, size_t n);
 void launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, const double* p,
-                       const double* q, size_t n, double* partials);
+                       const double* q, size_t n, double* partials, float* r32 = nullptr,
+                       const double* dsc = nullptr);
 void launch_fcg_dir(hipStream_t s, double* dev, const double* z, double* p, size_t n, int first);
 void launch_cast(hipStream_t s, const double* x, float* y, size_t n);
+template <typename TX>
+int launch_out_dots(hipStream_t s, const TX* x, const double* dsc, double* z, const double* r, const double* q,
+                    size_t n, double* partials);
 void launch_cast(hipStream_t s, const float* x, double* y, size_t n);
 void launch_fill(hipStream_t s, double* x, double v, size_t n);
 
