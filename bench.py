@@ -23,7 +23,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16+learned": 2, "bf16all": 3, "bf16all+learned": 3}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16+learned": 2, "bf16all": 3, "bf16all+learned": 3,
+        "fp16": 4, "fp16+learned": 4, "fp16all": 5, "fp16all+learned": 5}
 METRIC = "time-to-1e-8 residual, 2048^2 mesh: plain FP64 vs mixed+learned; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak
@@ -137,7 +138,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--paths", default="fp64,fp32,bf16,bf16+learned",
-                    help="comma list of fp64, fp32, bf16, bf16+learned, bf16all, bf16all+learned")
+                    help="comma list of fp64, fp32, bf16, bf16+learned, bf16all, bf16all+learned, fp16, fp16+learned, fp16all, fp16all+learned")
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels"],
@@ -252,7 +253,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f64+f32"}.get(best, "f64+f32+bf16"),
+        "dtype": {"fp64": "f64", "fp32": "f64+f32"}.get(best, "f64+f32+fp16+bf16" if best.startswith("fp16")
+                                                        else "f64+f32+bf16"),
         "data": "synthetic",
         "config": {"workload": w.name, "mesh": f"{n}x{n} Q1", "unknowns": 2 * nn,
                    "tol": 1e-8, "path": best, "newton_its": R["newton"], "krylov_its": R["krylov"]},

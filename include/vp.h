@@ -70,7 +70,8 @@ enum {
   VP_EBREAKDOWN = -6       /* Krylov breakdown (indefinite or singular operator)    */
 };
 enum { VP_SVN = 0, VP_STDN = 1 };                         /* linearisation          */
-enum { VP_PREC_FP64 = 0, VP_PREC_FP32 = 1, VP_PREC_FP32_BF16COARSE = 2, VP_PREC_BF16 = 3 };
+enum { VP_PREC_FP64 = 0, VP_PREC_FP32 = 1, VP_PREC_FP32_BF16COARSE = 2, VP_PREC_BF16 = 3,
+       VP_PREC_FP16_BF16COARSE = 4, VP_PREC_FP16 = 5 };
 enum { VP_KRYLOV_FGMRES = 0, VP_KRYLOV_FCG = 1 };
 enum { VP_LS_ENERGY = 0, VP_LS_RESIDUAL = 1 };
 
@@ -122,7 +123,9 @@ typedef struct {
   int max_coarse;        /* coarsest level dof bound (<= 1024)                     */
   int precision;         /* VP_PREC_*: V-cycle arithmetic and operator storage:
                             FP64; FP32; FP32 finest + BF16 Jacobi-scaled coarse levels;
-                            BF16 Jacobi-scaled on every level (FP32 arithmetic)      */
+                            BF16 Jacobi-scaled on every level (FP32 arithmetic);
+                            FP16 Jacobi-scaled finest + BF16 Jacobi-scaled coarse;
+                            FP16 Jacobi-scaled on every level                      */
   double cheb_ratio;     /* smoothing interval [lmax/ratio, lmax]                  */
   double omega_scale;    /* prolongator damping scale (1 = 4/(3 lmax))             */
 } vp_amg_opts;
@@ -131,6 +134,19 @@ int vp_amg_setup(vp_ctx ctx, const vp_amg_opts* opts);
 int vp_amg_apply(vp_ctx ctx, const double* r, double* z);
 /* Number of AMG levels (host out) and their node grids (host arrays of >= 16). */
 int vp_amg_info(vp_ctx ctx, int* levels, int* nxn, int* nyn, int* dofs_per_node);
+/* Copy AMG level `level` (0 = finest) to device buffers, for inspection.
+ *  A (nullable): the level's FP64 operator, 5*B*B*nn doubles in the layout of
+ *    vp_operator_export with B x B blocks (B = dofs per node and nn = nxn*nyn
+ *    from vp_amg_info).
+ *  P (nullable; not on the coarsest level): the smoothed prolongator to level+1,
+ *    12*B*nn doubles, P[((s*B + r)*3 + c)*nn + n] = entry (fine dof r of node n,
+ *    coarse dof c) for the coarse node in slot s = sx + 2*sy.  Along x, sx = 0
+ *    names the aggregate holding the node (aggregates are runs of 3 nodes, the
+ *    last run 3..5) and sx = 1 the neighbouring aggregate that a run's first or
+ *    last node also touches; the same along y.  Absent slots hold 0.
+ * Asynchronous on the context's stream.  VP_ESTATE before vp_amg_setup; VP_EINVAL
+ * for a level out of range or P asked for on the coarsest level. */
+int vp_amg_export(vp_ctx ctx, int level, double* A, double* P);
 
 /* Krylov solve K x = b with the last assembled operator and AMG (Sec. 5.4):
  * FGMRES(restart) right-preconditioned with classical Gram-Schmidt applied twice,

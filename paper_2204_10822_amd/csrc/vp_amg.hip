@@ -59,6 +59,10 @@ __device__ __forceinline__ void load_raw(const TM* __restrict__ p, TA (&v)[B * B
     const uint2 t = *reinterpret_cast<const uint2*>(p);   // 4 BF16 = 8 bytes
     v[0] = (TA)__uint_as_float(t.x << 16); v[1] = (TA)__uint_as_float(t.x & 0xffff0000u);
     v[2] = (TA)__uint_as_float(t.y << 16); v[3] = (TA)__uint_as_float(t.y & 0xffff0000u);
+  } else if constexpr (B == 2 && std::is_same<TM, _Float16>::value) {
+    typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+    const half4 t = *reinterpret_cast<const half4*>(p);   // 4 FP16 = 8 bytes
+    v[0] = (TA)t.x; v[1] = (TA)t.y; v[2] = (TA)t.z; v[3] = (TA)t.w;
   } else if constexpr (B == 2 && std::is_same<TM, double>::value) {
     const double2 t0 = reinterpret_cast<const double2*>(p)[0];
     const double2 t1 = reinterpret_cast<const double2*>(p)[1];
@@ -678,18 +682,73 @@ k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
 }
 
 // Galerkin coarse operator Ac = P^T A P in the 5-block symmetric storage (3x3
-// blocks).  One wavefront per coarse node I: lane l takes fine node l of the
-// (<= 7 x 7) window that holds the support of I's prolongator columns, adds its
-// terms P(i,I)^T A(i,k) P(k,J) for its 9 stencil neighbours k and the 5 stored
-// targets J, and the 45 entries are summed across the wave (fixed order).
+// blocks), in two coalesced passes.
+//
+// Pass 1 (one thread per fine node i): W(i, J) = sum_k A(i,k) P(k,J) for the
+// coarse nodes J = agg(i) + (qx-1, qy-1), q = qy*3 + qx in 0..8 (A P vanishes for
+// every other J: the prolongator columns of k's neighbours reach at most one
+// aggregate further).  W[((q*B + r)*3 + c)*nn + i], zero where J is absent.
 template <int B>
-__global__ void __launch_bounds__(256)
-k_galerkin(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
-           const double* __restrict__ P, double* __restrict__ Ac) {
+__global__ void __launch_bounds__(kBlock)
+k_galerkin_ap(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
+              const double* __restrict__ P, double* __restrict__ W) {
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  const int ax = agg_of(i, ncx), ay = agg_of(j, ncy);
+  double w[9][B][3];
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[q][r][c] = 0.0;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const int ii = i + kDI[d], jj = j + kDJ[d];
+    if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+    double blk[B][B];
+    load_block<B>(A, nn, nxn, i, j, d, blk);
+    const size_t m = (size_t)jj * nxn + ii;
+#pragma unroll
+    for (int qy = 0; qy < 3; ++qy) {
+      const int sy = slot1(jj, nyn, ncy, ay + qy - 1);
+      if (sy < 0) continue;
+#pragma unroll
+      for (int qx = 0; qx < 3; ++qx) {
+        const int sx = slot1(ii, nxn, ncx, ax + qx - 1);
+        if (sx < 0) continue;
+        const int sl = sx + 2 * sy;
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double pv = P[pidx(B, nn, sl, m, k, c)];
+#pragma unroll
+            for (int r = 0; r < B; ++r) w[qy * 3 + qx][r][c] += blk[r][k] * pv;
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) W[(size_t)((q * B + r) * 3 + c) * nn + n] = w[q][r][c];
+}
+
+// Pass 2 (one thread per coarse node I): Ac(I, J_t) = sum over the fine nodes i of
+// I's prolongator support of P(i,I)^T W(i, J_t) for the 5 stored targets
+// J_t = I + {(0,0), (1,0), (0,1), (1,1), (-1,1)}; the diagonal block is
+// symmetrised and empty coarse dofs get a unit diagonal.
+template <int B>
+__global__ void __launch_bounds__(kBlock)
+k_galerkin_ptw(const double* __restrict__ P, const double* __restrict__ W, size_t nn, int nxn, int nyn,
+               int ncx, int ncy, double* __restrict__ Ac) {
   const size_t ncn = (size_t)ncx * ncy;
-  const size_t I = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (I >= ncn) return;  // whole wave exits together
+  const size_t I = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= ncn) return;
   const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
   const int tJx[5] = {Ix, Ix + 1, Ix, Ix + 1, Ix - 1};
   const int tJy[5] = {Iy, Iy, Iy + 1, Iy + 1, Iy + 1};
@@ -702,78 +761,50 @@ k_galerkin(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
       for (int c = 0; c < 3; ++c) acc[t][a][c] = 0.0;
   const int i0 = max(3 * Ix - 1, 0), i1 = min(agg_last(Ix, nxn, ncx) + 1, nxn - 1);
   const int j0 = max(3 * Iy - 1, 0), j1 = min(agg_last(Iy, nyn, ncy) + 1, nyn - 1);
-  const int i = i0 + lane % 7, j = j0 + lane / 7;
-  bool active = lane < 49 && i <= i1 && j <= j1;
-  int sI = 0;
-  if (active) {
-    const int sx = slot1(i, nxn, ncx, Ix), sy = slot1(j, nyn, ncy, Iy);
-    active = sx >= 0 && sy >= 0;
-    sI = sx + 2 * sy;
-  }
-  if (active) {
-    const size_t n = (size_t)j * nxn + i;
-    double PI[B][3];
+  for (int j = j0; j <= j1; ++j) {
+    const int sy = slot1(j, nyn, ncy, Iy);
+    if (sy < 0) continue;
+    const int ay = agg_of(j, ncy);
+    for (int i = i0; i <= i1; ++i) {
+      const int sx = slot1(i, nxn, ncx, Ix);
+      if (sx < 0) continue;
+      const int sl = sx + 2 * sy;
+      const size_t n = (size_t)j * nxn + i;
+      const int ax = agg_of(i, ncx);
+      double PI[B][3];
 #pragma unroll
-    for (int r = 0; r < B; ++r)
+      for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) PI[r][c] = P[pidx(B, nn, sI, n, r, c)];
-#pragma unroll
-    for (int d = 0; d < 9; ++d) {
-      const int ii = i + kDI[d], jj = j + kDJ[d];
-      if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
-      double blk[B][B];
-      load_block<B>(A, nn, nxn, i, j, d, blk);
-      double Y[3][B];  // PI^T blk
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-          double s = 0.0;
-#pragma unroll
-          for (int r = 0; r < B; ++r) s += PI[r][a] * blk[r][k];
-          Y[a][k] = s;
-        }
-      const size_t m = (size_t)jj * nxn + ii;
+        for (int c = 0; c < 3; ++c) PI[r][c] = P[pidx(B, nn, sl, n, r, c)];
 #pragma unroll
       for (int t = 0; t < 5; ++t) {
-        const int Jx = tJx[t], Jy = tJy[t];
-        if (Jx < 0 || Jx >= ncx || Jy >= ncy) continue;
-        const int sx = slot1(ii, nxn, ncx, Jx), sy = slot1(jj, nyn, ncy, Jy);
-        if (sx < 0 || sy < 0) continue;
-        const int sJ = sx + 2 * sy;
+        const int qx = tJx[t] - ax + 1, qy = tJy[t] - ay + 1;
+        if (tJx[t] < 0 || tJx[t] >= ncx || tJy[t] >= ncy || qx < 0 || qx > 2 || qy > 2) continue;
+        const int q = qy * 3 + qx;
 #pragma unroll
         for (int k = 0; k < B; ++k)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double pv = P[pidx(B, nn, sJ, m, k, c)];
+            const double wv = W[(size_t)((q * B + k) * 3 + c) * nn + n];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) acc[t][a][c] += Y[a][k] * pv;
+            for (int a = 0; a < 3; ++a) acc[t][a][c] += PI[k][a] * wv;
           }
       }
     }
   }
 #pragma unroll
-  for (int t = 0; t < 5; ++t)
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[t][a][c] = wave_sum(acc[t][a][c]);
-  if (lane != 0) return;
-  // symmetrise the diagonal block; guard empty coarse dofs
-#pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int c = a + 1; c < 3; ++c) {
-      const double s = 0.5 * (acc[0][a][c] + acc[0][c][a]);
-      acc[0][a][c] = acc[0][c][a] = s;
+      const double sv = 0.5 * (acc[0][a][c] + acc[0][c][a]);
+      acc[0][a][c] = acc[0][c][a] = sv;
     }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
     if (acc[0][a][a] == 0.0) acc[0][a][a] = 1.0;
 #pragma unroll
   for (int t = 0; t < 5; ++t) {
-    const int Jx = tJx[t], Jy = tJy[t];
-    const bool valid = !(Jx < 0 || Jx >= ncx || Jy >= ncy);
+    const bool valid = !(tJx[t] < 0 || tJx[t] >= ncx || tJy[t] >= ncy);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -793,10 +824,13 @@ __global__ void k_diag_sqrt(const double* __restrict__ A, size_t nn, double* __r
   }
 }
 
-// S = D^{-1/2} A D^{-1/2} stored in BF16 (same 5-block layout)
-template <int B>
-__global__ void k_scale_to_bf16(const double* __restrict__ A, size_t nn, int nxn, int nyn,
-                                const double* __restrict__ dsc, __hip_bfloat16* __restrict__ S) {
+__device__ __forceinline__ void store16(__hip_bfloat16* p, double v) { *p = __float2bfloat16((float)v); }
+__device__ __forceinline__ void store16(_Float16* p, double v) { *p = (_Float16)(float)v; }
+
+// S = D^{-1/2} A D^{-1/2} stored in 16 bits (BF16 or FP16; same 5-block layout)
+template <int B, typename T16>
+__global__ void k_scale_to_16(const double* __restrict__ A, size_t nn, int nxn, int nyn,
+                              const double* __restrict__ dsc, T16* __restrict__ S) {
   const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
@@ -808,7 +842,7 @@ __global__ void k_scale_to_bf16(const double* __restrict__ A, size_t nn, int nxn
       for (int c = 0; c < B; ++c) {
         const size_t k = aidx(B, nn, blk, n, r, c);
         const double v = ok ? A[k] / (dsc[n * B + r] * dsc[m * B + c]) : 0.0;
-        S[k] = __float2bfloat16((float)v);
+        store16(S + k, v);
       }
   }
 }
@@ -1000,11 +1034,13 @@ void amg_free(vp_ctx c) {
     dfree(L.Ainv64);
     dfree(L.Ainv32);
     dfree(L.Abf);
+    dfree(L.Ah);
     dfree(L.dsc64);
     free_vectors(L);
     L = Level();
   }
   dfree(c->dense);
+  dfree(c->gal_work);
   c->nlev = 0;
   c->amg_struct = false;
   c->amg_ready = false;
@@ -1074,35 +1110,44 @@ void alloc_vectors(vp_ctx c) {
 // S_l = D_l^{-1/2} A_l D_l^{-1/2} in BF16 and the V-cycle works there in the
 // scaled variables, with prolongators P^_l = D_l^{1/2} P_l D_{l+1}^{-1/2} (FP32;
 // D_0 = I) and the coarsest inverse D^{1/2} A^{-1} D^{1/2} (FP32).
-void bf16_copies(vp_ctx c, hipStream_t s, bool finest_bf16) {
+// 16-bit copies of the operators for the mixed modes.  finest: 0 FP32 (unscaled),
+// 1 BF16 Jacobi-scaled, 2 FP16 Jacobi-scaled; coarse levels are Jacobi-scaled in
+// FP16 (coarse_fp16) or BF16.
+void bf16_copies(vp_ctx c, hipStream_t s, int finest, bool coarse_fp16) {
+  const bool finest_scaled = finest != 0;
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const size_t na = (size_t)5 * L.B * L.B * L.nn;
     const unsigned g = (unsigned)((L.nn + 255) / 256);
-    if (l == 0 && finest_bf16) {
-      if (!L.dsc64) L.dsc64 = dalloc<double>((size_t)L.B * L.nn);
-      if (!L.Abf) L.Abf = dalloc<__hip_bfloat16>(na);
-      if (L.B == 2) {
-        hipLaunchKernelGGL(k_diag_sqrt<2>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
-        VP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_scale_to_bf16<2>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64, L.Abf);
-      } else {
-        hipLaunchKernelGGL(k_diag_sqrt<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
-        VP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_scale_to_bf16<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64, L.Abf);
-      }
-      VP_LAUNCH_CHECK();
-    } else if (l == 0) {
+    if (l == 0 && finest == 0) {
       if (!L.A32) L.A32 = dalloc<float>(na);
       convert(s, L.A64, L.A32, na);
-    } else {
-      if (!L.dsc64) L.dsc64 = dalloc<double>((size_t)L.B * L.nn);
-      if (!L.Abf) L.Abf = dalloc<__hip_bfloat16>(na);
-      hipLaunchKernelGGL(k_diag_sqrt<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
-      VP_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_scale_to_bf16<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64, L.Abf);
-      VP_LAUNCH_CHECK();
+      continue;
     }
+    if (!L.dsc64) L.dsc64 = dalloc<double>((size_t)L.B * L.nn);
+    if (L.B == 2)
+      hipLaunchKernelGGL(k_diag_sqrt<2>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
+    else
+      hipLaunchKernelGGL(k_diag_sqrt<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
+    VP_LAUNCH_CHECK();
+    if ((l == 0 && finest == 2) || (l > 0 && coarse_fp16)) {
+      if (!L.Ah) L.Ah = dalloc<_Float16>(na);
+      if (L.B == 2)
+        hipLaunchKernelGGL((k_scale_to_16<2, _Float16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
+                           L.Ah);
+      else
+        hipLaunchKernelGGL((k_scale_to_16<3, _Float16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
+                           L.Ah);
+    } else {
+      if (!L.Abf) L.Abf = dalloc<__hip_bfloat16>(na);
+      if (L.B == 2)
+        hipLaunchKernelGGL((k_scale_to_16<2, __hip_bfloat16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn,
+                           L.dsc64, L.Abf);
+      else
+        hipLaunchKernelGGL((k_scale_to_16<3, __hip_bfloat16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn,
+                           L.dsc64, L.Abf);
+    }
+    VP_LAUNCH_CHECK();
   }
   for (int l = 0; l + 1 < c->nlev; ++l) {
     Level& L = c->lev[l];
@@ -1112,7 +1157,7 @@ void bf16_copies(vp_ctx c, hipStream_t s, bool finest_bf16) {
     const unsigned g = (unsigned)((L.nn + 255) / 256);
     if (L.B == 2)
       hipLaunchKernelGGL(k_scale_p<2>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
-                         (const double*)(finest_bf16 ? L.dsc64 : nullptr), (const double*)N.dsc64, L.P32);
+                         (const double*)(finest_scaled ? L.dsc64 : nullptr), (const double*)N.dsc64, L.P32);
     else
       hipLaunchKernelGGL(k_scale_p<3>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          (const double*)L.dsc64, (const double*)N.dsc64, L.P32);
@@ -1121,13 +1166,24 @@ void bf16_copies(vp_ctx c, hipStream_t s, bool finest_bf16) {
   Level& C = c->lev[c->nlev - 1];
   const int nd = C.B * (int)C.nn;
   if (!C.Ainv32) C.Ainv32 = dalloc<float>((size_t)nd * nd);
-  if (c->nlev == 1 && !finest_bf16) {
+  if (c->nlev == 1 && !finest_scaled) {
     convert(s, C.Ainv64, C.Ainv32, (size_t)nd * nd);
   } else {
     hipLaunchKernelGGL(k_scale_dense, dim3((unsigned)(((size_t)nd * nd + 255) / 256)), dim3(256), 0, s, C.Ainv64, nd,
                        (const double*)C.dsc64, C.Ainv32);
     VP_LAUNCH_CHECK();
   }
+}
+
+// Scratch for the Galerkin products: the largest 9*3*B*nn over the levels that
+// have a coarser level (allocated once per hierarchy).
+double* galerkin_work(vp_ctx c) {
+  if (!c->gal_work) {
+    size_t mx = 0;
+    for (int l = 0; l + 1 < c->nlev; ++l) mx = std::max(mx, (size_t)27 * c->lev[l].B * c->lev[l].nn);
+    c->gal_work = dalloc<double>(std::max<size_t>(mx, 1));
+  }
+  return c->gal_work;
 }
 
 // Restart the spectral estimates from the fixed start vector at the next setup.
@@ -1192,13 +1248,21 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
                          L.Ptent, L.lmax, omega_scale, L.P64);
     VP_LAUNCH_CHECK();
     Level& N = c->lev[l + 1];
-    const unsigned gc = (unsigned)((N.nn + 3) / 4);  // one wavefront per coarse node
-    if (L.B == 2)
-      hipLaunchKernelGGL(k_galerkin<2>, dim3(gc), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
-                         L.P64, N.A64);
-    else
-      hipLaunchKernelGGL(k_galerkin<3>, dim3(gc), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
-                         L.P64, N.A64);
+    const unsigned gc = (unsigned)((N.nn + kBlock - 1) / kBlock);
+    double* Wap = galerkin_work(c);
+    if (L.B == 2) {
+      hipLaunchKernelGGL(k_galerkin_ap<2>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         L.P64, Wap);
+      VP_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_galerkin_ptw<2>, dim3(gc), dim3(kBlock), 0, s, L.P64, Wap, L.nn, L.nxn, L.nyn, L.ncx,
+                         L.ncy, N.A64);
+    } else {
+      hipLaunchKernelGGL(k_galerkin_ap<3>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         L.P64, Wap);
+      VP_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_galerkin_ptw<3>, dim3(gc), dim3(kBlock), 0, s, L.P64, Wap, L.nn, L.nxn, L.nyn, L.ncx,
+                         L.ncy, N.A64);
+    }
     VP_LAUNCH_CHECK();
   }
   // coarsest: dense inverse
@@ -1215,8 +1279,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   else hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, C.Ainv64, nd);
   VP_LAUNCH_CHECK();
   // reduced-precision copies
-  if (precision == VP_PREC_FP32_BF16COARSE || precision == VP_PREC_BF16) {
-    bf16_copies(c, s, precision == VP_PREC_BF16);
+  if (precision == VP_PREC_FP32_BF16COARSE || precision == VP_PREC_BF16 || precision == VP_PREC_FP16_BF16COARSE ||
+      precision == VP_PREC_FP16) {
+    const int finest = precision == VP_PREC_BF16 ? 1 : precision == VP_PREC_FP32_BF16COARSE ? 0 : 2;
+    bf16_copies(c, s, finest, precision == VP_PREC_FP16);
   } else if (precision != VP_PREC_FP64) {
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
@@ -1349,8 +1415,12 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     if (L.B == 2) run(std::integral_constant<int, 2>(), double(), double(), L.A64, L.P64);
     else run(std::integral_constant<int, 3>(), double(), double(), L.A64, L.P64);
   } else {
-    const bool bf = (c->amg_prec == VP_PREC_FP32_BF16COARSE && l > 0) || c->amg_prec == VP_PREC_BF16;
-    if (L.B == 2 && bf) run(std::integral_constant<int, 2>(), __hip_bfloat16(), float(), L.Abf, L.P32);
+    const bool bf = ((c->amg_prec == VP_PREC_FP32_BF16COARSE || c->amg_prec == VP_PREC_FP16_BF16COARSE) && l > 0) ||
+                    c->amg_prec == VP_PREC_BF16;
+    if ((l == 0 && c->amg_prec == VP_PREC_FP16_BF16COARSE) || c->amg_prec == VP_PREC_FP16) {
+      if (L.B == 2) run(std::integral_constant<int, 2>(), _Float16(), float(), L.Ah, L.P32);
+      else run(std::integral_constant<int, 3>(), _Float16(), float(), L.Ah, L.P32);
+    } else if (L.B == 2 && bf) run(std::integral_constant<int, 2>(), __hip_bfloat16(), float(), L.Abf, L.P32);
     else if (L.B == 2) run(std::integral_constant<int, 2>(), float(), float(), L.A32, L.P32);
     else if (bf) run(std::integral_constant<int, 3>(), __hip_bfloat16(), float(), L.Abf, L.P32);
     else run(std::integral_constant<int, 3>(), float(), float(), L.A32, L.P32);
@@ -1358,6 +1428,11 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
 }
 
 }  // namespace
+
+// The finest level runs in Jacobi-scaled variables (16-bit finest storage).
+bool scaled_finest(vp_ctx c) {
+  return c->amg_prec == VP_PREC_BF16 || c->amg_prec == VP_PREC_FP16_BF16COARSE || c->amg_prec == VP_PREC_FP16;
+}
 
 // z = M^{-1} r (FP64 in/out; V-cycle in the setup's precision)
 void amg_apply(vp_ctx c, const double* r, double* z) {
@@ -1373,7 +1448,7 @@ void amg_apply(vp_ctx c, const double* r, double* z) {
   } end_{c, prof_begin(c, VP_KID_VCYCLE)};
   if (c->amg_prec == VP_PREC_FP64) {
     vcycle_level<double>(c, 0, r, z);
-  } else if (c->amg_prec == VP_PREC_BF16) {
+  } else if (scaled_finest(c)) {
     // finest level in the scaled variables: b^ = D^{-1/2} r, z = D^{-1/2} x^
     hipLaunchKernelGGL(k_scale_cast_df, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, r, L.dsc64, (float*)L.b, n);
     VP_LAUNCH_CHECK();
@@ -1392,8 +1467,9 @@ void amg_apply(vp_ctx c, const double* r, double* z) {
 // FP32 input buffer of the V-cycle (and the finest level's Jacobi scaling when
 // the V-cycle runs in scaled variables), or null for an FP64 V-cycle: callers
 // that produce the residual can write it there directly and pass input_ready.
+
 float* amg_input32(vp_ctx c, const double** dsc) {
-  if (dsc) *dsc = c->amg_prec == VP_PREC_BF16 ? c->lev[0].dsc64 : nullptr;
+  if (dsc) *dsc = scaled_finest(c) ? c->lev[0].dsc64 : nullptr;
   return c->amg_prec == VP_PREC_FP64 ? nullptr : (float*)c->lev[0].b;
 }
 
@@ -1411,7 +1487,7 @@ int amg_apply_dots(vp_ctx c, const double* r, const double* q, double* z, bool i
     vcycle_level<double>(c, 0, r, z);
     nb = launch_out_dots<double>(s, z, nullptr, z, r, q, n, c->partials);
   } else {
-    const bool scaled = c->amg_prec == VP_PREC_BF16;
+    const bool scaled = scaled_finest(c);
     if (!input_ready) {
       if (scaled) {
         hipLaunchKernelGGL(k_scale_cast_df, dim3(grid_for(n)), dim3(kBlock), 0, s, r, L.dsc64, (float*)L.b, n);

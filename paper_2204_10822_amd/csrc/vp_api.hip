@@ -277,7 +277,7 @@ void amg_setup(vp_ctx c, const vp_amg_opts& a) {
   require(c->have_K, VP_ESTATE, "no assembled operator");
   require(a.cheb_degree >= 1 && a.cheb_degree <= 16, VP_EINVAL, "cheb_degree out of range");
   require(a.max_coarse >= 8 && a.max_coarse <= 1024, VP_EINVAL, "max_coarse out of range");
-  require(a.precision >= 0 && a.precision <= 3, VP_EINVAL, "bad precision");
+  require(a.precision >= 0 && a.precision <= 5, VP_EINVAL, "bad precision");
   require(a.cheb_ratio > 1.0 && a.omega_scale > 0.0, VP_EINVAL, "bad smoother options");
   if (!c->amg_struct || c->max_coarse != a.max_coarse) amg_build_structure(c, c->lev[0].A64, a.max_coarse);
   c->cheb_degree = a.cheb_degree;
@@ -540,6 +540,23 @@ int vp_amg_info(vp_ctx c, int* levels, int* nxn, int* nyn, int* dpn) {
   });
 }
 
+int vp_amg_export(vp_ctx c, int level, double* A, double* P) {
+  return guarded(c, [&] {
+    require(c != nullptr, VP_EINVAL, "null context");
+    require(c->amg_ready, VP_ESTATE, "AMG not set up");
+    require(level >= 0 && level < c->nlev, VP_EINVAL, "level out of range");
+    require(!P || level + 1 < c->nlev, VP_EINVAL, "the coarsest level has no prolongator");
+    const Level& L = c->lev[level];
+    if (A)
+      VP_HIP(hipMemcpyAsync(A, L.A64, (size_t)5 * L.B * L.B * L.nn * sizeof(double), hipMemcpyDeviceToDevice,
+                            c->stream));
+    if (P)
+      VP_HIP(hipMemcpyAsync(P, L.P64, (size_t)12 * L.B * L.nn * sizeof(double), hipMemcpyDeviceToDevice,
+                            c->stream));
+    return VP_OK;
+  });
+}
+
 int vp_krylov_solve(vp_ctx c, const double* b, double* x, const vp_krylov_opts* o, vp_krylov_info* info) {
   return guarded(c, [&] {
     require(c != nullptr && b && x && o, VP_EINVAL, "null argument");
@@ -592,10 +609,10 @@ int vp_profile_read(vp_ctx c, int kid, double* total_ms, int* launches, double* 
     switch (kid) {
       case VP_KID_APPLY_FINE: b = nn * (20 * 8 + 2 * 16); break;
       case VP_KID_CHEB_STEP0:
-        b = c->amg_prec == VP_PREC_BF16 ? nn * (20 * 2 + 6 * 8) : f32 ? nn * (20 * 4 + 6 * 8) : nn * (20 * 8 + 6 * 16);
+        b = c->amg_prec >= VP_PREC_BF16 ? nn * (20 * 2 + 6 * 8) : f32 ? nn * (20 * 4 + 6 * 8) : nn * (20 * 8 + 6 * 16);
         break;
       case VP_KID_STEN_RESID0:
-        b = c->amg_prec == VP_PREC_BF16 ? nn * (20 * 2 + 3 * 8) : f32 ? nn * (20 * 4 + 3 * 8) : nn * (20 * 8 + 3 * 16);
+        b = c->amg_prec >= VP_PREC_BF16 ? nn * (20 * 2 + 3 * 8) : f32 ? nn * (20 * 4 + 3 * 8) : nn * (20 * 8 + 3 * 16);
         break;
       case VP_KID_RESIDUAL: b = nn * 64 + nc * 16; break;
       case VP_KID_ASSEMBLE: b = nn * (32 + 160) + nc * (16 + 96); break;

@@ -117,6 +117,7 @@ __host__ __device__ __forceinline__ size_t pidx(int B, size_t nn, int s, size_t 
 __device__ __forceinline__ float ld(const float* p) { return *p; }
 __device__ __forceinline__ double ld(const double* p) { return *p; }
 __device__ __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+__device__ __forceinline__ float ld(const _Float16* p) { return (float)*p; }
 
 // ---------------------------------------------------------------------------
 // element constants (uniform structured mesh, 2x2 Gauss)
@@ -140,6 +141,7 @@ struct Level {
   double* A64 = nullptr;
   float* A32 = nullptr;
   __hip_bfloat16* Abf = nullptr; // Jacobi-scaled values (mixed+bf16 mode, levels >= 1)
+  _Float16* Ah = nullptr;         // Jacobi-scaled FP16 values (finest level, FP16 mode)
   double* dsc64 = nullptr;       // sqrt(diag A) per dof (bf16 mode, levels >= 1)
   bool own_A64 = true;
   // transfer to the next level (aggregation of 3x3 nodes)
@@ -209,6 +211,7 @@ struct vp_ctx_s {
   double* kv = nullptr;            // Krylov bases [(2*restart+1 + 4) * ndof]
   int kv_restart = 0;
   double* dense = nullptr;         // coarse dense matrix scratch
+  double* gal_work = nullptr;      // A P per fine node for the Galerkin product [9*3*B*nn]
   // Newton history (Eisenstat-Walker state)
   double ew_rn_prev = -1.0, ew_eta_prev = 0.1;
 };

@@ -18,13 +18,14 @@ _LIB_PATH = os.path.join(_HERE, "libvp.so")
 VP_OK, VP_NOT_CONVERGED, VP_LINESEARCH_FAIL, VP_KRYLOV_MAXIT = 0, 1, 2, 3
 VP_EINVAL, VP_EHIP, VP_ENOMEM, VP_ESTATE, VP_ENONFINITE, VP_EBREAKDOWN = -1, -2, -3, -4, -5, -6
 VP_SVN, VP_STDN = 0, 1
-VP_PREC_FP64, VP_PREC_FP32, VP_PREC_FP32_BF16COARSE, VP_PREC_BF16 = 0, 1, 2, 3
+VP_PREC_FP64, VP_PREC_FP32, VP_PREC_FP32_BF16COARSE, VP_PREC_BF16, VP_PREC_FP16_BF16COARSE, VP_PREC_FP16 = \
+    0, 1, 2, 3, 4, 5
 VP_KRYLOV_FGMRES, VP_KRYLOV_FCG = 0, 1
 VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
 
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_residual",
             "vp_newton_assemble", "vp_operator_apply", "vp_operator_export", "vp_amg_setup",
-            "vp_amg_apply", "vp_amg_info", "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
+            "vp_amg_apply", "vp_amg_info", "vp_amg_export", "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
             "vp_newton_step", "vp_newton_solve", "vp_default_opts", "vp_profile",
             "vp_profile_read"]
 EXPORTED_NET = ["vpnet_create", "vpnet_destroy", "vpnet_last_error", "vpnet_param_count",
@@ -88,6 +89,7 @@ def _load():
         "vp_amg_setup": (I, [P, C.POINTER(vp_amg_opts)]),
         "vp_amg_apply": (I, [P, P, P]),
         "vp_amg_info": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+        "vp_amg_export": (I, [P, I, P, P]),
         "vp_krylov_solve": (I, [P, P, P, C.POINTER(vp_krylov_opts), C.POINTER(vp_krylov_info)]),
         "vp_pi_update": (I, [P, P, P, P, D]),
         "vp_pi_init": (I, [P, P, P]),
@@ -236,6 +238,17 @@ class Context:
         b = (C.c_int * 16)()
         self._check(LIB.vp_amg_info(self.h, C.byref(lv), nx, ny, b))
         return [(nx[i], ny[i], b[i]) for i in range(lv.value)]
+
+    def vp_amg_export(self, level, A=None, P=None):
+        """A: [5*B*B, nn] (layout of vp_operator_export, B x B blocks); P: [12*B, nn]."""
+        lv = self.vp_amg_info()
+        if not 0 <= level < len(lv):
+            raise ValueError("level out of range")
+        nxn, nyn, B = lv[level]
+        nn = nxn * nyn
+        pa = _ptr(A, (5 * B * B * nn,), "A") if A is not None else None
+        pp = _ptr(P, (12 * B * nn,), "P") if P is not None else None
+        return self._check(LIB.vp_amg_export(self.h, int(level), pa, pp))
 
     def vp_krylov_solve(self, b, x, opts=None):
         if opts is None:

@@ -131,7 +131,7 @@ def test_pi_update_and_init_parity(vp, nx, ny, seed):
 
 
 @pytest.mark.parametrize("method", ["fgmres", "fcg"])
-@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
 def test_krylov_solves_assembled_system(vp, method, prec):
     nx, ny, seed = 64, 48, 5
     w, prob, ctx = _case(vp, nx, ny, seed)
@@ -223,10 +223,12 @@ def test_newton_solve_parity(vp, nx, ny, seed, variant):
 def test_vcycle_reduced_precision_close_to_fp64(vp):
     """The FP32 V-cycle applies the same operator as the FP64 one up to FP32
     rounding; with BF16 coarse operators (Jacobi-scaled) the difference is of the
-    order of BF16 rounding.  Fresh contexts give all the same spectral estimates."""
+    order of BF16 rounding, with an FP16 finest level below that, and FP16 on
+    every level of the order of FP16 rounding.  Fresh contexts give all the same
+    spectral estimates."""
     nx, ny, seed = 64, 48, 5
     outs = {}
-    for prec in (0, 1, 2, 3):
+    for prec in (0, 1, 2, 3, 4, 5):
         w, prob, ctx = _case(vp, nx, ny, seed)
         v = O.newton_solve(prob, maxit=2).v
         ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
@@ -242,7 +244,108 @@ def test_vcycle_reduced_precision_close_to_fp64(vp):
     d32 = _relerr(outs[1], outs[0])
     dbf = _relerr(outs[2], outs[0])
     dba = _relerr(outs[3], outs[0])
-    print(f"[vcycle] fp32 vs fp64 {d32:.2e}  bf16-coarse vs fp64 {dbf:.2e}  bf16-all vs fp64 {dba:.2e}", flush=True)
+    dh = _relerr(outs[4], outs[0])
+    dha = _relerr(outs[5], outs[0])
+    print(f"[vcycle] fp32 vs fp64 {d32:.2e}  bf16-coarse vs fp64 {dbf:.2e}  bf16-all vs fp64 {dba:.2e}  "
+          f"fp16-finest vs fp64 {dh:.2e}  fp16-all vs fp64 {dha:.2e}", flush=True)
     assert d32 < 1e-4
     assert dbf < 5e-2
     assert dba < 1e-1
+    assert dh < 5e-2
+    assert dha < 1e-2
+
+
+def _stencil_matrix(blocks, nxn, nyn, B):
+    """CSR matrix of a symmetric block 9-point stencil from the 5-block storage
+    (blocks: [5][node][B][B] flattened, self, E, N, NE, NW)."""
+    nn = nxn * nyn
+    A = blocks.reshape(5, nn, B, B)
+    jj, ii = np.divmod(np.arange(nn), nxn)
+    offs = [(0, 0), (1, 0), (0, 1), (1, 1), (-1, 1)]
+    rows, cols, vals = [], [], []
+    for b, (di, dj) in enumerate(offs):
+        ok = (ii + di >= 0) & (ii + di < nxn) & (jj + dj < nyn)
+        n = np.nonzero(ok)[0]
+        m = (jj[n] + dj) * nxn + ii[n] + di
+        for r in range(B):
+            for c in range(B):
+                rows.append(B * n + r); cols.append(B * m + c); vals.append(A[b, n, r, c])
+                if b > 0:
+                    rows.append(B * m + c); cols.append(B * n + r); vals.append(A[b, n, r, c])
+    M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(B * nn, B * nn)).tocsr()
+    M.sum_duplicates()
+    return M
+
+
+def _runs(n):
+    """Aggregates along one axis: runs of 3 nodes, the last run takes 3..5."""
+    na = n // 3
+    own = np.minimum(np.arange(n) // 3, na - 1)
+    other = np.full(n, -1)
+    for a in range(na):
+        first, last = 3 * a, (n - 1 if a == na - 1 else 3 * a + 2)
+        if a > 0:
+            other[first] = a - 1
+        if a < na - 1:
+            other[last] = a + 1
+    return na, own, other
+
+
+def _prolongator_matrix(P, nxn, nyn, B):
+    """CSR matrix of the exported prolongator, and the mask of absent slots."""
+    nn = nxn * nyn
+    ncx, ownx, othx = _runs(nxn)
+    ncy, owny, othy = _runs(nyn)
+    P = P.reshape(4, B, 3, nn)
+    jj, ii = np.divmod(np.arange(nn), nxn)
+    rows, cols, vals, absent = [], [], [], []
+    for s in range(4):
+        Jx = ownx[ii] if s % 2 == 0 else othx[ii]
+        Jy = owny[jj] if s // 2 == 0 else othy[jj]
+        ok = (Jx >= 0) & (Jy >= 0)
+        absent.append(P[s][:, :, ~ok].ravel())
+        n = np.nonzero(ok)[0]
+        J = Jy[n] * ncx + Jx[n]
+        for r in range(B):
+            for c in range(3):
+                rows.append(B * n + r); cols.append(3 * J + c); vals.append(P[s, r, c, n])
+    M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(B * nn, 3 * ncx * ncy)).tocsr()
+    M.sum_duplicates()
+    return M, np.concatenate(absent)
+
+
+@pytest.mark.parametrize("nx,ny,seed", [(64, 48, 5), (100, 37, 4)])
+def test_galerkin_coarse_operators(vp, nx, ny, seed):
+    """Every coarse operator equals P^T A P of the level above (exported through the
+    C ABI and multiplied on the host), empty coarse dofs aside (unit diagonal), and
+    prolongator entries of absent slots are zero."""
+    w, prob, ctx = _case(vp, nx, ny, seed)
+    v = O.newton_solve(prob, maxit=2).v
+    ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
+    n, a, k = vp.default_opts()
+    ctx.vp_amg_setup(a)
+    levels = ctx.vp_amg_info()
+    print(f"[galerkin] levels {levels}", flush=True)
+    assert len(levels) >= 3
+    mats = []
+    for l, (nxn, nyn, B) in enumerate(levels):
+        At = torch.zeros(5 * B * B * nxn * nyn, dtype=torch.float64, device="cuda")
+        Pt = torch.zeros(12 * B * nxn * nyn, dtype=torch.float64, device="cuda") if l + 1 < len(levels) else None
+        ctx.vp_amg_export(l, At, Pt)
+        mats.append((_host(At), None if Pt is None else _host(Pt)))
+    for l in range(len(levels) - 1):
+        nxn, nyn, B = levels[l]
+        A = _stencil_matrix(mats[l][0], nxn, nyn, B)
+        P, absent = _prolongator_matrix(mats[l][1], nxn, nyn, B)
+        assert np.all(absent == 0.0)
+        G = (P.T @ A @ P).toarray()
+        d = np.diag(G).copy()
+        d[d == 0.0] = 1.0
+        np.fill_diagonal(G, d)
+        cx, cy, cB = levels[l + 1]
+        Ac = _stencil_matrix(mats[l + 1][0], cx, cy, cB).toarray()
+        err = np.linalg.norm(Ac - G) / np.linalg.norm(G)
+        print(f"[galerkin] level {l}->{l + 1}: rel err {err:.2e}", flush=True)
+        assert err < 1e-12
