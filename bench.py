@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--paths", default="fp64,fp32,bf16,bf16+learned",
+    ap.add_argument("--paths", default="fp64,fp32,fp16,fp16all,fp16all+learned",
                     help="comma list of fp64, fp32, bf16, bf16+learned, bf16all, bf16all+learned, fp16, fp16+learned, fp16all, fp16all+learned")
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")

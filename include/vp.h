@@ -199,6 +199,18 @@ int vp_newton_solve(vp_ctx ctx, double* v, double* pi, int maxit,
                     const vp_newton_opts* nopts, const vp_amg_opts* aopts,
                     const vp_krylov_opts* kopts, vp_solve_info* info, double* history);
 
+/* One explicit Euler step (Sec. 3) of the transport equations eq. model:A and
+ * eq. model:H for the cell fields A and H, finite volumes on the cells (Q0, Sec. 5)
+ * with the mesh and time step of the context: the normal velocity of a face is
+ * the mean of its two nodal values of v, the flux is first-order upwind, the
+ * boundary carries no flux (v = 0 there, so the inflow values never enter).  A is
+ * clipped to [0, 1] and H to [0, inf) afterwards.  Positivity needs
+ * dt (max|u|/hx + max|v|/hy) <= 1 (not checked).
+ *  v: device nodes [(ny+1)(nx+1)][2]; A, H, A_out, H_out: device cells [ny][nx].
+ * Asynchronous on the context's stream.  VP_EINVAL for null pointers or outputs
+ * that alias an input or each other. */
+int vp_advect(vp_ctx ctx, const double* v, const double* A, const double* H, double* A_out, double* H_out);
+
 /* Per-kernel timing with HIP events recorded on the context's stream around the
  * launches of selected kernels (finest level only).  vp_profile(ctx, 1) clears
  * and starts recording, vp_profile(ctx, 0) stops.  vp_profile_read synchronises
@@ -217,7 +229,10 @@ enum {
 int vp_profile(vp_ctx ctx, int enable);
 int vp_profile_read(vp_ctx ctx, int kid, double* total_ms, int* launches, double* bytes_per_launch);
 
-/* Default option sets. */
+/* Default option sets: svN, tol 1e-8, eta_max 0.1, 30 halvings, energy line
+ * search; Chebyshev degree 4 on [lmax/30, lmax], coarsest level <= 140 dofs,
+ * FP64 V-cycle, omega scale 1; flexible CG, restart 30 (FGMRES), 500
+ * iterations, rtol 1e-2 (replaced by the forcing term inside Newton). */
 void vp_default_opts(vp_newton_opts* n, vp_amg_opts* a, vp_krylov_opts* k);
 
 #ifdef __cplusplus

@@ -386,7 +386,7 @@ extern "C" {
 
 void vp_default_opts(vp_newton_opts* n, vp_amg_opts* a, vp_krylov_opts* k) {
   if (n) *n = vp_newton_opts{VP_SVN, 1e-8, 0.1, 30, VP_LS_ENERGY};
-  if (a) *a = vp_amg_opts{3, 140, VP_PREC_FP64, 30.0, 1.0};
+  if (a) *a = vp_amg_opts{4, 140, VP_PREC_FP64, 30.0, 1.0};
   if (k) *k = vp_krylov_opts{VP_KRYLOV_FCG, 30, 500, 1e-2};
 }
 
@@ -576,6 +576,16 @@ int vp_pi_init(vp_ctx c, const double* v, double* pi) {
   return guarded(c, [&] {
     require(c != nullptr && v && pi, VP_EINVAL, "null argument");
     launch_pi_init(c, v, pi);
+    return VP_OK;
+  });
+}
+
+int vp_advect(vp_ctx c, const double* v, const double* A, const double* H, double* A_out, double* H_out) {
+  return guarded(c, [&] {
+    require(c != nullptr && v && A && H && A_out && H_out, VP_EINVAL, "null argument");
+    require(A_out != A && A_out != H && H_out != A && H_out != H && A_out != H_out, VP_EINVAL,
+            "outputs must not alias the inputs or each other");
+    launch_advect(c, v, A, H, A_out, H_out);
     return VP_OK;
   });
 }

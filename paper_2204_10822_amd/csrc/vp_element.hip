@@ -441,4 +441,50 @@ void launch_pi_init(vp_ctx c, const double* v, double* pi) {
   VP_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------
+// transport of A and H (eq. model:A, eq. model:H): one explicit Euler step
+// (Sec. 3) of cell-wise constant fields (finite volumes, Sec. 5) with the Q1
+// velocity.  Face normal velocity = mean of the face's two nodal values (exact
+// for Q1), first-order upwind flux (v.n)|f| Q_up, no flux through the boundary
+// (v = 0 there).  Each face flux is evaluated by both adjacent cells with the
+// same operands, so the update is conservative.  A is clipped to [0, 1] and H to
+// [0, inf).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_advect(const double* __restrict__ v, const double* __restrict__ A, const double* __restrict__ H, int nx,
+         int ny, double hx, double hy, double dt, double* __restrict__ Ao, double* __restrict__ Ho) {
+  const size_t c = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (c >= (size_t)nx * ny) return;
+  const int i = (int)(c % nx), j = (int)(c / nx);
+  const size_t nxn = (size_t)nx + 1;
+  const double2* V = reinterpret_cast<const double2*>(v);
+  const double2 v00 = V[(size_t)j * nxn + i], v10 = V[(size_t)j * nxn + i + 1];
+  const double2 v01 = V[(size_t)(j + 1) * nxn + i], v11 = V[(size_t)(j + 1) * nxn + i + 1];
+  const double uw = i > 0 ? 0.5 * (v00.x + v01.x) : 0.0;
+  const double ue = i < nx - 1 ? 0.5 * (v10.x + v11.x) : 0.0;
+  const double us = j > 0 ? 0.5 * (v00.y + v10.y) : 0.0;
+  const double un = j < ny - 1 ? 0.5 * (v01.y + v11.y) : 0.0;
+  const double s = dt / (hx * hy);
+  const double* Q[2] = {A, H};
+  double out[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const double* q = Q[f];
+    const double qc = q[c];
+    const double qw = i > 0 ? q[c - 1] : qc, qe = i < nx - 1 ? q[c + 1] : qc;
+    const double qs = j > 0 ? q[c - nx] : qc, qn = j < ny - 1 ? q[c + nx] : qc;
+    const double Fw = uw * hy * (uw > 0.0 ? qw : qc), Fe = ue * hy * (ue > 0.0 ? qc : qe);
+    const double Fs = us * hx * (us > 0.0 ? qs : qc), Fn = un * hx * (un > 0.0 ? qc : qn);
+    out[f] = qc - s * ((Fe - Fw) + (Fn - Fs));
+  }
+  Ao[c] = fmin(fmax(out[0], 0.0), 1.0);
+  Ho[c] = fmax(out[1], 0.0);
+}
+
+void launch_advect(vp_ctx c, const double* v, const double* A, const double* H, double* Ao, double* Ho) {
+  hipLaunchKernelGGL(k_advect, dim3(grid_for(c->ncell)), dim3(kBlock), 0, c->stream, v, A, H, c->ec.nx, c->ec.ny,
+                     c->ec.hx, c->ec.hy, c->ec.dt, Ao, Ho);
+  VP_LAUNCH_CHECK();
+}
+
 }  // namespace vp

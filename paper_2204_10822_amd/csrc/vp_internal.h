@@ -249,6 +249,7 @@ void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, 
 void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, double* K);
 void launch_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
 void launch_pi_init(vp_ctx c, const double* v, double* pi);
+void launch_advect(vp_ctx c, const double* v, const double* A, const double* H, double* Ao, double* Ho);
 
 // reductions / BLAS-1 (vector length n doubles)
 void launch_finish_sum(hipStream_t s, const double* partials, int nblocks, int K, double* out);

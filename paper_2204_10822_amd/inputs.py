@@ -223,3 +223,44 @@ def problem_one(n: int = 512) -> Workload:
     va[..., 1] = 5.0
     vo = np.zeros((n + 1, n + 1, 2))
     return Workload(f"problem_one_{n}", desc, H, A, va, vo, np.zeros_like(vo), None, 5.0)
+
+
+DAY = 86400.0
+
+
+def problem_two_wind(n: int, t: float, Lx: float = 512e3, Ly: float = 512e3) -> np.ndarray:
+    """Atmospheric wind of the paper's Problem II (Sec. 5.3) at time t [s]: a
+    cyclone whose centre moves along the diagonal at 51.2 km/day (out for 4 days,
+    then back), peak factor 15 m/s with the tanh ramps, inflow angle 72 degrees
+    (81 after day 4), shape exp(-r/100 km)/50 times the offset in km."""
+    td = t / DAY
+    if td <= 4.0:
+        vmax = -15.0 * math.tanh((4.0 - td) * (4.0 + td) / 2.0)
+        alpha = math.radians(72.0)
+        m = 256e3 + 51.2e3 * td
+    else:
+        vmax = 15.0 * math.tanh((12.0 - td) * (-4.0 + td) / 2.0)
+        alpha = math.radians(81.0)
+        m = 665.6e3 - 51.2e3 * td
+    X, Y = node_coords(n, n, Lx, Ly)
+    dxk, dyk = (X - m) / 1e3, (Y - m) / 1e3          # offsets in km
+    omega = np.exp(-np.sqrt(dxk * dxk + dyk * dyk) / 100.0) / 50.0
+    ca, sa = math.cos(alpha), math.sin(alpha)
+    w = np.empty((n + 1, n + 1, 2))
+    w[..., 0] = omega * vmax * (ca * dxk + sa * dyk)
+    w[..., 1] = omega * vmax * (-sa * dxk + ca * dyk)
+    return w
+
+
+def problem_two(n: int = 128, delta_min: float = 2e-9) -> Workload:
+    """Initial state and forcing of the paper's Problem II (Sec. 5.3), the
+    time-dependent benchmark: A = 1, H = 0.3 m + 0.005 m (sin(60 x/1000 km) +
+    sin(30 y/1000 km)), v = 0, ocean gyre of 0.01 m/s, the moving cyclone at t = 0,
+    no Coriolis term (Table tab:params)."""
+    desc = ProblemDesc(nx=n, ny=n, f_coriolis=0.0, delta_min=delta_min)
+    X, Y = cell_centres(n, n, desc.Lx, desc.Ly)
+    H = 0.3 + 0.005 * (np.sin(60.0 * X / 1e6) + np.sin(30.0 * Y / 1e6))
+    A = np.ones((n, n))
+    va = problem_two_wind(n, 0.0, desc.Lx, desc.Ly)
+    vo = ocean_gyre(n, n, desc.Lx, desc.Ly, 0.01)
+    return Workload(f"problem_two_{n}", desc, H, A, va, vo, np.zeros((n + 1, n + 1, 2)), None, 15.0)

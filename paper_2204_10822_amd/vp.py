@@ -26,7 +26,7 @@ VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_residual",
             "vp_newton_assemble", "vp_operator_apply", "vp_operator_export", "vp_amg_setup",
             "vp_amg_apply", "vp_amg_info", "vp_amg_export", "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
-            "vp_newton_step", "vp_newton_solve", "vp_default_opts", "vp_profile",
+            "vp_newton_step", "vp_newton_solve", "vp_default_opts", "vp_advect", "vp_profile",
             "vp_profile_read"]
 EXPORTED_NET = ["vpnet_create", "vpnet_destroy", "vpnet_last_error", "vpnet_param_count",
                 "vpnet_set_params", "vpnet_get_params", "vpnet_get_grads", "vpnet_forward",
@@ -97,6 +97,7 @@ def _load():
                                C.POINTER(vp_krylov_opts), C.POINTER(vp_newton_info)]),
         "vp_newton_solve": (I, [P, P, P, I, C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
                                 C.POINTER(vp_krylov_opts), C.POINTER(vp_solve_info), P]),
+        "vp_advect": (I, [P, P, P, P, P, P]),
         "vp_profile": (I, [P, I]),
         "vp_profile_read": (I, [P, I, C.POINTER(D), C.POINTER(I), C.POINTER(D)]),
         "vp_default_opts": (None, [C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
@@ -276,6 +277,11 @@ class Context:
             _ptr(pi, self.pi_shape, "pi") if pi is not None else None,
             C.byref(nopts or dn), C.byref(aopts or da), C.byref(kopts or dk), C.byref(info)))
         return rc, info
+
+    def vp_advect(self, v, A, H, A_out, H_out):
+        return self._check(LIB.vp_advect(
+            self.h, _ptr(v, self.node_shape, "v"), _ptr(A, self.cell_shape, "A"), _ptr(H, self.cell_shape, "H"),
+            _ptr(A_out, self.cell_shape, "A_out"), _ptr(H_out, self.cell_shape, "H_out")))
 
     def vp_profile(self, enable):
         return self._check(LIB.vp_profile(self.h, int(bool(enable))))

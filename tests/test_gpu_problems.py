@@ -58,3 +58,70 @@ def test_problem_one_standard_newton_is_much_slower(vp):
     assert rc_s == 0
     assert info_s.iterations <= 20
     assert info_d.iterations >= 4 * info_s.iterations
+
+
+def test_advect_parity(vp):
+    """The transport kernel against the oracle's upwind step on a ragged mesh with
+    a random velocity (zero on the boundary), anisotropic cells and clipping."""
+    from oracle import transport as T
+    nx, ny = 37, 23
+    w = inputs.synthetic(nx, 7, ny=ny, Ly=0.4 * 512e3)
+    rng = np.random.default_rng(11)
+    v = 0.3 * rng.standard_normal((ny + 1, nx + 1, 2))
+    v[0], v[-1], v[:, 0], v[:, -1] = 0.0, 0.0, 0.0, 0.0
+    A = np.clip(w.A + 0.02 * rng.standard_normal(w.A.shape), 0.0, 1.0)
+    H = w.H
+    ctx = vp.context_for(w)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).cuda()
+    Ao, Ho = torch.empty(ny, nx, dtype=torch.float64, device="cuda"), torch.empty(ny, nx, dtype=torch.float64,
+                                                                                  device="cuda")
+    ctx.vp_advect(dev(v.reshape(-1, 2)), dev(A), dev(H), Ao, Ho)
+    torch.cuda.synchronize()
+    Ar, Hr = T.advect(v.ravel(), A, H, nx, ny, w.desc.Lx, w.desc.Ly, w.desc.dt)
+    ea = np.abs(Ao.cpu().numpy() - Ar).max()
+    eh = np.abs(Ho.cpu().numpy() - Hr).max() / np.abs(Hr).max()
+    print(f"[advect] max |dA| {ea:.2e}  max |dH|/max H {eh:.2e}", flush=True)
+    assert ea < 1e-14 and eh < 1e-14
+    assert np.any(Ar == 1.0) and np.any(np.abs(Ar - A) > 1e-3)   # clipping and motion exercised
+
+
+def test_problem_two_steps_match_oracle(vp):
+    """Three half-hour steps of Problem II at 32^2 (transport with the previous
+    velocity, then the momentum solve from the previous (v, pi) to 1e-8 of
+    ||R(0)||): velocity, A and H after every step agree with the oracle's run."""
+    from oracle import transport as T
+    n = 32
+    w = inputs.problem_two(n)
+    d = w.desc
+    ctx = vp.context_for(w)
+    st = ctx._state
+    v_d = torch.zeros((n + 1) ** 2, 2, dtype=torch.float64, device="cuda")
+    pi_d = torch.zeros(4, 3, n, n, dtype=torch.float64, device="cuda")
+    A_d, H_d = st["A"].clone(), st["H"].clone()
+    A2, H2 = torch.empty_like(A_d), torch.empty_like(H_d)
+    no, ao, ko = vp.default_opts()
+    no.tol = 1e-8
+    v_o, pi_o, A_o, H_o = np.zeros(2 * (n + 1) ** 2), None, w.A.copy(), w.H.copy()
+    for k in range(3):
+        t1 = (k + 1) * d.dt
+        va = inputs.problem_two_wind(n, t1)
+        # GPU
+        ctx.vp_advect(v_d, A_d, H_d, A2, H2)
+        A_d, A2, H_d, H2 = A2, A_d, H2, H_d
+        ctx.vp_set_state(H_d, A_d, vp.to_device(va.reshape(-1, 2)), st["v_ocean"], v_d)
+        rc, info, _ = ctx.vp_newton_solve(v_d, pi_d, 200, no, ao, ko)
+        assert rc == 0
+        # oracle
+        A_o, H_o = T.advect(v_o, A_o, H_o, n, n, d.Lx, d.Ly, d.dt)
+        prob = O.problem_from_workload(inputs.Workload("p2", d, H_o, A_o, va, w.v_ocean,
+                                                       v_o.reshape(n + 1, n + 1, 2)))
+        ref = O.newton_solve(prob, v0=v_o, pi0=pi_o, tol=1e-8)
+        assert ref.converged
+        v_o, pi_o = ref.v, ref.pi
+        torch.cuda.synchronize()
+        ev = np.linalg.norm(v_d.cpu().numpy().ravel() - v_o) / np.linalg.norm(v_o)
+        ea = np.abs(A_d.cpu().numpy() - A_o).max()
+        eh = np.abs(H_d.cpu().numpy() - H_o).max()
+        print(f"[problem_two] step {k + 1}: newton {info.iterations} (oracle {ref.iterations}) "
+              f"|dv|/|v| {ev:.2e} |dA| {ea:.2e} |dH| {eh:.2e}", flush=True)
+        assert ev < 1e-6 and ea < 1e-9 and eh < 1e-9
