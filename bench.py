@@ -128,6 +128,9 @@ def kernel_sequence(args, ctx, v, pi, torch, vp):
     torch.add(a, b, alpha=0.5, out=c)
     torch.cuda.synchronize()
     log("calibration triad (2 GiB read, 1 GiB written) done")
+    c.copy_(a)                                   # a plain 1 GiB device copy, for comparison
+    torch.cuda.synchronize()
+    log("device copy (1 GiB read, 1 GiB written) done")
     print(json.dumps({"mode": "kernels", "paths": args.paths, "n": args.n}), flush=True)
 
 

@@ -196,14 +196,16 @@ __device__ __forceinline__ void stencil_row(const TM* __restrict__ A, size_t nn,
 // ---------------------------------------------------------------------------
 // stencil kernels
 // ---------------------------------------------------------------------------
-// r = b - A x (b may be null: r = -A x); in-place r == b is allowed.
+// Per-node bodies of the stencil and transfer kernels.  Each __global__ kernel
+// below maps one thread to one node (eight lanes to one coarse node for the
+// restriction); the single-workgroup kernel for the smallest levels loops the
+// same bodies over the nodes, so both give identical results.
+
+// r = b - A x at node n (b may be null: r = -A x); in-place r == b is allowed.
 template <int B, typename TM, typename TV>
-__global__ void __launch_bounds__(kBlock)
-k_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ x,
-             const TV* b, TV* r) {
+__device__ __forceinline__ void node_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
+                                                const TV* __restrict__ x, const TV* b, TV* r, size_t n) {
   using TA = typename Acc<TV>::type;
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   TA y[B], D[B][B], bb[B];
   stencil_row<B>(A, nn, nxn, nyn, i, j, x, y, D);
@@ -213,35 +215,13 @@ k_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __
   store_node<B>(r, n, bb);
 }
 
-// y = A x (FP64 finest level), partial sums of x.y per workgroup (for CG)
-__global__ void __launch_bounds__(kBlock)
-k_apply_fine(const double* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
-             double* __restrict__ y, double* __restrict__ partials) {
-  __shared__ double lds[16];
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  double acc[1] = {0.0};
-  if (n < nn) {
-    const int i = (int)(n % nxn), j = (int)(n / nxn);
-    double yy[2], D[2][2];
-    stencil_row<2>(A, nn, nxn, nyn, i, j, x, yy, D);
-    reinterpret_cast<double2*>(y)[n] = make_double2(yy[0], yy[1]);
-    acc[0] = yy[0] * x[2 * n] + yy[1] * x[2 * n + 1];
-  }
-  if (partials) {
-    block_sum<1>(acc, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
-  }
-}
-
 // Chebyshev first step: d = D^{-1} src * inv_theta.  x (if given) = d, or x += d
 // with add; r (if given) = src.
 template <int B, typename TM, typename TV>
-__global__ void __launch_bounds__(kBlock)
-k_cheb_first(const TM* __restrict__ A, size_t nn, const TV* __restrict__ src, TV* __restrict__ r,
-             TV* __restrict__ d, TV* __restrict__ x, typename Acc<TV>::type inv_theta, int add) {
+__device__ __forceinline__ void node_cheb_first(const TM* __restrict__ A, size_t nn, const TV* __restrict__ src,
+                                                TV* __restrict__ r, TV* __restrict__ d, TV* __restrict__ x,
+                                                typename Acc<TV>::type inv_theta, int add, size_t n) {
   using TA = typename Acc<TV>::type;
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
   TA v[B * B], D[B][B], Di[B][B], sv[B], dk[B];
   load_raw<B>(A + aidx(B, nn, 0, n, 0, 0), v);
 #pragma unroll
@@ -277,13 +257,11 @@ k_cheb_first(const TM* __restrict__ A, size_t nn, const TV* __restrict__ src, TV
 // r = b - A x, d = D^{-1} r * inv_theta.  x itself is not updated here (its
 // neighbours are still being read); the following step adds d (xmode 1).
 template <int B, typename TM, typename TV>
-__global__ void __launch_bounds__(kBlock)
-k_resid_first(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ x,
-              const TV* __restrict__ b, TV* __restrict__ r, TV* __restrict__ d,
-              typename Acc<TV>::type inv_theta) {
+__device__ __forceinline__ void node_resid_first(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
+                                                 const TV* __restrict__ x, const TV* __restrict__ b,
+                                                 TV* __restrict__ r, TV* __restrict__ d,
+                                                 typename Acc<TV>::type inv_theta, size_t n) {
   using TA = typename Acc<TV>::type;
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   TA y[B], D[B][B], Di[B][B], rn[B], dk[B];
   stencil_row<B>(A, nn, nxn, nyn, i, j, x, y, D);
@@ -306,13 +284,12 @@ k_resid_first(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* _
 //   xmode 0: x += dn;  1: x = (x + dp) + dn;  2: x = dp + dn (x not read).
 // rin may equal rout.
 template <int B, typename TM, typename TV>
-__global__ void __launch_bounds__(kBlock)
-k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ dp,
-            const TV* rin, TV* rout, TV* __restrict__ dn, TV* __restrict__ x, typename Acc<TV>::type cdd,
-            typename Acc<TV>::type cdr, int xmode) {
+__device__ __forceinline__ void node_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
+                                               const TV* __restrict__ dp, const TV* rin, TV* rout,
+                                               TV* __restrict__ dn, TV* __restrict__ x,
+                                               typename Acc<TV>::type cdd, typename Acc<TV>::type cdr, int xmode,
+                                               size_t n) {
   using TA = typename Acc<TV>::type;
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   TA y[B], D[B][B], Di[B][B], rn[B], dpn[B], xn[B], dk[B];
   stencil_row<B>(A, nn, nxn, nyn, i, j, dp, y, D);
@@ -349,50 +326,51 @@ k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __r
 //   P[pidx(B, nn, slot, node, r, c)]
 // slot = sx + 2 sy, sx = 0: own aggregate in x, 1: the adjacent one (agg_other)
 // ---------------------------------------------------------------------------
-// One thread per coarse node; its window spans at most 6 fine nodes per
-// direction (the aggregate, one node on each side, a last aggregate of up to 5).
+// Restriction with eight lanes per coarse node I (lane sub of the group, gid / 8 =
+// I): I's window spans at most 6 x 6 fine nodes (the aggregate, one node on each
+// side, a last aggregate of up to 5); lane k sums the window nodes k, k+8, ... and
+// the eight partial sums are combined by a fixed butterfly within the lane group
+// (deterministic).  All eight lanes of a group must call this together.
+constexpr int kRestrictLanes = 8;
 template <int B, typename TP, typename TV>
-__global__ void __launch_bounds__(kBlock)
-k_restrict(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
-           const TV* __restrict__ r, TV* __restrict__ bc) {
+__device__ __forceinline__ void group_restrict(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx,
+                                               int ncy, const TV* __restrict__ r, TV* __restrict__ bc, size_t I,
+                                               int sub) {
   using TA = typename Acc<TV>::type;
-  const size_t I = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= (size_t)ncx * ncy) return;
   const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
   const int i0 = max(3 * Ix - 1, 0), i1 = min(agg_last(Ix, nxn, ncx) + 1, nxn - 1);
   const int j0 = max(3 * Iy - 1, 0), j1 = min(agg_last(Iy, nyn, ncy) + 1, nyn - 1);
-  int sxs[6];
-#pragma unroll
-  for (int di = 0; di < 6; ++di) sxs[di] = i0 + di <= i1 ? slot1(i0 + di, nxn, ncx, Ix) : -1;
   TA acc[3] = {TA(0), TA(0), TA(0)};
-  for (int j = j0; j <= j1; ++j) {
-    const int sy = slot1(j, nyn, ncy, Iy);
-    if (sy < 0) continue;
 #pragma unroll
-    for (int di = 0; di < 6; ++di) {
-      const int sx = sxs[di];
-      if (sx < 0) continue;
-      const int s = sx + 2 * sy;
-      const size_t n = (size_t)j * nxn + i0 + di;
-      TA rv[B];
-      load_node<B>(r, n, rv);
+  for (int w = sub; w < 36; w += kRestrictLanes) {
+    const int i = i0 + w % 6, j = j0 + w / 6;
+    if (i > i1 || j > j1) continue;
+    const int sx = slot1(i, nxn, ncx, Ix), sy = slot1(j, nyn, ncy, Iy);
+    if (sx < 0 || sy < 0) continue;
+    const int s = sx + 2 * sy;
+    const size_t n = (size_t)j * nxn + i;
+    TA rv[B];
+    load_node<B>(r, n, rv);
 #pragma unroll
-      for (int rr = 0; rr < B; ++rr)
+    for (int rr = 0; rr < B; ++rr)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += (TA)ld(P + pidx(B, nn, s, n, rr, c)) * rv[rr];
-    }
+      for (int c = 0; c < 3; ++c) acc[c] += (TA)ld(P + pidx(B, nn, s, n, rr, c)) * rv[rr];
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) bc[I * 3 + c] = (TV)acc[c];
+  for (int o = 1; o < kRestrictLanes; o <<= 1)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
+  if (sub == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bc[I * 3 + c] = (TV)acc[c];
+  }
 }
 
+// x += P xc at fine node n
 template <int B, typename TP, typename TV>
-__global__ void __launch_bounds__(kBlock)
-k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
-              const TV* __restrict__ xc, TV* __restrict__ x) {
+__device__ __forceinline__ void node_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx,
+                                                 int ncy, const TV* __restrict__ xc, TV* __restrict__ x, size_t n) {
   using TA = typename Acc<TV>::type;
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   const int ax[2] = {agg_of(i, ncx), agg_other(i, nxn, ncx)};
   const int ay[2] = {agg_of(j, ncy), agg_other(j, nyn, ncy)};
@@ -414,6 +392,178 @@ k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, in
   }
 #pragma unroll
   for (int rr = 0; rr < B; ++rr) x[n * B + rr] = (TV)acc[rr];
+}
+
+// x = M b for the dense coarsest inverse, row rw
+template <typename TM, typename TV>
+__device__ __forceinline__ void row_dense_apply(const TM* __restrict__ M, int nd, const TV* __restrict__ b,
+                                                TV* __restrict__ x, int rw) {
+  using TA = typename Acc<TV>::type;
+  TA s = TA(0);
+  for (int c = 0; c < nd; ++c) s += (TA)M[(size_t)rw * nd + c] * (TA)b[c];
+  x[rw] = (TV)s;
+}
+
+// ---- one thread per node ----------------------------------------------------
+template <int B, typename TM, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ x, const TV* b, TV* r) {
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n < nn) node_sten_resid<B>(A, nn, nxn, nyn, x, b, r, n);
+}
+
+// y = A x (FP64 finest level), partial sums of x.y per workgroup (for CG)
+__global__ void __launch_bounds__(kBlock)
+k_apply_fine(const double* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
+             double* __restrict__ y, double* __restrict__ partials) {
+  __shared__ double lds[16];
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  double acc[1] = {0.0};
+  if (n < nn) {
+    const int i = (int)(n % nxn), j = (int)(n / nxn);
+    double yy[2], D[2][2];
+    stencil_row<2>(A, nn, nxn, nyn, i, j, x, yy, D);
+    reinterpret_cast<double2*>(y)[n] = make_double2(yy[0], yy[1]);
+    acc[0] = yy[0] * x[2 * n] + yy[1] * x[2 * n + 1];
+  }
+  if (partials) {
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+  }
+}
+
+template <int B, typename TM, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_cheb_first(const TM* __restrict__ A, size_t nn, const TV* __restrict__ src, TV* __restrict__ r,
+             TV* __restrict__ d, TV* __restrict__ x, typename Acc<TV>::type inv_theta, int add) {
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n < nn) node_cheb_first<B>(A, nn, src, r, d, x, inv_theta, add, n);
+}
+
+template <int B, typename TM, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_resid_first(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ x,
+              const TV* __restrict__ b, TV* __restrict__ r, TV* __restrict__ d,
+              typename Acc<TV>::type inv_theta) {
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n < nn) node_resid_first<B>(A, nn, nxn, nyn, x, b, r, d, inv_theta, n);
+}
+
+template <int B, typename TM, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ dp,
+            const TV* rin, TV* rout, TV* __restrict__ dn, TV* __restrict__ x, typename Acc<TV>::type cdd,
+            typename Acc<TV>::type cdr, int xmode) {
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n < nn) node_cheb_step<B>(A, nn, nxn, nyn, dp, rin, rout, dn, x, cdd, cdr, xmode, n);
+}
+
+template <int B, typename TP, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_restrict(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
+           const TV* __restrict__ r, TV* __restrict__ bc) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t I = gid / kRestrictLanes;
+  if (I >= (size_t)ncx * ncy) return;  // whole lane groups leave together
+  group_restrict<B>(P, nn, nxn, nyn, ncx, ncy, r, bc, I, (int)(gid % kRestrictLanes));
+}
+
+template <int B, typename TP, typename TV>
+__global__ void __launch_bounds__(kBlock)
+k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
+              const TV* __restrict__ xc, TV* __restrict__ x) {
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n < nn) node_prolong_add<B>(P, nn, nxn, nyn, ncx, ncy, xc, x, n);
+}
+
+// ---------------------------------------------------------------------------
+// the smallest levels in one workgroup
+// ---------------------------------------------------------------------------
+// Below a few thousand nodes every kernel of the V-cycle is launch- and
+// latency-bound (a few microseconds for a handful of waves).  The part of the
+// cycle from level l0 (coarse, B = 3) down to the dense coarsest solve and back
+// runs in one workgroup instead: the same per-node bodies, looped over the nodes
+// of each sweep, with a workgroup barrier between sweeps.
+constexpr int kTailNodes = 1024;   // levels with at most this many nodes
+constexpr int kTailLevels = 6;
+constexpr int kTailDegree = 8;
+constexpr int kTailThreads = 1024;
+
+struct TailLevel {
+  const void* A;     // operator (storage type TM)
+  const void* P;     // prolongator to the next level (TP)
+  void *b, *x, *r, *d0, *d1;
+  unsigned nn;
+  int nxn, nyn, ncx, ncy;
+  double inv_theta;
+  double cdd[kTailDegree], cdr[kTailDegree];   // Chebyshev step coefficients, index 1..degree-1
+};
+struct TailArgs {
+  TailLevel L[kTailLevels];
+  const void* Ainv;  // dense inverse of the coarsest level (TV)
+  int nlev, degree, nd;
+};
+
+template <typename TM, typename TV>
+__device__ void tail_smooth(const TailLevel& L, const TV* b, TV* x, bool pre, int degree) {
+  using TA = typename Acc<TV>::type;
+  const TM* A = (const TM*)L.A;
+  TV* r = (TV*)L.r;
+  TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
+  const size_t nn = L.nn;
+  const TA inv_theta = (TA)L.inv_theta;
+  const unsigned t0 = threadIdx.x, nt = blockDim.x;
+  if (pre) {
+    for (size_t n = t0; n < nn; n += nt)
+      node_cheb_first<3>(A, nn, b, degree == 1 ? r : (TV*)nullptr, d[0], degree == 1 ? x : (TV*)nullptr, inv_theta, 0,
+                         n);
+  } else if (degree == 1) {
+    for (size_t n = t0; n < nn; n += nt) node_sten_resid<3>(A, nn, L.nxn, L.nyn, (const TV*)x, b, r, n);
+    __syncthreads();
+    for (size_t n = t0; n < nn; n += nt) node_cheb_first<3>(A, nn, (const TV*)r, (TV*)nullptr, d[0], x, inv_theta, 1, n);
+  } else {
+    for (size_t n = t0; n < nn; n += nt) node_resid_first<3>(A, nn, L.nxn, L.nyn, (const TV*)x, b, r, d[0], inv_theta, n);
+  }
+  __syncthreads();
+  for (int k = 1; k < degree; ++k) {
+    const int xmode = k > 1 ? 0 : pre ? 2 : 1;
+    const TV* rin = (pre && k == 1) ? b : (const TV*)r;
+    for (size_t n = t0; n < nn; n += nt)
+      node_cheb_step<3>(A, nn, L.nxn, L.nyn, (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], x, (TA)L.cdd[k],
+                        (TA)L.cdr[k], xmode, n);
+    __syncthreads();
+  }
+  if (pre) {
+    for (size_t n = t0; n < nn; n += nt)
+      node_sten_resid<3>(A, nn, L.nxn, L.nyn, (const TV*)d[(degree - 1) & 1], (const TV*)r, r, n);
+    __syncthreads();
+  }
+}
+
+template <typename TM, typename TP, typename TV>
+__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs a) {
+  const unsigned t0 = threadIdx.x, nt = blockDim.x;   // nt is a multiple of the restriction lane group
+  for (int l = 0; l + 1 < a.nlev; ++l) {
+    const TailLevel& L = a.L[l];
+    const TailLevel& N = a.L[l + 1];
+    tail_smooth<TM, TV>(L, (const TV*)L.b, (TV*)L.x, true, a.degree);
+    const size_t ng = (size_t)N.nn * kRestrictLanes;
+    for (size_t g = t0; g < ng; g += nt)
+      group_restrict<3>((const TP*)L.P, (size_t)L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)L.r, (TV*)N.b,
+                        g / kRestrictLanes, (int)(g % kRestrictLanes));
+    __syncthreads();
+  }
+  const TailLevel& C = a.L[a.nlev - 1];
+  for (int rw = (int)t0; rw < a.nd; rw += (int)nt) row_dense_apply((const TV*)a.Ainv, a.nd, (const TV*)C.b, (TV*)C.x, rw);
+  __syncthreads();
+  for (int l = a.nlev - 2; l >= 0; --l) {
+    const TailLevel& L = a.L[l];
+    const TailLevel& N = a.L[l + 1];
+    for (size_t n = t0; n < L.nn; n += nt)
+      node_prolong_add<3>((const TP*)L.P, (size_t)L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)N.x, (TV*)L.x, n);
+    __syncthreads();
+    tail_smooth<TM, TV>(L, (const TV*)L.b, (TV*)L.x, false, a.degree);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -969,12 +1119,8 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan_lds(double* __restrict__ 
 
 template <typename TM, typename TV>
 __global__ void k_dense_apply(const TM* __restrict__ M, int nd, const TV* __restrict__ b, TV* __restrict__ x) {
-  using TA = typename Acc<TV>::type;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nd) return;
-  TA s = TA(0);
-  for (int c = 0; c < nd; ++c) s += (TA)M[(size_t)r * nd + c] * (TA)b[c];
-  x[r] = (TV)s;
+  if (r < nd) row_dense_apply(M, nd, b, x, r);
 }
 
 template <typename TS, typename TD>
@@ -1192,6 +1338,17 @@ void amg_reset_estimates(vp_ctx c) {
 }
 
 // Numeric setup on the current finest operator.
+// First level handled by the single-workgroup tail kernel, or -1 (also when the
+// environment sets VP_AMG_TAIL=0, which keeps one launch per sweep everywhere).
+int tail_start(vp_ctx c) {
+  const char* env = std::getenv("VP_AMG_TAIL");
+  if (env && env[0] == '0') return -1;
+  if (c->cheb_degree > kTailDegree) return -1;
+  for (int l = 1; l + 1 < c->nlev; ++l)
+    if (c->lev[l].B == 3 && c->lev[l].nn <= (size_t)kTailNodes && c->nlev - l <= kTailLevels) return l;
+  return -1;
+}
+
 void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   if (!c->amg_struct) throw Error(VP_ESTATE, "AMG structure missing");
   hipStream_t s = c->stream;
@@ -1316,6 +1473,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     if (!(c->hscal[l] > 0.0) || !std::isfinite(c->hscal[l]))
       throw Error(VP_ENONFINITE, "AMG setup: non-finite or non-positive spectral bound");
   }
+  c->tail_level = tail_start(c);
   c->amg_ready = true;
 }
 
@@ -1381,8 +1539,59 @@ void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bo
 }
 
 template <typename TV>
+void launch_tail(vp_ctx c, int l0) {
+  TailArgs a{};
+  a.nlev = c->nlev - l0;
+  a.degree = c->cheb_degree;
+  const bool fp64 = std::is_same<TV, double>::value;
+  const int prec = c->amg_prec;
+  for (int k = 0; k < a.nlev; ++k) {
+    const Level& L = c->lev[l0 + k];
+    TailLevel& T = a.L[k];
+    T.nn = (unsigned)L.nn;
+    T.nxn = L.nxn; T.nyn = L.nyn; T.ncx = L.ncx; T.ncy = L.ncy;
+    T.b = L.b; T.x = L.x; T.r = L.r; T.d0 = L.d0; T.d1 = L.d1;
+    T.P = fp64 ? (const void*)L.P64 : (const void*)L.P32;
+    if (fp64) T.A = L.A64;
+    else if (prec == VP_PREC_FP32) T.A = L.A32;
+    else if (prec == VP_PREC_FP16) T.A = L.Ah;
+    else T.A = L.Abf;
+    // the coefficients of smooth(), in the same arithmetic
+    const double lmax = L.lmax_h, lmin = lmax / c->cheb_ratio;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    T.inv_theta = 1.0 / theta;
+    for (int s = 1; s < a.degree; ++s) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      T.cdd[s] = rn * rho;
+      T.cdr[s] = 2.0 * rn / delta;
+      rho = rn;
+    }
+  }
+  const Level& C = c->lev[c->nlev - 1];
+  a.nd = C.B * (int)C.nn;
+  a.Ainv = fp64 ? (const void*)C.Ainv64 : (const void*)C.Ainv32;
+  hipStream_t s = c->stream;
+  if (fp64)
+    hipLaunchKernelGGL((k_vcycle_tail<double, double, double>), dim3(1), dim3(kTailThreads), 0, s, a);
+  else if (prec == VP_PREC_FP32)
+    hipLaunchKernelGGL((k_vcycle_tail<float, float, float>), dim3(1), dim3(kTailThreads), 0, s, a);
+  else if (prec == VP_PREC_FP16)
+    hipLaunchKernelGGL((k_vcycle_tail<_Float16, float, float>), dim3(1), dim3(kTailThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_vcycle_tail<__hip_bfloat16, float, float>), dim3(1), dim3(kTailThreads), 0, s, a);
+  VP_LAUNCH_CHECK();
+}
+
+template <typename TV>
 void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
   hipStream_t s = c->stream;
+  if (l > 0 && l == c->tail_level) {
+    if constexpr (std::is_same<TV, double>::value) launch_tail<double>(c, l);
+    else launch_tail<float>(c, l);
+    return;
+  }
   Level& L = c->lev[l];
   const bool fp64 = std::is_same<TV, double>::value;
   if (l == c->nlev - 1) {
@@ -1402,7 +1611,8 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     const TM* A = (const TM*)Av;
     const TP* P = (const TP*)Pv;
     smooth<B, TM, TV>(c, l, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
-    hipLaunchKernelGGL((k_restrict<B, TP, TV>), dim3((unsigned)((N.nn + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((k_restrict<B, TP, TV>), dim3((unsigned)((N.nn * kRestrictLanes + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0,
                        s, P, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)L.r, (TV*)N.b);
     VP_LAUNCH_CHECK();
     vcycle_level<TV>(c, l + 1, (const TV*)N.b, (TV*)N.x);

@@ -246,8 +246,8 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
       launch_apply_fine(s, c->lev[0], p, q, c->partials);  // q = K p, p.q
       prof_end(c, pr);
       finish(c, (int)grid_for(c->lev[0].nn), 1, 1);
-      launch_fcg_update(s, c->dscal, x, r, p, q, n, c->partials, r32, dsc);
-      finish(c, kRedBlocks, 1, 4);
+      nb = launch_fcg_update(s, c->dscal, x, r, p, q, n, c->partials, r32, dsc);
+      finish(c, nb, 1, 4);
       fetch(c, 0, 5);
       ++it;
       if (!std::isfinite(c->hscal[4]) || !std::isfinite(c->hscal[1]))

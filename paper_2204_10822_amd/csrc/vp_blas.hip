@@ -237,22 +237,52 @@ k_fcg_update(const double* __restrict__ dev, double* __restrict__ x, double* __r
   __shared__ double lds[16];
   const double alpha = dev[1] != 0.0 ? dev[0] / dev[1] : 0.0;
   double a[1] = {0.0};
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    x[e] = fma(alpha, p[e], x[e]);
-    const double re = fma(-alpha, q[e], r[e]);
-    r[e] = re;
-    if (r32) r32[e] = (float)(dsc ? re / dsc[e] : re);
-    a[0] = fma(re, re, a[0]);
+  // node pairs (two dofs) per step: 16-byte loads and stores
+  const size_t n2 = n / 2;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
+    const double2 pe = reinterpret_cast<const double2*>(p)[e];
+    const double2 qe = reinterpret_cast<const double2*>(q)[e];
+    double2 xe = reinterpret_cast<const double2*>(x)[e];
+    double2 re = reinterpret_cast<const double2*>(r)[e];
+    xe.x = fma(alpha, pe.x, xe.x);
+    xe.y = fma(alpha, pe.y, xe.y);
+    re.x = fma(-alpha, qe.x, re.x);
+    re.y = fma(-alpha, qe.y, re.y);
+    reinterpret_cast<double2*>(x)[e] = xe;
+    reinterpret_cast<double2*>(r)[e] = re;
+    if (r32) {
+      float2 o;
+      if (dsc) {
+        const double2 de = reinterpret_cast<const double2*>(dsc)[e];
+        o = make_float2((float)(re.x / de.x), (float)(re.y / de.y));
+      } else {
+        o = make_float2((float)re.x, (float)re.y);
+      }
+      reinterpret_cast<float2*>(r32)[e] = o;
+    }
+    a[0] = fma(re.x, re.x, a[0]);
+    a[0] = fma(re.y, re.y, a[0]);
+  }
+  if (n & 1) {  // odd length: last element by the first thread
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      const size_t e = n - 1;
+      x[e] = fma(alpha, p[e], x[e]);
+      const double re = fma(-alpha, q[e], r[e]);
+      r[e] = re;
+      if (r32) r32[e] = (float)(dsc ? re / dsc[e] : re);
+      a[0] = fma(re, re, a[0]);
+    }
   }
   block_sum<1>(a, lds);
   if (threadIdx.x == 0) partials[blockIdx.x] = a[0];
 }
 
-void launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, const double* p,
-                       const double* q, size_t n, double* partials, float* r32, const double* dsc) {
-  hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(kBlock), 0, s, dev, x, r, p, q, n, partials, r32,
-                     dsc);
+int launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, const double* p,
+                      const double* q, size_t n, double* partials, float* r32, const double* dsc) {
+  hipLaunchKernelGGL(k_fcg_update, dim3(kDotBlocks), dim3(kBlock), 0, s, dev, x, r, p, q, n, partials, r32, dsc);
   VP_LAUNCH_CHECK();
+  return kDotBlocks;
 }
 
 // The V-cycle's output to the Krylov solver: z = x (widened, divided by dsc if

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstddef>
 #include <type_traits>
 #include <cstdint>
@@ -199,6 +200,7 @@ struct vp_ctx_s {
   bool amg_struct = false;
   int amg_prec = 0;
   int cheb_degree = 3;
+  int tail_level = -1;             // first level run by the single-workgroup tail kernel
   double cheb_ratio = 30.0;
   int max_coarse = 140;
   int power_its_cold = 16, power_its_warm = 6;
@@ -265,9 +267,9 @@ void launch_gemv_add(hipStream_t s, const double* Z, size_t ld, int nz, const do
 void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, size_t n);
 void launch_scale_copy(hipStream_t s, const double* x, const double* scal, int invert,
                        double* y, size_t n);
-void launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, const double* p,
-                       const double* q, size_t n, double* partials, float* r32 = nullptr,
-                       const double* dsc = nullptr);
+int launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, const double* p,
+                      const double* q, size_t n, double* partials, float* r32 = nullptr,
+                      const double* dsc = nullptr);
 void launch_fcg_dir(hipStream_t s, double* dev, const double* z, double* p, size_t n, int first);
 void launch_cast(hipStream_t s, const double* x, float* y, size_t n);
 template <typename TX>

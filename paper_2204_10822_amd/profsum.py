@@ -2,11 +2,14 @@
 
     python -m paper_2204_10822_amd.profsum stats  <kernel_stats.csv>  [top]
     python -m paper_2204_10822_amd.profsum counter <counter_collection.csv> <COUNTER>
+    python -m paper_2204_10822_amd.profsum grids <kernel_trace.csv> [top]
 
 `stats` prints the top kernels by summed duration.  `counter` prints, per kernel
 name, the dispatch count and the mean value of one counter per dispatch (for
 FETCH_SIZE / WRITE_SIZE this is KiB per dispatch), plus the values seen for the
-device copy kernels used as a calibration of known size.
+device copy kernels used as a calibration of known size.  `grids` splits the
+kernel time by (kernel, grid size): on the AMG hierarchy the grid size names the
+level.
 """
 from __future__ import annotations
 
@@ -49,8 +52,25 @@ def counter(path: str, cname: str) -> None:
         print(f"{k[:58]:58s} {len(v):5d} {sum(v) / len(v):14.1f} {grids[k]:>10s}")
 
 
+def grids(path: str, top: int = 40) -> None:
+    acc = collections.defaultdict(lambda: [0, 0.0])
+    tot = 0.0
+    for r in csv.DictReader(open(path)):
+        d = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        k = (_short(r["Kernel_Name"]), r.get("Grid_Size", r.get("Grid_Size_X", "")))
+        acc[k][0] += 1
+        acc[k][1] += d
+        tot += d
+    print(f"{'kernel':50s} {'grid':>10s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>9s} {'pct':>6s}")
+    for (k, g), (n, t) in sorted(acc.items(), key=lambda kv: -kv[1][1])[:top]:
+        print(f"{k[:50]:50s} {g:>10s} {n:7d} {t / 1e6:10.3f} {t / n / 1e3:9.2f} {100 * t / tot:6.2f}")
+    print(f"total kernel time {tot / 1e6:.3f} ms")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25)
+    elif sys.argv[1] == "grids":
+        grids(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 40)
     else:
         counter(sys.argv[2], sys.argv[3])

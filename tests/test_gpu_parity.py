@@ -349,3 +349,29 @@ def test_galerkin_coarse_operators(vp, nx, ny, seed):
         err = np.linalg.norm(Ac - G) / np.linalg.norm(G)
         print(f"[galerkin] level {l}->{l + 1}: rel err {err:.2e}", flush=True)
         assert err < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 5])
+def test_vcycle_tail_kernel_matches_per_sweep_launches(vp, prec, monkeypatch):
+    """The single-workgroup kernel for the smallest levels runs the same per-node
+    arithmetic as the one-launch-per-sweep path: the V-cycle outputs are bitwise
+    equal (VP_AMG_TAIL=0 switches the single-workgroup kernel off at setup)."""
+    nx, ny, seed = 200, 150, 8
+    outs = []
+    for env in ("0", "1"):   # fresh contexts: identical spectral estimates
+        monkeypatch.setenv("VP_AMG_TAIL", env)
+        w, prob, ctx = _case(vp, nx, ny, seed)
+        v = _rand_v(prob, 3, 0.05)
+        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
+        rng = np.random.default_rng(4)
+        r = rng.standard_normal(2 * prob.mesh.nnode)
+        r[~prob.mesh.free_dof] = 0.0
+        n, a, k = vp.default_opts()
+        a.precision = prec
+        ctx.vp_amg_setup(a)
+        z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+        ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
+        outs.append(_host(z).ravel())
+    print(f"[tail] prec={prec} levels {ctx.vp_amg_info()} max |diff| {np.abs(outs[0] - outs[1]).max():.2e}",
+          flush=True)
+    assert np.array_equal(outs[0], outs[1])
