@@ -91,14 +91,26 @@ def counter_traffic(kernel_name):
     return 1024.0 * (fetch[kernel_name] * CALIB_READ_KIB / cal_f + write[kernel_name] * CALIB_WRITE_KIB / cal_w)
 
 
-KERNEL_NAMES = {  # profiled kernel id -> kernel name in the rocprofv3 summaries
-    ("cheb_step0", "fp64"): "k_cheb_step<2, double, double>",
-    ("cheb_step0", "fp32"): "k_cheb_step<2, float, float>",
-    ("sten_resid0", "fp64"): "k_sten_resid<2, double, double>",
-    ("sten_resid0", "fp32"): "k_sten_resid<2, float, float>",
-    ("apply_fine", "fp64"): "k_apply_fine",
-    ("apply_fine", "fp32"): "k_apply_fine",
-}
+_STORAGE = {"fp64": ("double", "double"), "fp32": ("float", "float"), "fp16": ("_Float16", "float"),
+            "bf16": ("__hip_bfloat16", "float")}
+
+
+def kernel_name(kid, kind):
+    """Name in the rocprofv3 summaries of the kernel behind a profiled kernel id."""
+    tm, tv = _STORAGE[kind]
+    return {"apply_fine": "k_apply_fine",
+            "cheb_step0": f"k_cheb_step<2, {tm}, {tv}>",
+            "sten_resid0": f"k_sten_resid<2, {tm}, {tv}>",
+            "cheb_pair0": (f"k_cheb_pair<0, 0, {tm}, {tv}, 128, 8, 256, 8>" if tv == "double"
+                           else f"k_cheb_pair<0, 0, {tm}, {tv}, 64, 16, 1024, 4>"),
+            "residual": "k_residual",
+            "assemble": "k_assemble"}.get(kid)
+
+
+def storage_kind(path):
+    """Finest-level operator storage of a benchmark path."""
+    p = PREC[path]
+    return "fp64" if p == 0 else "fp32" if p in (1, 2) else "bf16" if p == 3 else "fp16"
 
 
 def kernel_sequence(args, ctx, v, pi, torch, vp):
@@ -239,8 +251,7 @@ def main():
     single = {k: d for k, d in R["kernels"].items() if k != "vcycle" and d["bytes_per_launch"] > 0}
     dom = max(single, key=lambda k: single[k]["total_ms"])
     D = single[dom]
-    prec_kind = "fp64" if best == "fp64" else "fp32"
-    kname = KERNEL_NAMES.get((dom, prec_kind))
+    kname = kernel_name(dom, storage_kind(best))
     roof = dict(kernel=kname or dom, bound="hbm", achieved=D["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=D["gbs"] / HBM_PEAK_GBS, traffic=counter_traffic(kname) if kname else None,
                 bytes_per_launch=D["bytes_per_launch"], avg_us=D["avg_us"])

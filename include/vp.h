@@ -224,7 +224,8 @@ enum {
   VP_KID_RESIDUAL = 3,     /* nonlinear residual + energy                            */
   VP_KID_ASSEMBLE = 4,     /* operator assembly                                      */
   VP_KID_VCYCLE = 5,       /* one whole V-cycle (composite, not a single kernel)     */
-  VP_KID_COUNT = 6
+  VP_KID_CHEB_PAIR0 = 6,   /* two fused Chebyshev steps on the finest level          */
+  VP_KID_COUNT = 7
 };
 int vp_profile(vp_ctx ctx, int enable);
 int vp_profile_read(vp_ctx ctx, int kid, double* total_ms, int* launches, double* bytes_per_launch);

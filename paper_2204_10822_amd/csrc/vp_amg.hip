@@ -162,11 +162,11 @@ __device__ __forceinline__ void invert_block(const TA (&Din)[B][B], TA (&Di)[B][
   }
 }
 
-// (A x)_n for node (i, j) of the stencil
-template <int B, typename TM, typename TV, typename TA>
-__device__ __forceinline__ void stencil_row(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int i,
-                                            int j, const TV* __restrict__ x, TA (&y)[B],
-                                            TA (&D)[B][B]) {
+// (A x)_n for node (i, j) of the stencil; getx(m, ii, jj, xm) supplies the B
+// values of x at neighbour node m = (ii, jj) (global memory or a staged tile).
+template <int B, typename TM, typename TA, typename GetX>
+__device__ __forceinline__ void stencil_row_f(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int i, int j,
+                                              GetX getx, TA (&y)[B], TA (&D)[B][B]) {
 #pragma unroll
   for (int r = 0; r < B; ++r) y[r] = TA(0);
 #pragma unroll
@@ -183,12 +183,19 @@ __device__ __forceinline__ void stencil_row(const TM* __restrict__ A, size_t nn,
     }
     const size_t m = (size_t)jj * nxn + ii;
     TA xm[B];
-    load_node<B>(x, m, xm);
+    getx(m, ii, jj, xm);
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
       for (int c = 0; c < B; ++c) y[r] += blk[r][c] * xm[c];
   }
+}
+
+template <int B, typename TM, typename TV, typename TA>
+__device__ __forceinline__ void stencil_row(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int i,
+                                            int j, const TV* __restrict__ x, TA (&y)[B],
+                                            TA (&D)[B][B]) {
+  stencil_row_f<B>(A, nn, nxn, nyn, i, j, [&](size_t m, int, int, TA (&xm)[B]) { load_node<B>(x, m, xm); }, y, D);
 }
 
 }  // namespace
@@ -281,12 +288,12 @@ __device__ __forceinline__ void node_resid_first(const TM* __restrict__ A, size_
 }
 
 // Chebyshev step: r = rin - A dp; dn = cdd dp + cdr D^{-1} r;
-//   xmode 0: x += dn;  1: x = (x + dp) + dn;  2: x = dp + dn (x not read).
-// rin may equal rout.
+//   xmode 0: xout = xin + dn;  1: xout = (xin + dp) + dn;  2: xout = dp + dn (xin not read).
+// rin may equal rout and xin may equal xout.
 template <int B, typename TM, typename TV>
 __device__ __forceinline__ void node_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
                                                const TV* __restrict__ dp, const TV* rin, TV* rout,
-                                               TV* __restrict__ dn, TV* __restrict__ x,
+                                               TV* __restrict__ dn, const TV* xin, TV* xout,
                                                typename Acc<TV>::type cdd, typename Acc<TV>::type cdr, int xmode,
                                                size_t n) {
   using TA = typename Acc<TV>::type;
@@ -300,7 +307,7 @@ __device__ __forceinline__ void node_cheb_step(const TM* __restrict__ A, size_t 
 #pragma unroll
     for (int k = 0; k < B; ++k) xn[k] = dpn[k];
   } else {
-    load_node<B>(x, n, xn);
+    load_node<B>(xin, n, xn);
     if (xmode == 1) {
 #pragma unroll
       for (int k = 0; k < B; ++k) xn[k] += dpn[k];
@@ -318,7 +325,7 @@ __device__ __forceinline__ void node_cheb_step(const TM* __restrict__ A, size_t 
     xn[k] += dk[k];
   }
   store_node<B>(dn, n, dk);
-  store_node<B>(x, n, xn);
+  store_node<B>(xout, n, xn);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,10 +459,10 @@ k_resid_first(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* _
 template <int B, typename TM, typename TV>
 __global__ void __launch_bounds__(kBlock)
 k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ dp,
-            const TV* rin, TV* rout, TV* __restrict__ dn, TV* __restrict__ x, typename Acc<TV>::type cdd,
+            const TV* rin, TV* rout, TV* __restrict__ dn, const TV* xin, TV* xout, typename Acc<TV>::type cdd,
             typename Acc<TV>::type cdr, int xmode) {
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n < nn) node_cheb_step<B>(A, nn, nxn, nyn, dp, rin, rout, dn, x, cdd, cdr, xmode, n);
+  if (n < nn) node_cheb_step<B>(A, nn, nxn, nyn, dp, rin, rout, dn, xin, xout, cdd, cdr, xmode, n);
 }
 
 template <int B, typename TP, typename TV>
@@ -474,6 +481,151 @@ k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, in
               const TV* __restrict__ xc, TV* __restrict__ x) {
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
   if (n < nn) node_prolong_add<B>(P, nn, nxn, nyn, ncx, ncy, xc, x, n);
+}
+
+// ---------------------------------------------------------------------------
+// two smoother sweeps per pass on the finest level
+// ---------------------------------------------------------------------------
+// A pass covers a tile of kPairTX x kPairTY nodes.  The first sweep is evaluated
+// on the tile and a one-node ring around it (its results for the ring are what
+// the second sweep's stencil needs), kept in LDS; the second sweep then runs on
+// the tile and writes the outputs.  Each node's arithmetic is exactly that of the
+// single-sweep kernels (same per-node expressions, same storage type of every
+// intermediate), so the results are bitwise those of two launches, while the
+// intermediate direction, residual and iterate never travel through HBM.
+//   PAIR_STEP_STEP  : Chebyshev steps k and k+1.  vin = d_{k-1}, rin = residual
+//                     before step k, xin = iterate (not read for xmode1 = 2).
+//                     Out: residual, direction and iterate after step k+1.
+//   PAIR_STEP_RESID : Chebyshev step k, then the residual r - A d_k of
+//                     pre-smoothing.  Out: that residual and the iterate.
+//   PAIR_RFIRST_STEP: residual r = b - A x with the first correction
+//                     d0 = D^{-1} r / theta (vin = x, rin = b), then step 1
+//                     (xmode 1).  Out: residual, direction, iterate; xout must
+//                     not alias xin (neighbouring tiles still read x).
+// rin and rout, and vin and dout, must not alias (ring nodes of one tile are
+// interior nodes of another).
+enum { PAIR_STEP_STEP = 0, PAIR_STEP_RESID = 1, PAIR_RFIRST_STEP = 2 };
+constexpr int kPairTX = 64, kPairTY = 16, kPairThreads = 256;   // defaults; launch_pair picks per type
+
+template <int MODE, int XM, typename TM, typename TV, int TX = kPairTX, int TY = kPairTY, int NT = kPairThreads,
+          int WMAX = 8>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, WMAX)))
+k_cheb_pair(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, int tiles,
+            const TV* __restrict__ vin, const TV* __restrict__ rin, const TV* xin, TV* __restrict__ rout,
+            TV* __restrict__ dout, TV* xout, typename Acc<TV>::type c1a, typename Acc<TV>::type c1b,
+            typename Acc<TV>::type c2a, typename Acc<TV>::type c2b) {
+  constexpr int xmode1 = XM;   // xmode of the first sweep's Chebyshev step (STEP modes)
+  using TA = typename Acc<TV>::type;
+  constexpr int B = 2;
+  __shared__ TV s_d[(TX + 2) * (TY + 2)][B];   // first sweep's direction on the ringed tile
+  __shared__ TV s_r[(TX + 2) * (TY + 2)][B];   // first sweep's residual
+  const int tb = (int)xcd_block();
+  if (tb >= tiles) return;                   // whole workgroup
+  const int i0 = (tb % tiles_x) * TX, j0 = (tb / tiles_x) * TY;
+  // first sweep on the tile and its ring (loops kept rolled: the unrolled body
+  // would not fit the instruction cache)
+#pragma unroll 1
+  for (int k = threadIdx.x; k < (TX + 2) * (TY + 2); k += NT) {
+    const int i = i0 - 1 + k % (TX + 2), j = j0 - 1 + k / (TX + 2);
+    if (i < 0 || j < 0 || i >= nxn || j >= nyn) continue;
+    const size_t n = (size_t)j * nxn + i;
+    TA y[B], D[B][B], Di[B][B], rn[B], dk[B];
+    stencil_row<B>(A, nn, nxn, nyn, i, j, vin, y, D);
+    invert_block<B>(D, Di);
+    load_node<B>(rin, n, rn);
+#pragma unroll
+    for (int q = 0; q < B; ++q) rn[q] -= y[q];
+    if constexpr (MODE == PAIR_RFIRST_STEP) {
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        TA t = TA(0);
+#pragma unroll
+        for (int c = 0; c < B; ++c) t += Di[q][c] * rn[c];
+        dk[q] = t * c1a;
+      }
+    } else {
+      TA dpn[B];
+      load_node<B>(vin, n, dpn);
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        TA t = TA(0);
+#pragma unroll
+        for (int c = 0; c < B; ++c) t += Di[q][c] * rn[c];
+        dk[q] = c1a * dpn[q] + c1b * t;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      s_d[k][q] = (TV)dk[q];
+      s_r[k][q] = (TV)rn[q];
+    }
+  }
+  __syncthreads();
+  // second sweep on the tile
+#pragma unroll 1
+  for (int k = threadIdx.x; k < TX * TY; k += NT) {
+    const int li = k % TX, lj = k / TX;
+    const int i = i0 + li, j = j0 + lj;
+    if (i >= nxn || j >= nyn) continue;
+    const size_t n = (size_t)j * nxn + i;
+    const int lk = (lj + 1) * (TX + 2) + li + 1;
+    TA d1[B], r1[B], x1[B], y[B], D[B][B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      d1[q] = (TA)s_d[lk][q];
+      r1[q] = (TA)s_r[lk][q];
+    }
+    // iterate after the first sweep (as the single-sweep kernels store it)
+    if constexpr (MODE == PAIR_RFIRST_STEP) {
+      load_node<B>(xin, n, x1);                        // the first sweep leaves x unchanged
+    } else {
+      TA dpn[B];
+      load_node<B>(vin, n, dpn);
+      if constexpr (xmode1 == 2) {
+#pragma unroll
+        for (int q = 0; q < B; ++q) x1[q] = dpn[q];
+      } else {
+        load_node<B>(xin, n, x1);
+        if constexpr (xmode1 == 1) {
+#pragma unroll
+          for (int q = 0; q < B; ++q) x1[q] += dpn[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < B; ++q) x1[q] = (TA)(TV)(x1[q] + d1[q]);
+    }
+    stencil_row_f<B>(A, nn, nxn, nyn, i, j,
+                     [&](size_t, int ii, int jj, TA (&xm)[B]) {
+                       const int l = (jj - j0 + 1) * (TX + 2) + (ii - i0 + 1);
+#pragma unroll
+                       for (int q = 0; q < B; ++q) xm[q] = (TA)s_d[l][q];
+                     },
+                     y, D);
+    TA r2[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) r2[q] = r1[q] - y[q];
+    store_node<B>(rout, n, r2);
+    if constexpr (MODE == PAIR_STEP_RESID) {
+      store_node<B>(xout, n, x1);
+    } else {
+      TA Di[B][B], d2[B], x2[B];
+      invert_block<B>(D, Di);
+      if constexpr (MODE == PAIR_RFIRST_STEP) {
+#pragma unroll
+        for (int q = 0; q < B; ++q) x1[q] += d1[q];     // step 1 in xmode 1: (x + d0) + d1
+      }
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        TA t = TA(0);
+#pragma unroll
+        for (int c = 0; c < B; ++c) t += Di[q][c] * r2[c];
+        d2[q] = c2a * d1[q] + c2b * t;
+        x2[q] = x1[q] + d2[q];
+      }
+      store_node<B>(dout, n, d2);
+      store_node<B>(xout, n, x2);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -529,8 +681,8 @@ __device__ void tail_smooth(const TailLevel& L, const TV* b, TV* x, bool pre, in
     const int xmode = k > 1 ? 0 : pre ? 2 : 1;
     const TV* rin = (pre && k == 1) ? b : (const TV*)r;
     for (size_t n = t0; n < nn; n += nt)
-      node_cheb_step<3>(A, nn, L.nxn, L.nyn, (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], x, (TA)L.cdd[k],
-                        (TA)L.cdr[k], xmode, n);
+      node_cheb_step<3>(A, nn, L.nxn, L.nyn, (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], (const TV*)x, x,
+                        (TA)L.cdd[k], (TA)L.cdr[k], xmode, n);
     __syncthreads();
   }
   if (pre) {
@@ -1148,7 +1300,7 @@ void dfree(T*& p) {
 }
 
 void free_vectors(Level& L) {
-  void** v[5] = {&L.x, &L.b, &L.r, &L.d0, &L.d1};
+  void** v[7] = {&L.x, &L.b, &L.r, &L.d0, &L.d1, &L.r2, &L.x2};
   for (auto pp : v) {
     if (*pp) (void)hipFree(*pp);
     *pp = nullptr;
@@ -1247,6 +1399,10 @@ void alloc_vectors(vp_ctx c) {
     L.r = dalloc<TV>(n);
     L.d0 = dalloc<TV>(n);
     L.d1 = dalloc<TV>(n);
+    if (l == 0) {
+      L.r2 = dalloc<TV>(n);
+      L.x2 = dalloc<TV>(n);
+    }
   }
 }
 
@@ -1474,6 +1630,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       throw Error(VP_ENONFINITE, "AMG setup: non-finite or non-positive spectral bound");
   }
   c->tail_level = tail_start(c);
+  {
+    const char* env = std::getenv("VP_AMG_PAIRS");   // VP_AMG_PAIRS=0: one launch per sweep
+    c->pair_sweeps = !(env && env[0] == '0');
+  }
   c->amg_ready = true;
 }
 
@@ -1529,7 +1689,7 @@ void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bo
     const TV* rin = (pre && k == 1) ? b : (const TV*)r;
     const int pr = (l == 0 && xmode == 0) ? prof_begin(c, VP_KID_CHEB_STEP0) : -1;
     hipLaunchKernelGGL((k_cheb_step<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
-                       (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], x, (TA)cdd, (TA)cdr, xmode);
+                       (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], (const TV*)x, x, (TA)cdd, (TA)cdr, xmode);
     VP_LAUNCH_CHECK();
     prof_end(c, pr);
     rho = rn;
@@ -1584,6 +1744,123 @@ void launch_tail(vp_ctx c, int l0) {
   VP_LAUNCH_CHECK();
 }
 
+// Finest-level smoothing with the sweeps fused in pairs (k_cheb_pair); the same
+// sequence of per-node operations as smooth().  Pre-smoothing from x = 0 returns
+// the buffer holding r = b - A x; post-smoothing leaves x updated in place.
+// Tile shape and workgroup per value type (measured at 2049^2: FP32 vectors
+// 64 x 16 tiles, 1024 threads, at most 4 waves per SIMD; FP64 128 x 8, 256 threads).
+template <int MODE, int XM, typename TM, typename TV>
+void launch_pair(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV* rin, const TV* xin, TV* rout,
+                 TV* dout, TV* xout, double c1a, double c1b, double c2a, double c2b) {
+  using TA = typename Acc<TV>::type;
+  constexpr bool f64 = std::is_same<TV, double>::value;
+  constexpr int TX = f64 ? 128 : 64, TY = f64 ? 8 : 16, NT = f64 ? 256 : 1024, W = f64 ? 8 : 4;
+  const int tx = (L.nxn + TX - 1) / TX, ty = (L.nyn + TY - 1) / TY;
+  const int tiles = tx * ty;
+  const unsigned g = (unsigned)((tiles + 7) / 8 * 8);
+  hipLaunchKernelGGL((k_cheb_pair<MODE, XM, TM, TV, TX, TY, NT, W>), dim3(g), dim3(NT), 0, c->stream, A, L.nn, L.nxn,
+                     L.nyn, tx, tiles, vin, rin, xin, rout, dout, xout, (TA)c1a, (TA)c1b, (TA)c2a, (TA)c2b);
+  VP_LAUNCH_CHECK();
+}
+
+struct ChebCoef {
+  double inv_theta;
+  double cdd[32], cdr[32];   // index 1..degree-1
+};
+inline ChebCoef cheb_coefficients(double lmax_h, double ratio, int degree) {
+  ChebCoef k{};
+  const double lmax = lmax_h, lmin = lmax / ratio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  k.inv_theta = 1.0 / theta;
+  for (int s = 1; s < degree && s < 32; ++s) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    k.cdd[s] = rn * rho;
+    k.cdr[s] = 2.0 * rn / delta;
+    rho = rn;
+  }
+  return k;
+}
+
+template <typename TM, typename TV>
+const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x) {
+  using TA = typename Acc<TV>::type;
+  const int m = c->cheb_degree - 1;
+  const ChebCoef k = cheb_coefficients(L.lmax_h, c->cheb_ratio, c->cheb_degree);
+  TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
+  TV* rb[2] = {(TV*)L.r, (TV*)L.r2};
+  hipLaunchKernelGGL((k_cheb_first<2, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, b,
+                     (TV*)nullptr, d[0], (TV*)nullptr, (TA)k.inv_theta, 0);
+  VP_LAUNCH_CHECK();
+  const TV* rcur = b;
+  int di = 0, ri = 0;
+  for (int s = 1; s <= m;) {
+    if (s + 1 <= m) {
+      if (s == 1)
+        launch_pair<PAIR_STEP_STEP, 2>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], d[di ^ 1], x,
+                                       k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
+      else {
+        const int pr = prof_begin(c, VP_KID_CHEB_PAIR0);
+        launch_pair<PAIR_STEP_STEP, 0>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], d[di ^ 1], x,
+                                       k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
+        prof_end(c, pr);
+      }
+      rcur = rb[ri];
+      ri ^= 1;
+      di ^= 1;
+      s += 2;
+    } else {
+      if (s == 1)
+        launch_pair<PAIR_STEP_RESID, 2>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], (TV*)nullptr, x,
+                                        k.cdd[s], k.cdr[s], 0.0, 0.0);
+      else
+        launch_pair<PAIR_STEP_RESID, 0>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], (TV*)nullptr, x,
+                                        k.cdd[s], k.cdr[s], 0.0, 0.0);
+      return rb[ri];
+    }
+  }
+  // even number of steps: the final residual alone, in place
+  sten_resid<2>(c, 0, L, A, (const TV*)d[di], rcur, (TV*)rcur);
+  return rcur;
+}
+
+template <typename TM, typename TV>
+void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x) {
+  using TA = typename Acc<TV>::type;
+  const int m = c->cheb_degree - 1;
+  const ChebCoef k = cheb_coefficients(L.lmax_h, c->cheb_ratio, c->cheb_degree);
+  TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
+  TV* rb[2] = {(TV*)L.r, (TV*)L.r2};
+  TV* x2 = (TV*)L.x2;
+  launch_pair<PAIR_RFIRST_STEP, 1>(c, L, A, (const TV*)x, b, (const TV*)x, rb[0], d[1], x2, k.inv_theta, 0.0,
+                                   k.cdd[1], k.cdr[1]);
+  const TV* xcur = x2;
+  TV* rcur = rb[0];
+  int di = 1, ri = 1;
+  for (int s = 2; s <= m;) {
+    if (s + 1 <= m) {
+      const int pr = prof_begin(c, VP_KID_CHEB_PAIR0);
+      launch_pair<PAIR_STEP_STEP, 0>(c, L, A, (const TV*)d[di], (const TV*)rcur, xcur, rb[ri], d[di ^ 1], x,
+                                     k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
+      prof_end(c, pr);
+      rcur = rb[ri];
+      ri ^= 1;
+      di ^= 1;
+      s += 2;
+    } else {
+      hipLaunchKernelGGL((k_cheb_step<2, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, L.nxn,
+                         L.nyn, (const TV*)d[di], (const TV*)rcur, rcur, d[di ^ 1], xcur, x, (TA)k.cdd[s],
+                         (TA)k.cdr[s], 0);
+      VP_LAUNCH_CHECK();
+      di ^= 1;
+      s += 1;
+    }
+    xcur = x;
+  }
+  if (xcur != x) VP_HIP(hipMemcpyAsync(x, xcur, sizeof(TV) * 2 * L.nn, hipMemcpyDeviceToDevice, c->stream));
+}
+
 template <typename TV>
 void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
   hipStream_t s = c->stream;
@@ -1610,16 +1887,28 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     using TP = decltype(tp_tag);
     const TM* A = (const TM*)Av;
     const TP* P = (const TP*)Pv;
-    smooth<B, TM, TV>(c, l, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
+    const bool pairs = B == 2 && l == 0 && c->pair_sweeps && c->cheb_degree >= 2 && c->cheb_degree <= 32;
+    const TV* rres = (const TV*)L.r;
+    if constexpr (B == 2) {
+      if (pairs) rres = smooth_pre_pairs<TM, TV>(c, L, A, b, x);
+      else smooth<B, TM, TV>(c, l, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
+    } else {
+      smooth<B, TM, TV>(c, l, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
+    }
     hipLaunchKernelGGL((k_restrict<B, TP, TV>), dim3((unsigned)((N.nn * kRestrictLanes + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0,
-                       s, P, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)L.r, (TV*)N.b);
+                       s, P, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, rres, (TV*)N.b);
     VP_LAUNCH_CHECK();
     vcycle_level<TV>(c, l + 1, (const TV*)N.b, (TV*)N.x);
     hipLaunchKernelGGL((k_prolong_add<B, TP, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
                        L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
     VP_LAUNCH_CHECK();
-    smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
+    if constexpr (B == 2) {
+      if (pairs) smooth_post_pairs<TM, TV>(c, L, A, b, x);
+      else smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
+    } else {
+      smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
+    }
   };
   if constexpr (std::is_same<TV, double>::value) {
     if (L.B == 2) run(std::integral_constant<int, 2>(), double(), double(), L.A64, L.P64);

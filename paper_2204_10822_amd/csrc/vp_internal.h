@@ -159,6 +159,7 @@ struct Level {
   double lmax_h = 0.0;
   // V-cycle vectors, B*nn each, in the V-cycle precision
   void* x = nullptr; void* b = nullptr; void* r = nullptr; void* d0 = nullptr; void* d1 = nullptr;
+  void* r2 = nullptr; void* x2 = nullptr;   // second residual / iterate (finest level, paired sweeps)
   // coarsest level: dense inverse (row-major, ndof x ndof)
   double* Ainv64 = nullptr;
   float* Ainv32 = nullptr;
@@ -201,6 +202,7 @@ struct vp_ctx_s {
   int amg_prec = 0;
   int cheb_degree = 3;
   int tail_level = -1;             // first level run by the single-workgroup tail kernel
+  bool pair_sweeps = true;         // finest-level smoother sweeps fused in pairs
   double cheb_ratio = 30.0;
   int max_coarse = 140;
   int power_its_cold = 16, power_its_warm = 6;

@@ -19,7 +19,48 @@ import re
 import sys
 
 
+def _demangle_vp(name: str) -> str:
+    """Readable name for a mangled vp:: kernel template the profiler left mangled
+    (its demangler does not know _Float16, mangled DF16_)."""
+    m = re.match(r"_ZN2vp(?:3net)?(\d+)", name)
+    if not m:
+        return name
+    k = m.end()
+    ln = int(m.group(1))
+    ident = name[k:k + ln]
+    k += ln
+    if k >= len(name) or name[k] != "I":
+        return ident
+    k += 1
+    args = []
+    while k < len(name) and name[k] != "E":
+        if name.startswith("Li", k):
+            e = name.index("E", k)
+            args.append(name[k + 2:e])
+            k = e + 1
+        elif name.startswith("Lb", k):
+            args.append("true" if name[k + 2] == "1" else "false")
+            k = name.index("E", k) + 1
+        elif name.startswith("DF16_", k):
+            args.append("_Float16")
+            k += 5
+        elif name[k] in "fdi":
+            args.append({"f": "float", "d": "double", "i": "int"}[name[k]])
+            k += 1
+        elif name[k].isdigit():
+            mm = re.match(r"\d+", name[k:])
+            n = int(mm.group(0))
+            k += len(mm.group(0))
+            args.append(name[k:k + n])
+            k += n
+        else:
+            return ident + "<?>"
+    return f"{ident}<{', '.join(args)}>"
+
+
 def _short(name: str) -> str:
+    if name.startswith("_Z"):
+        return _demangle_vp(name)
     name = re.sub(r"\(.*$", "", name)           # drop the argument list
     name = name.replace("void ", "").replace("vp::", "")
     return name
