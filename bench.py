@@ -65,8 +65,11 @@ CALIB_READ_KIB, CALIB_WRITE_KIB = 2 << 20, 1 << 20   # the triad of kernel_seque
 
 def counter_traffic(kernel_name):
     """HBM bytes per launch of `kernel_name` from the committed FETCH_SIZE and
-    WRITE_SIZE summaries, each scaled by the counter's reading for the calibration
-    triad; None if a summary or the kernel is missing."""
+    WRITE_SIZE summaries: (calibrated, raw).  Calibrated scales each counter by its
+    reading for the calibration triad (FETCH_SIZE counts a read request as 64 B and
+    the triad's requests carry 128 B: factor 2); raw is the counters as read, a
+    lower bound for kernels whose requests carry 64 B.  (None, None) if a summary
+    or the kernel is missing."""
     def table(fname):
         path = os.path.join(PROFILES, fname)
         if not os.path.exists(path):
@@ -85,10 +88,12 @@ def counter_traffic(kernel_name):
     fetch = table("vp_sharp_2048_kernels_fetch_size.txt")
     write = table("vp_sharp_2048_kernels_write_size.txt")
     if not fetch or not write or kernel_name not in fetch or kernel_name not in write:
-        return None
+        return None, None
     cal_f = max(v for k, v in fetch.items() if "elementwise" in k)
     cal_w = max(v for k, v in write.items() if "elementwise" in k)
-    return 1024.0 * (fetch[kernel_name] * CALIB_READ_KIB / cal_f + write[kernel_name] * CALIB_WRITE_KIB / cal_w)
+    calibrated = 1024.0 * (fetch[kernel_name] * CALIB_READ_KIB / cal_f + write[kernel_name] * CALIB_WRITE_KIB / cal_w)
+    raw = 1024.0 * (fetch[kernel_name] + write[kernel_name])
+    return calibrated, raw
 
 
 _STORAGE = {"fp64": ("double", "double"), "fp32": ("float", "float"), "fp16": ("_Float16", "float"),
@@ -252,8 +257,9 @@ def main():
     dom = max(single, key=lambda k: single[k]["total_ms"])
     D = single[dom]
     kname = kernel_name(dom, storage_kind(best))
+    traffic, traffic_raw = counter_traffic(kname) if kname else (None, None)
     roof = dict(kernel=kname or dom, bound="hbm", achieved=D["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=D["gbs"] / HBM_PEAK_GBS, traffic=counter_traffic(kname) if kname else None,
+                frac=D["gbs"] / HBM_PEAK_GBS, traffic=traffic, traffic_raw_lower_bound=traffic_raw,
                 bytes_per_launch=D["bytes_per_launch"], avg_us=D["avg_us"])
     spmv = R["kernels"].get("apply_fine")
     out = {
