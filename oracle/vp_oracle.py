@@ -21,15 +21,17 @@ What it computes (paper sections / equations):
   * the Newton iteration with energy backtracking            Sec. 4, Sec. 5.1
 
 Discretisation choices where the paper is silent (each is a stated reading):
-  Q1 velocity on a uniform structured quad mesh with zero Dirichlet data on the
-  whole boundary; Q0 (cellwise constant) A, H and so P and rho*H; 2x2 Gauss
-  quadrature for every term (so the residual is the exact gradient of the
-  discrete energy); wind and ocean velocities as nodal Q1 fields interpolated to
+  Q1 velocity (or Q2 with desc.order = 2, Sec. 5) on a uniform structured quad
+  mesh with zero Dirichlet data on the whole boundary; Q0 (cellwise constant)
+  A, H and so P and rho*H; Gauss quadrature with 2x2 points for Q1 and 3x3 for Q2
+  for every term (so the residual is the exact gradient of the discrete energy);
+  wind and ocean velocities as nodal fields of the velocity space interpolated to
   quadrature points; the auxiliary stress pi stored per quadrature point.
 
-Array conventions: node vectors are [(ny+1)*(nx+1), 2] (node n = j*(nx+1)+i),
-dof index 2n+c.  pi is [4 qp, 3 comps (xx, yy, xy), ny, nx]; quadrature point q =
-qx + 2*qy with qx, qy = 0 for the lower and 1 for the upper Gauss point.
+Array conventions: node vectors are [nyn*nxn, 2] (node n = j*nxn+i; nxn = nx+1 for
+Q1, 2nx+1 for Q2), dof index 2n+c.  pi is [nq, 3 comps (xx, yy, xy), ny, nx]
+(nq = 4 or 9); quadrature point q = qx + k*qy (k = 2 or 3 points per direction,
+lower point first).
 Parity pins: every function here is pinned by tests in tests/test_oracle_*.py.
 """
 from __future__ import annotations
@@ -41,37 +43,57 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-# Gauss points of the 2-point rule on [0, 1].
+# Gauss rules on [0, 1]: 2 points (Q1) and 3 points (Q2).
 _G = (0.5 - 0.5 / math.sqrt(3.0), 0.5 + 0.5 / math.sqrt(3.0))
+_G3 = (0.5 - 0.5 * math.sqrt(0.6), 0.5, 0.5 + 0.5 * math.sqrt(0.6))
+_W3 = (5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0)
+
+
+def _lagrange1d(order, t):
+    """Values and derivatives of the 1-D Lagrange basis of the given order on [0, 1]
+    (nodes 0, 1 for order 1; 0, 1/2, 1 for order 2) at t."""
+    if order == 1:
+        return np.array([1.0 - t, t]), np.array([-1.0, 1.0])
+    return (np.array([2.0 * (t - 0.5) * (t - 1.0), -4.0 * t * (t - 1.0), 2.0 * t * (t - 0.5)]),
+            np.array([4.0 * t - 3.0, -8.0 * t + 4.0, 4.0 * t - 1.0]))
 
 
 class Mesh:
-    """Uniform structured mesh of [0,Lx]x[0,Ly] with nx x ny square-ish cells."""
+    """Uniform structured mesh of [0,Lx]x[0,Ly] with nx x ny cells and Q1 (order 1)
+    or Q2 (order 2, biquadratic: nodes at cell corners, edge midpoints and centres)
+    velocity elements (Sec. 5: Q1 by default, Q2 as the higher-order option)."""
 
-    def __init__(self, nx: int, ny: int, Lx: float, Ly: float):
+    def __init__(self, nx: int, ny: int, Lx: float, Ly: float, order: int = 1):
+        assert order in (1, 2)
+        self.order = order
         self.nx, self.ny, self.Lx, self.Ly = nx, ny, Lx, Ly
         self.hx, self.hy = Lx / nx, Ly / ny
-        self.nxn, self.nyn = nx + 1, ny + 1
+        self.nxn, self.nyn = order * nx + 1, order * ny + 1
         self.nnode = self.nxn * self.nyn
+        k = order + 1                      # nodes per direction in a cell
+        self.nen = k * k                   # element nodes
         jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
-        sw = jj * self.nxn + ii
-        # corners in the order SW, SE, NW, NE -> [4, ny, nx]
-        self.corners = np.stack([sw, sw + 1, sw + self.nxn, sw + self.nxn + 1])
+        base = (order * jj) * self.nxn + order * ii
+        # element node a = ax + k*ay at global node (order*i + ax, order*j + ay) -> [nen, ny, nx]
+        self.corners = np.stack([base + ay * self.nxn + ax for ay in range(k) for ax in range(k)])
         bj, bi = np.meshgrid(np.arange(self.nyn), np.arange(self.nxn), indexing="ij")
-        self.boundary = ((bi == 0) | (bi == nx) | (bj == 0) | (bj == ny)).ravel()
+        self.boundary = ((bi == 0) | (bi == self.nxn - 1) | (bj == 0) | (bj == self.nyn - 1)).ravel()
         self.free_dof = np.repeat(~self.boundary, 2)
-        # quadrature table: (weight, N[4], dN/dx[4], dN/dy[4]) per point q = qx+2qy
+        # quadrature table: (weight, N[nen], dN/dx[nen], dN/dy[nen]) per point q = qx + nq1*qy
+        pts, wts = (_G, (0.5, 0.5)) if order == 1 else (_G3, _W3)
         self.qp = []
-        for qy in range(2):
-            for qx in range(2):
-                xi, eta = _G[qx], _G[qy]
-                N = np.array([(1 - xi) * (1 - eta), xi * (1 - eta), (1 - xi) * eta, xi * eta])
-                dxi = np.array([-(1 - eta), (1 - eta), -eta, eta]) / self.hx
-                deta = np.array([-(1 - xi), -xi, (1 - xi), xi]) / self.hy
-                self.qp.append((0.25 * self.hx * self.hy, N, dxi, deta))
+        for qy in range(len(pts)):
+            for qx in range(len(pts)):
+                lx, dlx = _lagrange1d(order, pts[qx])
+                ly, dly = _lagrange1d(order, pts[qy])
+                N = np.array([lx[ax] * ly[ay] for ay in range(k) for ax in range(k)])
+                dx = np.array([dlx[ax] * ly[ay] for ay in range(k) for ax in range(k)]) / self.hx
+                dy = np.array([lx[ax] * dly[ay] for ay in range(k) for ax in range(k)]) / self.hy
+                self.qp.append((wts[qx] * wts[qy] * self.hx * self.hy, N, dx, dy))
+        self.nq = len(self.qp)
 
     def at_corners(self, nodal: np.ndarray) -> np.ndarray:
-        """nodal [nnode, k] -> [4, ny, nx, k]"""
+        """nodal [nnode, k] -> [nen, ny, nx, k] (values at each cell's element nodes)"""
         return nodal.reshape(self.nnode, -1)[self.corners]
 
     def interp(self, corner_vals: np.ndarray, q: int) -> np.ndarray:
@@ -184,7 +206,7 @@ class VPProblem:
     def __init__(self, desc, H, A, v_air, v_ocean, v_prev, extra_load=None):
         self.desc = desc
         self.prm = Params.from_desc(desc)
-        self.mesh = Mesh(desc.nx, desc.ny, desc.Lx, desc.Ly)
+        self.mesh = Mesh(desc.nx, desc.ny, desc.Lx, desc.Ly, getattr(desc, "order", 1))
         m = self.mesh
         self.H = np.asarray(H, float).reshape(m.ny, m.nx)
         self.A = np.asarray(A, float).reshape(m.ny, m.nx)
@@ -198,13 +220,13 @@ class VPProblem:
 
     # --- basis-function tensors per quadrature point -------------------------
     def _tables(self):
-        """For phi = N_a e_d: grad phi, eps(phi), tau(phi) per point: [4, 2, 2, 2]."""
+        """For phi = N_a e_d: grad phi, eps(phi), tau(phi) per point: [nen, 2, 2, 2]."""
         m, prm = self.mesh, self.prm
         self.grad_phi, self.eps_phi, self.tau_phi = [], [], []
-        for q in range(4):
+        for q in range(m.nq):
             _, N, dx, dy = m.qp[q]
-            Gp = np.zeros((4, 2, 2, 2))
-            for a in range(4):
+            Gp = np.zeros((m.nen, 2, 2, 2))
+            for a in range(m.nen):
                 for d in range(2):
                     Gp[a, d, d, 0] = dx[a]
                     Gp[a, d, d, 1] = dy[a]
@@ -214,10 +236,10 @@ class VPProblem:
             self.tau_phi.append(tau_of_strain(Ep, prm))
 
     def _scatter_vec(self, elem):
-        """element vectors [4, ny, nx, 2] -> node vector [nnode*2]."""
+        """element vectors [nen, ny, nx, 2] -> node vector [nnode*2]."""
         m = self.mesh
         out = np.zeros((m.nnode, 2))
-        for a in range(4):
+        for a in range(m.nen):
             np.add.at(out, m.corners[a].ravel(), elem[a].reshape(-1, 2))
         return out.ravel()
 
@@ -229,8 +251,8 @@ class VPProblem:
     # --- F(phi)  (eq. F) -------------------------------------------------------
     def load(self):
         m, prm = self.mesh, self.prm
-        elem = np.zeros((4, m.ny, m.nx, 2))
-        for q in range(4):
+        elem = np.zeros((m.nen, m.ny, m.nx, 2))
+        for q in range(m.nq):
             w, N, _, _ = m.qp[q]
             vn = m.interp(self.vn_c, q)
             vo = m.interp(self.vo_c, q)
@@ -247,8 +269,8 @@ class VPProblem:
     # --- A(v, phi) - F(phi)  (eq. A and eq. F) -------------------------------
     def residual(self, v, dirichlet=True):
         m, prm = self.mesh, self.prm
-        elem = np.zeros((4, m.ny, m.nx, 2))
-        for q in range(4):
+        elem = np.zeros((m.nen, m.ny, m.nx, 2))
+        for q in range(m.nq):
             w, N, _, _ = m.qp[q]
             vq, G = self.qp_state(v, q)
             E = strain_rate(G)
@@ -265,10 +287,10 @@ class VPProblem:
 
     # --- Phi(v)  (eq. energy) --------------------------------------------------
     def energy_terms(self, v):
-        """Per-cell energy density integrated by 2x2 Gauss: [ny, nx]."""
+        """Per-cell energy integrated by the element's Gauss rule: [ny, nx]."""
         m, prm = self.mesh, self.prm
         out = np.zeros((m.ny, m.nx))
-        for q in range(4):
+        for q in range(m.nq):
             w = m.qp[q][0]
             vq, G = self.qp_state(v, q)
             E = strain_rate(G)
@@ -294,14 +316,15 @@ class VPProblem:
 
     # --- linearised operators ---------------------------------------------------
     def _assemble(self, elem):
-        """element matrices [ny, nx, 4, 2, 4, 2] -> CSR with identity Dirichlet rows/cols."""
+        """element matrices [ny, nx, nen, 2, nen, 2] -> CSR with identity Dirichlet rows/cols."""
         m = self.mesh
-        dof = (2 * m.corners[:, :, :, None] + np.arange(2)).transpose(1, 2, 0, 3)  # [ny,nx,4,2]
-        dof = dof.reshape(m.ny, m.nx, 8)
-        rows = np.broadcast_to(dof[:, :, :, None], (m.ny, m.nx, 8, 8)).ravel()
-        cols = np.broadcast_to(dof[:, :, None, :], (m.ny, m.nx, 8, 8)).ravel()
+        ne = 2 * m.nen
+        dof = (2 * m.corners[:, :, :, None] + np.arange(2)).transpose(1, 2, 0, 3)  # [ny,nx,nen,2]
+        dof = dof.reshape(m.ny, m.nx, ne)
+        rows = np.broadcast_to(dof[:, :, :, None], (m.ny, m.nx, ne, ne)).ravel()
+        cols = np.broadcast_to(dof[:, :, None, :], (m.ny, m.nx, ne, ne)).ravel()
         n = 2 * m.nnode
-        K = sp.coo_matrix((elem.reshape(m.ny, m.nx, 8, 8).ravel(), (rows, cols)), shape=(n, n)).tocsr()
+        K = sp.coo_matrix((elem.reshape(m.ny, m.nx, ne, ne).ravel(), (rows, cols)), shape=(n, n)).tocsr()
         f = m.free_dof.astype(float)
         Df = sp.diags(f)
         K = (Df @ K @ Df + sp.diags(1.0 - f)).tocsr()
@@ -327,13 +350,13 @@ class VPProblem:
     def jacobian_std(self, v):
         """Standard Newton operator (eq. standardNewton1, standardNewton2)."""
         m, prm = self.mesh, self.prm
-        elem = np.zeros((m.ny, m.nx, 4, 2, 4, 2))
-        for q in range(4):
+        elem = np.zeros((m.ny, m.nx, m.nen, 2, m.nen, 2))
+        for q in range(m.nq):
             w = m.qp[q][0]
             _, G = self.qp_state(v, q)
             T = tau_of_strain(strain_rate(G), prm)
             D = delta_of_tau(T, prm)
-            Tp = self.tau_phi[q]                               # [4,2,2,2]
+            Tp = self.tau_phi[q]                               # [nen,2,2,2]
             tt = np.einsum("adij,bfij->adbf", Tp, Tp)          # tau(phi_b):tau(phi_a)
             Tl = np.einsum("yxij,adij->yxad", T, Tp)           # tau_l : tau(phi)
             c1 = prm.dt * self.P / D
@@ -348,9 +371,9 @@ class VPProblem:
         replaced by (tau_l (x) pi_l + pi_l (x) tau_l) / (2 max(1, sqrt(2 pi:pi)))
         (eq. modification), where (X (x) Y) Z = (X:Z) Y."""
         m, prm = self.mesh, self.prm
-        elem = np.zeros((m.ny, m.nx, 4, 2, 4, 2))
+        elem = np.zeros((m.ny, m.nx, m.nen, 2, m.nen, 2))
         PI = pi_tensor(pi)
-        for q in range(4):
+        for q in range(m.nq):
             w = m.qp[q][0]
             _, G = self.qp_state(v, q)
             T = tau_of_strain(strain_rate(G), prm)
@@ -376,8 +399,8 @@ class VPProblem:
     def pi_consistent(self, v):
         """pi = tau(v)/Delta(v) at every quadrature point (eq. pi)."""
         m, prm = self.mesh, self.prm
-        out = np.zeros((4, 3, m.ny, m.nx))
-        for q in range(4):
+        out = np.zeros((m.nq, 3, m.ny, m.nx))
+        for q in range(m.nq):
             _, G = self.qp_state(v, q)
             T = tau_of_strain(strain_rate(G), prm)
             X = T / delta_of_tau(T, prm)[..., None, None]
@@ -388,9 +411,9 @@ class VPProblem:
         """Dual Newton step from eq. tautilde with the modification of eq. modification:
         pi~ = -pi_l + tau_l/D + tau(dv)/D - [(tau_l:tau(dv)) pi_l + (pi_l:tau(dv)) tau_l]/(D^2 s)."""
         m, prm = self.mesh, self.prm
-        out = np.zeros((4, 3, m.ny, m.nx))
+        out = np.zeros((m.nq, 3, m.ny, m.nx))
         PI = pi_tensor(pi)
-        for q in range(4):
+        for q in range(m.nq):
             _, G = self.qp_state(v, q)
             _, Gd = self.qp_state(dv, q)
             T = tau_of_strain(strain_rate(G), prm)
@@ -405,7 +428,7 @@ class VPProblem:
 
 
 def pi_tensor(pi):
-    """[4, 3, ny, nx] (xx, yy, xy) -> [4, ny, nx, 2, 2] symmetric tensors."""
+    """[nq, 3, ny, nx] (xx, yy, xy) -> [nq, ny, nx, 2, 2] symmetric tensors."""
     pi = np.asarray(pi, float)
     T = np.empty(pi.shape[:1] + pi.shape[2:] + (2, 2))
     T[..., 0, 0] = pi[:, 0]

@@ -12,7 +12,8 @@ paper's own analytic Problem I fields (Sec. 5.2) are also provided.
 
 Layouts (all numpy float64, C order):
   cell fields   H, A          [ny][nx]
-  node fields   v_air, v_ocean, v_prev   [ny+1][nx+1][2]   (x component first)
+  node fields   v_air, v_ocean, v_prev   [ny+1][nx+1][2]   (x component first);
+                [2ny+1][2nx+1][2] for Q2 velocity elements (desc.order = 2)
 """
 from __future__ import annotations
 
@@ -47,6 +48,7 @@ class ProblemDesc:
     f_coriolis: float = 1.46e-4
     dt: float = 1800.0
     delta_min: float = 2e-9
+    order: int = 1          # velocity elements: 1 = Q1, 2 = Q2 (biquadratic), Sec. 5
 
     def replace(self, **kw) -> "ProblemDesc":
         return dataclasses.replace(self, **kw)
@@ -168,19 +170,20 @@ class Workload:
 def synthetic(n: int, seed: int, h_range=(0.1, 2.0), a_range=(0.7, 1.0),
               wind_max: float = 15.0, delta_min: float = 2e-9, t: float = 0.0,
               name: str = "synthetic", f_coriolis: float = 1.46e-4, ny: int | None = None,
-              Ly: float | None = None) -> Workload:
-    """Seeded workload on an n x ny mesh (ny defaults to n) of a 512 km x Ly domain."""
+              Ly: float | None = None, order: int = 1) -> Workload:
+    """Seeded workload on an n x ny mesh (ny defaults to n) of a 512 km x Ly domain;
+    node fields on the nodes of Q1 (order 1) or Q2 (order 2) velocity elements."""
     nx = n
     ny = n if ny is None else ny
-    desc = ProblemDesc(nx=nx, ny=ny, delta_min=delta_min, f_coriolis=f_coriolis)
+    desc = ProblemDesc(nx=nx, ny=ny, delta_min=delta_min, f_coriolis=f_coriolis, order=order)
     if Ly is not None:
         desc = desc.replace(Ly=Ly)
     H = smooth_field(seed, nx, ny, desc.Lx, desc.Ly, *h_range)
     A = smooth_field(seed + 1000, nx, ny, desc.Lx, desc.Ly, *a_range)
     vs = make_vortices(seed + 2000, desc.Lx, desc.Ly)
-    va = vortex_wind(vs, nx, ny, desc.Lx, desc.Ly, wind_max, t)
-    vo = ocean_gyre(nx, ny, desc.Lx, desc.Ly, 0.1)
-    vp = np.zeros((ny + 1, nx + 1, 2))
+    va = vortex_wind(vs, order * nx, order * ny, desc.Lx, desc.Ly, wind_max, t)
+    vo = ocean_gyre(order * nx, order * ny, desc.Lx, desc.Ly, 0.1)
+    vp = np.zeros((order * ny + 1, order * nx + 1, 2))
     return Workload(name, desc, H, A, va, vo, vp, vs, wind_max)
 
 
@@ -206,11 +209,11 @@ def advance_wind(w: Workload, t: float) -> np.ndarray:
     return vortex_wind(w.vortices, d.nx, d.ny, d.Lx, d.Ly, w.wind_max, t)
 
 
-def problem_one(n: int = 512) -> Workload:
+def problem_one(n: int = 512, order: int = 1) -> Workload:
     """The paper's Problem I (Sec. 5.2): analytic A, H = 2A, constant wind
     (5, 5) m/s, no ocean current, zero Coriolis, delta_min = 2e-9.
     r_1 is taken as printed (its last term is not squared)."""
-    desc = ProblemDesc(nx=n, ny=n, f_coriolis=0.0, delta_min=2e-9)
+    desc = ProblemDesc(nx=n, ny=n, f_coriolis=0.0, delta_min=2e-9, order=order)
     X, Y = cell_centres(n, n, desc.Lx, desc.Ly)
     xk, yk = X / 1e6, Y / 1e6  # in units of 1000 km
     r = 0.04 - (xk - 0.25) ** 2 - (yk - 0.25) ** 2
@@ -218,11 +221,13 @@ def problem_one(n: int = 512) -> Workload:
     A = 1.0 - 0.5 * np.exp(-800.0 * np.abs(r)) - 0.4 * np.exp(-90.0 * np.abs(r1)) \
         - 0.4 * np.exp(-90.0 * np.abs(r1 + 0.7))
     H = 2.0 * A
-    va = np.zeros((n + 1, n + 1, 2))
+    m = order * n + 1
+    va = np.zeros((m, m, 2))
     va[..., 0] = 5.0
     va[..., 1] = 5.0
-    vo = np.zeros((n + 1, n + 1, 2))
-    return Workload(f"problem_one_{n}", desc, H, A, va, vo, np.zeros_like(vo), None, 5.0)
+    vo = np.zeros((m, m, 2))
+    return Workload(f"problem_one_{n}" + ("_q2" if order == 2 else ""), desc, H, A, va, vo, np.zeros_like(vo),
+                    None, 5.0)
 
 
 DAY = 86400.0
@@ -252,15 +257,17 @@ def problem_two_wind(n: int, t: float, Lx: float = 512e3, Ly: float = 512e3) -> 
     return w
 
 
-def problem_two(n: int = 128, delta_min: float = 2e-9) -> Workload:
+def problem_two(n: int = 128, delta_min: float = 2e-9, order: int = 1) -> Workload:
     """Initial state and forcing of the paper's Problem II (Sec. 5.3), the
     time-dependent benchmark: A = 1, H = 0.3 m + 0.005 m (sin(60 x/1000 km) +
     sin(30 y/1000 km)), v = 0, ocean gyre of 0.01 m/s, the moving cyclone at t = 0,
     no Coriolis term (Table tab:params)."""
-    desc = ProblemDesc(nx=n, ny=n, f_coriolis=0.0, delta_min=delta_min)
+    desc = ProblemDesc(nx=n, ny=n, f_coriolis=0.0, delta_min=delta_min, order=order)
     X, Y = cell_centres(n, n, desc.Lx, desc.Ly)
     H = 0.3 + 0.005 * (np.sin(60.0 * X / 1e6) + np.sin(30.0 * Y / 1e6))
     A = np.ones((n, n))
-    va = problem_two_wind(n, 0.0, desc.Lx, desc.Ly)
-    vo = ocean_gyre(n, n, desc.Lx, desc.Ly, 0.01)
-    return Workload(f"problem_two_{n}", desc, H, A, va, vo, np.zeros((n + 1, n + 1, 2)), None, 15.0)
+    va = problem_two_wind(order * n, 0.0, desc.Lx, desc.Ly)
+    vo = ocean_gyre(order * n, order * n, desc.Lx, desc.Ly, 0.01)
+    m = order * n + 1
+    return Workload(f"problem_two_{n}" + ("_q2" if order == 2 else ""), desc, H, A, va, vo, np.zeros((m, m, 2)),
+                    None, 15.0)
