@@ -43,7 +43,8 @@ extern "C" {
 
 /* Mesh, physics constants (Table tab:params) and step settings (Sec. 5.2/5.3). */
 typedef struct {
-  int32_t nx, ny;          /* cells per side; nodes (nx+1)(ny+1)                    */
+  int32_t nx, ny;          /* cells per side; nodes (nx+1)(ny+1) for Q1 velocity,    */
+                           /* (2nx+1)(2ny+1) for Q2                                 */
   double Lx, Ly;           /* domain size [m]                                       */
   double rho_ice, rho_air, rho_ocean;  /* densities [kg/m^3]                        */
   double C_air, C_ocean;   /* drag coefficients                                     */
@@ -53,6 +54,12 @@ typedef struct {
   double f_coriolis;       /* Coriolis parameter [1/s], explicit (Sec. 3 footnote)  */
   double dt;               /* time step [s]                                         */
   double delta_min;        /* Delta_min [1/s] (eq. Delta)                           */
+  int32_t order;           /* velocity elements: 1 (or 0) = Q1 with 2x2 Gauss, 2 = Q2 */
+                           /* (biquadratic, 3x3 Gauss; Sec. 5).  With Q2 the          */
+                           /* operator is a block 25-point stencil, pi has 9 points   */
+                           /* per cell, and the AMG preconditioner is built on the    */
+                           /* standard-Newton Q1 operator of the 2nx x 2ny refined    */
+                           /* mesh, which has the same nodes                          */
 } vp_problem_desc;
 
 typedef struct vp_ctx_s* vp_ctx;
@@ -202,11 +209,13 @@ int vp_newton_solve(vp_ctx ctx, double* v, double* pi, int maxit,
 /* One explicit Euler step (Sec. 3) of the transport equations eq. model:A and
  * eq. model:H for the cell fields A and H, finite volumes on the cells (Q0, Sec. 5)
  * with the mesh and time step of the context: the normal velocity of a face is
- * the mean of its two nodal values of v, the flux is first-order upwind, the
+ * the mean of its two nodal values of v (Q1; Simpson's rule on the face's end and
+ * midpoint nodes for Q2 velocity), the flux is first-order upwind, the
  * boundary carries no flux (v = 0 there, so the inflow values never enter).  A is
  * clipped to [0, 1] and H to [0, inf) afterwards.  Positivity needs
  * dt (max|u|/hx + max|v|/hy) <= 1 (not checked).
- *  v: device nodes [(ny+1)(nx+1)][2]; A, H, A_out, H_out: device cells [ny][nx].
+ *  v: device nodes [(ny+1)(nx+1)][2] (Q2: [(2ny+1)(2nx+1)][2]); A, H, A_out, H_out:
+ *  device cells [ny][nx].
  * Asynchronous on the context's stream.  VP_EINVAL for null pointers or outputs
  * that alias an input or each other. */
 int vp_advect(vp_ctx ctx, const double* v, const double* A, const double* H, double* A_out, double* H_out);

@@ -11,7 +11,8 @@ the structured mesh and the Q1 velocity v:
   F_f = (v . n_f) |f| Q_up,
 
 where v . n_f is the mean of the normal velocity along the face (the mean of the
-face's two nodal values, exact for Q1) and Q_up is the value of the cell the flow
+face's two nodal values, exact for Q1; Simpson's rule on the face's three nodes for
+Q2) and Q_up is the value of the cell the flow
 comes from (first-order upwind).  The velocity vanishes on the boundary (zero
 Dirichlet condition), so boundary faces carry no flux and the inflow values of
 Sec. 2 never enter.  Readings: faces whose mean normal velocity is exactly 0 take
@@ -23,12 +24,21 @@ from __future__ import annotations
 import numpy as np
 
 
-def face_velocities(v, nx, ny):
+def face_velocities(v, nx, ny, order=1):
     """Mean normal velocity on the vertical faces ux [ny][nx+1] (face between
-    cells i-1 and i of row j at x = i hx) and horizontal faces uy [ny+1][nx]."""
-    V = np.asarray(v, dtype=np.float64).reshape(ny + 1, nx + 1, 2)
-    ux = 0.5 * (V[:-1, :, 0] + V[1:, :, 0])
-    uy = 0.5 * (V[:, :-1, 1] + V[:, 1:, 1])
+    cells i-1 and i of row j at x = i hx) and horizontal faces uy [ny+1][nx].
+    Q1 velocity: the mean of the face's two end values.  Q2 velocity (nodes at the
+    face's ends and midpoint): Simpson's rule, exact for the quadratic trace."""
+    if order == 1:
+        V = np.asarray(v, dtype=np.float64).reshape(ny + 1, nx + 1, 2)
+        ux = 0.5 * (V[:-1, :, 0] + V[1:, :, 0])
+        uy = 0.5 * (V[:, :-1, 1] + V[:, 1:, 1])
+    else:
+        V = np.asarray(v, dtype=np.float64).reshape(2 * ny + 1, 2 * nx + 1, 2)
+        Vx = V[:, ::2, 0]                      # columns at cell faces x = i hx
+        ux = (Vx[0:-1:2] + 4.0 * Vx[1::2] + Vx[2::2]) / 6.0
+        Vy = V[::2, :, 1]                      # rows at cell faces y = j hy
+        uy = (Vy[:, 0:-1:2] + 4.0 * Vy[:, 1::2] + Vy[:, 2::2]) / 6.0
     ux[:, 0] = 0.0
     ux[:, nx] = 0.0
     uy[0, :] = 0.0
@@ -52,10 +62,11 @@ def upwind_fluxes(Q, ux, uy, hx, hy):
     return Fx, Fy
 
 
-def advect(v, A, H, nx, ny, Lx, Ly, dt, clip=True):
-    """One explicit upwind step of A and H ([ny][nx] arrays) with velocity v."""
+def advect(v, A, H, nx, ny, Lx, Ly, dt, clip=True, order=1):
+    """One explicit upwind step of A and H ([ny][nx] arrays) with velocity v (Q1 or
+    Q2 nodal values)."""
     hx, hy = Lx / nx, Ly / ny
-    ux, uy = face_velocities(v, nx, ny)
+    ux, uy = face_velocities(v, nx, ny, order)
     out = []
     for Q in (np.asarray(A, dtype=np.float64).reshape(ny, nx), np.asarray(H, dtype=np.float64).reshape(ny, nx)):
         Fx, Fy = upwind_fluxes(Q, ux, uy, hx, hy)

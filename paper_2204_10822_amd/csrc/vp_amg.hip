@@ -191,11 +191,59 @@ __device__ __forceinline__ void stencil_row_f(const TM* __restrict__ A, size_t n
   }
 }
 
-template <int B, typename TM, typename TV, typename TA>
+// (A x)_n of the symmetric block 25-point stencil of Q2 elements (ST = 1, B = 2):
+// the 13 stored blocks of node n times x at their offsets, plus the transposes of
+// the blocks stored at n - o for the 12 non-self offsets o.
+template <typename TM, typename TA, typename GetX>
+__device__ __forceinline__ void stencil_row25_f(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int i, int j,
+                                                GetX getx, TA (&y)[2], TA (&D)[2][2]) {
+  y[0] = y[1] = TA(0);
+  const size_t n = (size_t)j * nxn + i;
+#pragma unroll
+  for (int d = 0; d < 13; ++d) {
+    const int ox = q2_ox(d), oy = q2_oy(d);
+    {
+      const int ii = i + ox, jj = j + oy;
+      if (ii >= 0 && ii < nxn && jj < nyn) {
+        TA v[4];
+        load_raw<2>(A + aidx(2, nn, d, n, 0, 0), v);
+        if (d == 0) {
+          D[0][0] = v[0]; D[0][1] = v[1]; D[1][0] = v[2]; D[1][1] = v[3];
+        }
+        TA xm[2];
+        getx((size_t)jj * nxn + ii, ii, jj, xm);
+        y[0] += v[0] * xm[0] + v[1] * xm[1];
+        y[1] += v[2] * xm[0] + v[3] * xm[1];
+      }
+    }
+    if (d > 0) {
+      const int ii = i - ox, jj = j - oy;
+      if (ii >= 0 && ii < nxn && jj >= 0) {
+        const size_t m = (size_t)jj * nxn + ii;
+        TA v[4];
+        load_raw<2>(A + aidx(2, nn, d, m, 0, 0), v);
+        TA xm[2];
+        getx(m, ii, jj, xm);
+        y[0] += v[0] * xm[0] + v[2] * xm[1];
+        y[1] += v[1] * xm[0] + v[3] * xm[1];
+      }
+    }
+  }
+}
+
+// (A x)_n: ST = 0 the block 9-point stencil of every AMG level, ST = 1 the
+// 25-point stencil of Q2 elements on the finest level
+template <int B, int ST = 0, typename TM, typename TV, typename TA>
 __device__ __forceinline__ void stencil_row(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int i,
                                             int j, const TV* __restrict__ x, TA (&y)[B],
                                             TA (&D)[B][B]) {
-  stencil_row_f<B>(A, nn, nxn, nyn, i, j, [&](size_t m, int, int, TA (&xm)[B]) { load_node<B>(x, m, xm); }, y, D);
+  if constexpr (ST == 1) {
+    static_assert(B == 2, "the 25-point stencil has 2x2 blocks");
+    stencil_row25_f<TM, TA>(A, nn, nxn, nyn, i, j, [&](size_t m, int, int, TA (&xm)[2]) { load_node<2>(x, m, xm); },
+                            y, D);
+  } else {
+    stencil_row_f<B>(A, nn, nxn, nyn, i, j, [&](size_t m, int, int, TA (&xm)[B]) { load_node<B>(x, m, xm); }, y, D);
+  }
 }
 
 }  // namespace
@@ -209,13 +257,13 @@ __device__ __forceinline__ void stencil_row(const TM* __restrict__ A, size_t nn,
 // same bodies over the nodes, so both give identical results.
 
 // r = b - A x at node n (b may be null: r = -A x); in-place r == b is allowed.
-template <int B, typename TM, typename TV>
+template <int B, typename TM, typename TV, int ST = 0>
 __device__ __forceinline__ void node_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
                                                 const TV* __restrict__ x, const TV* b, TV* r, size_t n) {
   using TA = typename Acc<TV>::type;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   TA y[B], D[B][B], bb[B];
-  stencil_row<B>(A, nn, nxn, nyn, i, j, x, y, D);
+  stencil_row<B, ST>(A, nn, nxn, nyn, i, j, x, y, D);
   if (b) load_node<B>(b, n, bb);
 #pragma unroll
   for (int k = 0; k < B; ++k) bb[k] = (b ? bb[k] : TA(0)) - y[k];
@@ -263,7 +311,7 @@ __device__ __forceinline__ void node_cheb_first(const TM* __restrict__ A, size_t
 // Residual and first Chebyshev step of post-smoothing in one sweep:
 // r = b - A x, d = D^{-1} r * inv_theta.  x itself is not updated here (its
 // neighbours are still being read); the following step adds d (xmode 1).
-template <int B, typename TM, typename TV>
+template <int B, typename TM, typename TV, int ST = 0>
 __device__ __forceinline__ void node_resid_first(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
                                                  const TV* __restrict__ x, const TV* __restrict__ b,
                                                  TV* __restrict__ r, TV* __restrict__ d,
@@ -271,7 +319,7 @@ __device__ __forceinline__ void node_resid_first(const TM* __restrict__ A, size_
   using TA = typename Acc<TV>::type;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   TA y[B], D[B][B], Di[B][B], rn[B], dk[B];
-  stencil_row<B>(A, nn, nxn, nyn, i, j, x, y, D);
+  stencil_row<B, ST>(A, nn, nxn, nyn, i, j, x, y, D);
   invert_block<B>(D, Di);
   load_node<B>(b, n, rn);
 #pragma unroll
@@ -290,7 +338,7 @@ __device__ __forceinline__ void node_resid_first(const TM* __restrict__ A, size_
 // Chebyshev step: r = rin - A dp; dn = cdd dp + cdr D^{-1} r;
 //   xmode 0: xout = xin + dn;  1: xout = (xin + dp) + dn;  2: xout = dp + dn (xin not read).
 // rin may equal rout and xin may equal xout.
-template <int B, typename TM, typename TV>
+template <int B, typename TM, typename TV, int ST = 0>
 __device__ __forceinline__ void node_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
                                                const TV* __restrict__ dp, const TV* rin, TV* rout,
                                                TV* __restrict__ dn, const TV* xin, TV* xout,
@@ -299,7 +347,7 @@ __device__ __forceinline__ void node_cheb_step(const TM* __restrict__ A, size_t 
   using TA = typename Acc<TV>::type;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   TA y[B], D[B][B], Di[B][B], rn[B], dpn[B], xn[B], dk[B];
-  stencil_row<B>(A, nn, nxn, nyn, i, j, dp, y, D);
+  stencil_row<B, ST>(A, nn, nxn, nyn, i, j, dp, y, D);
   invert_block<B>(D, Di);
   load_node<B>(rin, n, rn);
   load_node<B>(dp, n, dpn);
@@ -412,11 +460,11 @@ __device__ __forceinline__ void row_dense_apply(const TM* __restrict__ M, int nd
 }
 
 // ---- one thread per node ----------------------------------------------------
-template <int B, typename TM, typename TV>
+template <int B, typename TM, typename TV, int ST = 0>
 __global__ void __launch_bounds__(kBlock)
 k_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ x, const TV* b, TV* r) {
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n < nn) node_sten_resid<B>(A, nn, nxn, nyn, x, b, r, n);
+  if (n < nn) node_sten_resid<B, TM, TV, ST>(A, nn, nxn, nyn, x, b, r, n);
 }
 
 // y = A x (FP64 finest level), partial sums of x.y per workgroup (for CG)
@@ -447,22 +495,22 @@ k_cheb_first(const TM* __restrict__ A, size_t nn, const TV* __restrict__ src, TV
   if (n < nn) node_cheb_first<B>(A, nn, src, r, d, x, inv_theta, add, n);
 }
 
-template <int B, typename TM, typename TV>
+template <int B, typename TM, typename TV, int ST = 0>
 __global__ void __launch_bounds__(kBlock)
 k_resid_first(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ x,
               const TV* __restrict__ b, TV* __restrict__ r, TV* __restrict__ d,
               typename Acc<TV>::type inv_theta) {
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n < nn) node_resid_first<B>(A, nn, nxn, nyn, x, b, r, d, inv_theta, n);
+  if (n < nn) node_resid_first<B, TM, TV, ST>(A, nn, nxn, nyn, x, b, r, d, inv_theta, n);
 }
 
-template <int B, typename TM, typename TV>
+template <int B, typename TM, typename TV, int ST = 0>
 __global__ void __launch_bounds__(kBlock)
 k_cheb_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ dp,
             const TV* rin, TV* rout, TV* __restrict__ dn, const TV* xin, TV* xout, typename Acc<TV>::type cdd,
             typename Acc<TV>::type cdr, int xmode) {
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n < nn) node_cheb_step<B>(A, nn, nxn, nyn, dp, rin, rout, dn, xin, xout, cdd, cdr, xmode, n);
+  if (n < nn) node_cheb_step<B, TM, TV, ST>(A, nn, nxn, nyn, dp, rin, rout, dn, xin, xout, cdd, cdr, xmode, n);
 }
 
 template <int B, typename TP, typename TV>
@@ -889,7 +937,7 @@ __global__ void k_power_init(double* __restrict__ x, size_t n) {
   }
 }
 
-template <int B>
+template <int B, int ST = 0>
 __global__ void __launch_bounds__(kBlock)
 k_power_step(const double* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
              const double* __restrict__ nrm2_in, double* __restrict__ y, double* __restrict__ partials) {
@@ -900,7 +948,7 @@ k_power_step(const double* __restrict__ A, size_t nn, int nxn, int nyn, const do
     const int i = (int)(n % nxn), j = (int)(n / nxn);
     const double s = nrm2_in[0] > 0.0 ? 1.0 / sqrt(nrm2_in[0]) : 0.0;
     double Ax[B], D[B][B], Di[B][B];
-    stencil_row<B>(A, nn, nxn, nyn, i, j, x, Ax, D);
+    stencil_row<B, ST>(A, nn, nxn, nyn, i, j, x, Ax, D);
     invert_block<B>(D, Di);
     for (int r = 0; r < B; ++r) {
       double t = 0.0;

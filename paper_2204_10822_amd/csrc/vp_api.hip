@@ -109,6 +109,15 @@ void ensure_krylov(vp_ctx c, int restart) {
 // ---------------------------------------------------------------------------
 // FGMRES(m), right preconditioned, CGS2 with one host synchronisation per iteration
 // ---------------------------------------------------------------------------
+}  // namespace
+
+void vp::launch_apply_K(vp_ctx c, const double* x, double* y, double* partials) {
+  if (c->order == 2) launch_q2_apply(c, x, y, partials);
+  else launch_apply_fine(c->stream, c->lev[0], x, y, partials);
+}
+
+namespace {
+
 int fgmres(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov_info* info) {
   const size_t n = c->ndof;
   const int m = o.restart;
@@ -128,7 +137,7 @@ int fgmres(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_kry
   double rel = 1.0;
   while (true) {
     // r0 = b - K x  -> V0 = r0 / |r0|
-    launch_apply_fine(s, c->lev[0], x, w, nullptr);
+    launch_apply_K(c, x, w, nullptr);
     launch_axpby(s, 1.0, b, -1.0, w, n);
     const double beta = norm2(c, w, n);
     rel = beta / bnorm;
@@ -143,7 +152,7 @@ int fgmres(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_kry
       double* zj = Z + (size_t)j * n;
       amg_apply(c, vj, zj);
       const int pr = prof_begin(c, VP_KID_APPLY_FINE);
-      launch_apply_fine(s, c->lev[0], zj, w, nullptr);
+      launch_apply_K(c, zj, w, nullptr);
       prof_end(c, pr);
       const int nv = j + 1;
       // pass 1: h1 = V^T w
@@ -203,7 +212,7 @@ int fgmres(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_kry
     VP_HIP(hipStreamSynchronize(s));
     if (done || total >= o.maxit) {
       // true residual for the report
-      launch_apply_fine(s, c->lev[0], x, w, nullptr);
+      launch_apply_K(c, x, w, nullptr);
       launch_axpby(s, 1.0, b, -1.0, w, n);
       rel = norm2(c, w, n) / bnorm;
       break;
@@ -231,7 +240,7 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
     launch_fill(s, x, 0.0, n);
     return VP_OK;
   }
-  launch_apply_fine(s, c->lev[0], x, r, nullptr);
+  launch_apply_K(c, x, r, nullptr);
   launch_axpby(s, 1.0, b, -1.0, r, n);
   double rel = norm2(c, r, n) / bnorm;
   int it = 0;
@@ -243,7 +252,7 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
     launch_fcg_dir(s, c->dscal, z, p, n, 1);
     while (it < o.maxit) {
       const int pr = prof_begin(c, VP_KID_APPLY_FINE);
-      launch_apply_fine(s, c->lev[0], p, q, c->partials);  // q = K p, p.q
+      launch_apply_K(c, p, q, c->partials);  // q = K p, p.q
       prof_end(c, pr);
       finish(c, (int)grid_for(c->lev[0].nn), 1, 1);
       nb = launch_fcg_update(s, c->dscal, x, r, p, q, n, c->partials, r32, dsc);
@@ -372,7 +381,9 @@ int newton_step(vp_ctx c, double* v, double* pi, const vp_newton_opts& no, const
 void check_desc(const vp_problem_desc* d) {
   require(d != nullptr, VP_EINVAL, "null problem description");
   require(d->nx >= 2 && d->ny >= 2, VP_EINVAL, "nx and ny must be >= 2");
-  require((int64_t)(d->nx + 1) * (d->ny + 1) < (int64_t)1 << 31, VP_EINVAL, "mesh too large");
+  require(d->order >= 0 && d->order <= 2, VP_EINVAL, "order must be 1 (Q1) or 2 (Q2)");
+  const int64_t o = d->order == 2 ? 2 : 1;
+  require((o * d->nx + 1) * (o * d->ny + 1) < (int64_t)1 << 31, VP_EINVAL, "mesh too large");
   require(d->Lx > 0 && d->Ly > 0 && d->dt > 0 && d->delta_min > 0 && d->e_ratio > 0, VP_EINVAL,
           "Lx, Ly, dt, delta_min and e_ratio must be positive");
   require(d->P_star >= 0 && d->rho_ice > 0 && d->rho_air >= 0 && d->rho_ocean >= 0 && d->C_air >= 0 &&
@@ -402,8 +413,10 @@ int vp_create(const vp_problem_desc* desc, void* stream, vp_ctx* out) {
       c->desc = *desc;
       c->stream = (hipStream_t)stream;
       VP_HIP(hipGetDevice(&c->device));
+      c->order = desc->order == 2 ? 2 : 1;
       ElemConst& e = c->ec;
-      e.nx = desc->nx; e.ny = desc->ny; e.nxn = desc->nx + 1; e.nyn = desc->ny + 1;
+      e.nx = desc->nx; e.ny = desc->ny;
+      e.nxn = c->order * desc->nx + 1; e.nyn = c->order * desc->ny + 1;
       e.hx = desc->Lx / desc->nx; e.hy = desc->Ly / desc->ny; e.wq = 0.25 * e.hx * e.hy;
       e.dt = desc->dt; e.dmin2 = desc->delta_min * desc->delta_min;
       e.c1 = 0.5 * (1.0 + 1.0 / desc->e_ratio); e.c2 = 0.5 * (1.0 - 1.0 / desc->e_ratio);
@@ -423,6 +436,16 @@ int vp_create(const vp_problem_desc* desc, void* stream, vp_ctx* out) {
       c->work = dalloc<double>(5 * c->ndof);
       c->lev[0].A64 = dalloc<double>(20 * c->nn);
       c->lev[0].nxn = e.nxn; c->lev[0].nyn = e.nyn; c->lev[0].B = 2; c->lev[0].nn = c->nn;
+      if (c->order == 2) {
+        // the refined Q1 mesh (same nodes) whose standard-Newton operator builds the AMG
+        ElemConst& r = c->ec1;
+        r = e;
+        r.nx = 2 * e.nx; r.ny = 2 * e.ny;
+        r.hx = 0.5 * e.hx; r.hy = 0.5 * e.hy; r.wq = 0.25 * r.hx * r.hy;
+        c->P1 = dalloc<double>(4 * c->ncell);
+        c->rhoH1 = dalloc<double>(4 * c->ncell);
+        c->K2 = dalloc<double>((size_t)52 * c->nn);
+      }
     } catch (...) {
       vp_destroy(c);
       throw;
@@ -438,7 +461,8 @@ void vp_destroy(vp_ctx c) {
   double* K = c->lev[0].A64;
   amg_free(c);
   if (K) (void)hipFree(K);
-  void* bufs[] = {c->P, c->rhoH, c->F, c->vo, c->partials, c->dscal, c->work, c->kv, c->dense};
+  void* bufs[] = {c->P, c->rhoH, c->F, c->vo, c->partials, c->dscal, c->work, c->kv, c->dense, c->P1, c->rhoH1,
+                  c->K2};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->hscal) (void)hipHostFree(c->hscal);
@@ -494,7 +518,7 @@ int vp_operator_apply(vp_ctx c, const double* x, double* y) {
   return guarded(c, [&] {
     require(c != nullptr && x && y, VP_EINVAL, "null argument");
     require(c->have_K, VP_ESTATE, "no assembled operator");
-    launch_apply_fine(c->stream, c->lev[0], x, y, nullptr);
+    launch_apply_K(c, x, y, nullptr);
     return VP_OK;
   });
 }
@@ -503,8 +527,11 @@ int vp_operator_export(vp_ctx c, double* blocks) {
   return guarded(c, [&] {
     require(c != nullptr && blocks, VP_EINVAL, "null argument");
     require(c->have_K, VP_ESTATE, "no assembled operator");
-    VP_HIP(hipMemcpyAsync(blocks, c->lev[0].A64, 20 * c->nn * sizeof(double), hipMemcpyDeviceToDevice,
-                          c->stream));
+    if (c->order == 2)
+      VP_HIP(hipMemcpyAsync(blocks, c->K2, 52 * c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    else
+      VP_HIP(hipMemcpyAsync(blocks, c->lev[0].A64, 20 * c->nn * sizeof(double), hipMemcpyDeviceToDevice,
+                            c->stream));
     return VP_OK;
   });
 }

@@ -147,9 +147,13 @@ void launch_precompute(vp_ctx c, const double* H, const double* A, const double*
   hipLaunchKernelGGL(k_cell_coeffs, dim3((unsigned)((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      c->stream, c->ec, H, A, c->P, c->rhoH);
   VP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_load_vector, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec,
-                     c->rhoH, va, vo, vprev, c->F);
-  VP_LAUNCH_CHECK();
+  if (c->order == 2) {
+    launch_q2_precompute(c, va, vo, vprev);
+  } else {
+    hipLaunchKernelGGL(k_load_vector, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec,
+                       c->rhoH, va, vo, vprev, c->F);
+    VP_LAUNCH_CHECK();
+  }
   VP_HIP(hipMemcpyAsync(c->vo, vo, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
 }
 
@@ -229,6 +233,10 @@ k_residual(ElemConst c, const double* __restrict__ v, const double* __restrict__
 
 void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, double* r,
                      double* partials, unsigned* nblocks) {
+  if (c->order == 2) {
+    launch_q2_residual(c, v, dv, alpha, r, partials, nblocks);
+    return;
+  }
   const unsigned g = grid_for(c->nn);
   hipLaunchKernelGGL(k_residual, dim3(g), dim3(kBlock), 0, c->stream, c->ec, v, dv, alpha, c->vo,
                      c->F, c->P, c->rhoH, r, partials);
@@ -368,7 +376,17 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
   }
 }
 
+// K receives the Q1 operator; with Q2 elements the Krylov operator goes to c->K2 and
+// K receives the preconditioner's operator: the standard-Newton Q1 Jacobian of the
+// refined mesh (same nodes, cells halved, cell fields copied to the four children).
 void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, double* K) {
+  if (c->order == 2) {
+    launch_q2_assemble(c, v, pi, variant);
+    hipLaunchKernelGGL(k_assemble, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec1, v,
+                       (const double*)nullptr, (int)VP_STDN, c->vo, c->P1, c->rhoH1, K);
+    VP_LAUNCH_CHECK();
+    return;
+  }
   hipLaunchKernelGGL(k_assemble, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec, v, pi,
                      variant, c->vo, c->P, c->rhoH, K);
   VP_LAUNCH_CHECK();
@@ -430,12 +448,20 @@ __global__ void k_pi_init(ElemConst c, const double* __restrict__ v, double* __r
 }
 
 void launch_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha) {
+  if (c->order == 2) {
+    launch_q2_pi_update(c, v, dv, pi, alpha);
+    return;
+  }
   hipLaunchKernelGGL(k_pi_update, dim3((unsigned)((c->ncell + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, c->stream, c->ec, v, dv, pi, alpha);
   VP_LAUNCH_CHECK();
 }
 
 void launch_pi_init(vp_ctx c, const double* v, double* pi) {
+  if (c->order == 2) {
+    launch_q2_pi_init(c, v, pi);
+    return;
+  }
   hipLaunchKernelGGL(k_pi_init, dim3((unsigned)((c->ncell + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      c->stream, c->ec, v, pi);
   VP_LAUNCH_CHECK();
@@ -445,25 +471,38 @@ void launch_pi_init(vp_ctx c, const double* v, double* pi) {
 // transport of A and H (eq. model:A, eq. model:H): one explicit Euler step
 // (Sec. 3) of cell-wise constant fields (finite volumes, Sec. 5) with the Q1
 // velocity.  Face normal velocity = mean of the face's two nodal values (exact
-// for Q1), first-order upwind flux (v.n)|f| Q_up, no flux through the boundary
+// for Q1; Simpson's rule on the face's end and midpoint nodes for Q2), first-order
+// upwind flux (v.n)|f| Q_up, no flux through the boundary
 // (v = 0 there).  Each face flux is evaluated by both adjacent cells with the
 // same operands, so the update is conservative.  A is clipped to [0, 1] and H to
 // [0, inf).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 k_advect(const double* __restrict__ v, const double* __restrict__ A, const double* __restrict__ H, int nx,
-         int ny, double hx, double hy, double dt, double* __restrict__ Ao, double* __restrict__ Ho) {
+         int ny, int order, double hx, double hy, double dt, double* __restrict__ Ao, double* __restrict__ Ho) {
   const size_t c = (size_t)xcd_block() * blockDim.x + threadIdx.x;
   if (c >= (size_t)nx * ny) return;
   const int i = (int)(c % nx), j = (int)(c / nx);
-  const size_t nxn = (size_t)nx + 1;
   const double2* V = reinterpret_cast<const double2*>(v);
-  const double2 v00 = V[(size_t)j * nxn + i], v10 = V[(size_t)j * nxn + i + 1];
-  const double2 v01 = V[(size_t)(j + 1) * nxn + i], v11 = V[(size_t)(j + 1) * nxn + i + 1];
-  const double uw = i > 0 ? 0.5 * (v00.x + v01.x) : 0.0;
-  const double ue = i < nx - 1 ? 0.5 * (v10.x + v11.x) : 0.0;
-  const double us = j > 0 ? 0.5 * (v00.y + v10.y) : 0.0;
-  const double un = j < ny - 1 ? 0.5 * (v01.y + v11.y) : 0.0;
+  double uw, ue, us, un;
+  if (order == 2) {
+    // Q2 velocity: Simpson's rule on each face's end and midpoint nodes
+    const size_t nxn = (size_t)2 * nx + 1;
+    auto at = [&](int I, int J) { return V[(size_t)J * nxn + I]; };
+    const int I0 = 2 * i, J0 = 2 * j;
+    uw = i > 0 ? (at(I0, J0).x + 4.0 * at(I0, J0 + 1).x + at(I0, J0 + 2).x) / 6.0 : 0.0;
+    ue = i < nx - 1 ? (at(I0 + 2, J0).x + 4.0 * at(I0 + 2, J0 + 1).x + at(I0 + 2, J0 + 2).x) / 6.0 : 0.0;
+    us = j > 0 ? (at(I0, J0).y + 4.0 * at(I0 + 1, J0).y + at(I0 + 2, J0).y) / 6.0 : 0.0;
+    un = j < ny - 1 ? (at(I0, J0 + 2).y + 4.0 * at(I0 + 1, J0 + 2).y + at(I0 + 2, J0 + 2).y) / 6.0 : 0.0;
+  } else {
+    const size_t nxn = (size_t)nx + 1;
+    const double2 v00 = V[(size_t)j * nxn + i], v10 = V[(size_t)j * nxn + i + 1];
+    const double2 v01 = V[(size_t)(j + 1) * nxn + i], v11 = V[(size_t)(j + 1) * nxn + i + 1];
+    uw = i > 0 ? 0.5 * (v00.x + v01.x) : 0.0;
+    ue = i < nx - 1 ? 0.5 * (v10.x + v11.x) : 0.0;
+    us = j > 0 ? 0.5 * (v00.y + v10.y) : 0.0;
+    un = j < ny - 1 ? 0.5 * (v01.y + v11.y) : 0.0;
+  }
   const double s = dt / (hx * hy);
   const double* Q[2] = {A, H};
   double out[2];
@@ -483,7 +522,7 @@ k_advect(const double* __restrict__ v, const double* __restrict__ A, const doubl
 
 void launch_advect(vp_ctx c, const double* v, const double* A, const double* H, double* Ao, double* Ho) {
   hipLaunchKernelGGL(k_advect, dim3(grid_for(c->ncell)), dim3(kBlock), 0, c->stream, v, A, H, c->ec.nx, c->ec.ny,
-                     c->ec.hx, c->ec.hy, c->ec.dt, Ao, Ho);
+                     c->order, c->ec.hx, c->ec.hy, c->ec.dt, Ao, Ho);
   VP_LAUNCH_CHECK();
 }
 

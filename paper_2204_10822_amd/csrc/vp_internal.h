@@ -114,6 +114,11 @@ __host__ __device__ __forceinline__ size_t pidx(int B, size_t nn, int s, size_t 
   return (size_t)((s * B + r) * 3 + c) * nn + n;
 }
 
+// Symmetric block 25-point stencil of Q2 elements: 13 stored blocks per node, the
+// self block (dir 0) and the forward offsets (1,0), (2,0), (-2..2, 1), (-2..2, 2).
+__host__ __device__ constexpr int q2_ox(int dir) { return dir == 0 ? 0 : dir <= 2 ? dir : (dir - 3) % 5 - 2; }
+__host__ __device__ constexpr int q2_oy(int dir) { return dir <= 2 ? 0 : (dir - 3) / 5 + 1; }
+
 // bf16 storage helpers (round to nearest even)
 __device__ __forceinline__ float ld(const float* p) { return *p; }
 __device__ __forceinline__ double ld(const double* p) { return *p; }
@@ -184,6 +189,16 @@ struct vp_ctx_s {
   int device = 0;
   vp::ElemConst ec{};
   size_t nn = 0, ncell = 0, ndof = 0;
+  int order = 1;                   // velocity elements: 1 = Q1, 2 = Q2
+  vp::ElemConst ec1{};             // Q2: the Q1 refined mesh of the preconditioner
+  double* P1 = nullptr;            // Q2: cell fields on the refined mesh [4*ncell]
+  double* rhoH1 = nullptr;
+  double* K2 = nullptr;            // Q2: the operator, 13 blocks per node
+  float* K2_32 = nullptr;          // Q2: FP32 copy for the V-cycle's finest level
+  double* lmax_q2 = nullptr;       // Q2: lmax(D^{-1} K2) for the finest smoother (device)
+  double lmax_q2_h = 0.0;
+  double *pq0 = nullptr, *pq1 = nullptr, *pqn = nullptr;  // Q2: its power-iteration vectors
+  bool pq_warm = false;
   std::string err;
   // state
   double* P = nullptr;      // [ncell]
@@ -254,6 +269,16 @@ void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, d
 void launch_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
 void launch_pi_init(vp_ctx c, const double* v, double* pi);
 void launch_advect(vp_ctx c, const double* v, const double* A, const double* H, double* Ao, double* Ho);
+// Q2 velocity elements
+void launch_q2_precompute(vp_ctx c, const double* va, const double* vo, const double* vprev);
+void launch_q2_residual(vp_ctx c, const double* v, const double* dv, double alpha, double* r, double* partials,
+                        unsigned* nblocks);
+void launch_q2_assemble(vp_ctx c, const double* v, const double* pi, int variant);
+void launch_q2_apply(vp_ctx c, const double* x, double* y, double* partials);
+void launch_q2_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
+void launch_q2_pi_init(vp_ctx c, const double* v, double* pi);
+// the Krylov operator of the context: the Q1 stencil in lev[0], or the Q2 operator
+void launch_apply_K(vp_ctx c, const double* x, double* y, double* partials);
 
 // reductions / BLAS-1 (vector length n doubles)
 void launch_finish_sum(hipStream_t s, const double* partials, int nblocks, int K, double* out);

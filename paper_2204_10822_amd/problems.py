@@ -30,12 +30,11 @@ PREC = {"fp64": vp.VP_PREC_FP64, "fp32": vp.VP_PREC_FP32, "bf16": vp.VP_PREC_FP3
 
 
 def run_problem_one(n: int, variant: str, precision: str = "fp64", tol: float = 1e-4, maxit: int = 200,
-                    warmup: bool = True) -> dict:
-    w = inputs.problem_one(n)
+                    warmup: bool = True, order: int = 1) -> dict:
+    w = inputs.problem_one(n, order)
     ctx = vp.context_for(w)
-    nn = (n + 1) ** 2
-    v = torch.zeros(nn, 2, dtype=torch.float64, device="cuda")
-    pi = torch.zeros(4, 3, n, n, dtype=torch.float64, device="cuda")
+    v = torch.zeros(ctx.node_shape, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(ctx.pi_shape, dtype=torch.float64, device="cuda")
     no, ao, ko = vp.default_opts()
     no.variant = vp.VP_SVN if variant == "svn" else vp.VP_STDN
     no.tol = tol
@@ -54,7 +53,7 @@ def run_problem_one(n: int, variant: str, precision: str = "fp64", tol: float = 
         solve()
     rc, info, hist, dt = solve()
     ctx.close()
-    return dict(problem="problem_one", n=n, dx_km=512.0 / n, variant=variant, precision=precision,
+    return dict(problem="problem_one", n=n, order=order, dx_km=512.0 / n, variant=variant, precision=precision,
                 tol=tol, maxit=maxit, rc=rc, converged=info.rel_resid <= tol,
                 newton_its=info.iterations, krylov_its=info.krylov_iters, rel_resid=info.rel_resid,
                 seconds=dt, history=[float(h) for h in hist])
@@ -71,30 +70,31 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--maxit", type=int, default=200)
     ap.add_argument("--no-warmup", action="store_true")
+    ap.add_argument("--order", type=int, default=1, choices=[1, 2], help="velocity elements: Q1 or Q2")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     for n in [int(x) for x in args.n.split(",") if x]:
         for var in [x for x in args.variants.split(",") if x]:
             if args.problem == "one":
-                r = run_problem_one(n, var, args.precision, args.tol, args.maxit, not args.no_warmup)
+                r = run_problem_one(n, var, args.precision, args.tol, args.maxit, not args.no_warmup, args.order)
             else:
-                r = run_problem_two(n, args.steps, var, args.precision, args.tol, args.maxit, args.delta_min)
+                r = run_problem_two(n, args.steps, var, args.precision, args.tol, args.maxit, args.delta_min,
+                                    args.order)
             print(json.dumps(r), flush=True)
 
 
 
 def run_problem_two(n: int, steps: int, variant: str = "svn", precision: str = "fp64", tol: float = 1e-4,
-                    maxit: int = 200, delta_min: float = 2e-9) -> dict:
+                    maxit: int = 200, delta_min: float = 2e-9, order: int = 1) -> dict:
     """The paper's Problem II (Sec. 5.3) for `steps` half-hour steps: each step
     advances A and H explicitly with the previous velocity (Sec. 3), then solves
     the momentum step from the previous (v, pi) until the residual has dropped by
     `tol` relative to its value at that start (the paper's 10^4 reduction)."""
-    w = inputs.problem_two(n, delta_min)
+    w = inputs.problem_two(n, delta_min, order)
     ctx = vp.context_for(w)
     st = ctx._state
-    nn = (n + 1) ** 2
-    v = torch.zeros(nn, 2, dtype=torch.float64, device="cuda")
-    pi = torch.zeros(4, 3, n, n, dtype=torch.float64, device="cuda")
+    v = torch.zeros(ctx.node_shape, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(ctx.pi_shape, dtype=torch.float64, device="cuda")
     zero = torch.zeros_like(v)
     A, H = st["A"].clone(), st["H"].clone()
     A2, H2 = torch.empty_like(A), torch.empty_like(H)
@@ -107,7 +107,7 @@ def run_problem_two(n: int, steps: int, variant: str = "svn", precision: str = "
     for k in range(steps):
         ctx.vp_advect(v, A, H, A2, H2)
         A, A2, H, H2 = A2, A, H2, H
-        va = vp.to_device(inputs.problem_two_wind(n, (k + 1) * w.desc.dt).reshape(-1, 2))
+        va = vp.to_device(inputs.problem_two_wind(order * n, (k + 1) * w.desc.dt).reshape(-1, 2))
         ctx.vp_set_state(H, A, va, st["v_ocean"], v)
         r_start, _ = ctx.vp_residual(v)
         r_zero, _ = ctx.vp_residual(zero)
@@ -121,7 +121,8 @@ def run_problem_two(n: int, steps: int, variant: str = "svn", precision: str = "
                   f"mean {sum(its) / len(its):.2f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out = dict(problem="problem_two", n=n, dx_km=512.0 / n, steps=steps, variant=variant, precision=precision,
+    out = dict(problem="problem_two", n=n, order=order, dx_km=512.0 / n, steps=steps, variant=variant,
+               precision=precision,
                delta_min=delta_min, tol=tol, mean_newton=sum(its) / len(its), max_newton=max(its),
                total_krylov=sum(kits), failed_steps=fails, seconds=dt, newton_per_step=its,
                A_mean=float(A.mean()), H_mean=float(H.mean()))

@@ -40,7 +40,7 @@ class vp_problem_desc(C.Structure):
                 ("rho_ice", C.c_double), ("rho_air", C.c_double), ("rho_ocean", C.c_double),
                 ("C_air", C.c_double), ("C_ocean", C.c_double), ("P_star", C.c_double),
                 ("C_strength", C.c_double), ("e_ratio", C.c_double), ("f_coriolis", C.c_double),
-                ("dt", C.c_double), ("delta_min", C.c_double)]
+                ("dt", C.c_double), ("delta_min", C.c_double), ("order", C.c_int32)]
 
 
 class vp_amg_opts(C.Structure):
@@ -157,7 +157,7 @@ def _ptr(t, shape, name):
 def desc_from(d) -> vp_problem_desc:
     return vp_problem_desc(d.nx, d.ny, d.Lx, d.Ly, d.rho_ice, d.rho_air, d.rho_ocean, d.C_air,
                            d.C_ocean, d.P_star, d.C_strength, d.e_ratio, d.f_coriolis, d.dt,
-                           d.delta_min)
+                           d.delta_min, int(getattr(d, "order", 1)))
 
 
 class Context:
@@ -166,9 +166,11 @@ class Context:
     def __init__(self, desc, stream=None):
         self.desc = desc
         self.nx, self.ny = desc.nx, desc.ny
-        self.node_shape = ((desc.ny + 1) * (desc.nx + 1), 2)
+        self.order = int(getattr(desc, "order", 1))
+        o = self.order
+        self.node_shape = ((o * desc.ny + 1) * (o * desc.nx + 1), 2)
         self.cell_shape = (desc.ny, desc.nx)
-        self.pi_shape = (4, 3, desc.ny, desc.nx)
+        self.pi_shape = (4 if o == 1 else 9, 3, desc.ny, desc.nx)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -220,8 +222,10 @@ class Context:
                                                  _ptr(y, self.node_shape, "y")))
 
     def vp_operator_export(self, blocks):
-        n = (self.nx + 1) * (self.ny + 1)
-        return self._check(LIB.vp_operator_export(self.h, _ptr(blocks, (20, n), "blocks")))
+        """blocks: [5 or 13 stored blocks x 4 values, nodes] (Q1 / Q2), layout [blk][node][r][c]."""
+        n = self.node_shape[0]
+        nb = 20 if self.order == 1 else 52
+        return self._check(LIB.vp_operator_export(self.h, _ptr(blocks, (nb, n), "blocks")))
 
     def vp_amg_setup(self, opts=None):
         if opts is None:

@@ -97,3 +97,22 @@ def test_clipping_bounds():
     v = _vel(rng, nx, ny, 1.0)
     A1, H1 = T.advect(v, A, H, nx, ny, L, L, 1800.0)
     assert A1.max() <= 1.0 and A1.min() >= 0.0 and H1.min() >= 0.0
+
+
+def test_q2_face_means_are_exact_for_quadratic_traces():
+    """With Q2 velocity the face mean uses the face's end and midpoint values and is
+    the exact mean of a quadratic trace: u = (1 + y/Ly)^2 on vertical faces."""
+    nx, ny, Lx, Ly = 5, 4, 512e3, 300e3
+    X, Y = np.meshgrid(np.linspace(0, Lx, 2 * nx + 1), np.linspace(0, Ly, 2 * ny + 1), indexing="xy")
+    v = np.stack([(1 + Y / Ly) ** 2, (2 - X / Lx) ** 2], -1)
+    ux, uy = T.face_velocities(v.ravel(), nx, ny, order=2)
+    hy, hx = Ly / ny, Lx / nx
+    for j in range(ny):
+        y0, y1 = j * hy, (j + 1) * hy
+        exact = ((1 + y1 / Ly) ** 3 - (1 + y0 / Ly) ** 3) * Ly / 3 / hy
+        assert np.allclose(ux[j, 1:-1], exact, rtol=1e-13)
+    for i in range(nx):
+        x0, x1 = i * hx, (i + 1) * hx
+        exact = -((2 - x1 / Lx) ** 3 - (2 - x0 / Lx) ** 3) * Lx / 3 / hx
+        assert np.allclose(uy[1:-1, i], exact, rtol=1e-13)
+    assert np.all(ux[:, [0, -1]] == 0.0) and np.all(uy[[0, -1], :] == 0.0)
