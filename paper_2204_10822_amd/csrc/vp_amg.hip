@@ -923,6 +923,52 @@ k_gershgorin(const double* __restrict__ A, size_t nn, int nxn, int nyn, double* 
   }
 }
 
+// The same bound for the symmetric block 25-point stencil of Q2 elements: the
+// stored blocks of node n and the transposes of the blocks stored at n - o.
+__global__ void __launch_bounds__(kBlock)
+k_gershgorin25(const double* __restrict__ A, size_t nn, int nxn, int nyn, double* __restrict__ partials) {
+  __shared__ double lds[16];
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double best = 0.0;
+  if (n < nn) {
+    const int i = (int)(n % nxn), j = (int)(n / nxn);
+    double D[2][2], Di[2][2];
+    for (int r = 0; r < 2; ++r)
+      for (int q = 0; q < 2; ++q) D[r][q] = A[aidx(2, nn, 0, n, r, q)];
+    invert_block<2>(D, Di);
+    double rs[2] = {0.0, 0.0};
+    auto add = [&](const double (&blk)[2][2]) {
+      for (int r = 0; r < 2; ++r)
+        for (int q = 0; q < 2; ++q) rs[r] += fabs(Di[r][0] * blk[0][q] + Di[r][1] * blk[1][q]);
+    };
+    for (int d = 0; d < 13; ++d) {
+      const int ox = q2_ox(d), oy = q2_oy(d);
+      if (i + ox >= 0 && i + ox < nxn && j + oy < nyn) {
+        double blk[2][2];
+        for (int r = 0; r < 2; ++r)
+          for (int q = 0; q < 2; ++q) blk[r][q] = A[aidx(2, nn, d, n, r, q)];
+        add(blk);
+      }
+      if (d > 0 && i - ox >= 0 && i - ox < nxn && j - oy >= 0) {
+        const size_t m = (size_t)(j - oy) * nxn + (i - ox);
+        double blk[2][2];
+        for (int r = 0; r < 2; ++r)
+          for (int q = 0; q < 2; ++q) blk[r][q] = A[aidx(2, nn, d, m, q, r)];
+        add(blk);
+      }
+    }
+    best = fmax(rs[0], rs[1]);
+  }
+  best = wave_max(best);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, lds[w]);
+    partials[blockIdx.x] = m;
+  }
+}
+
 // Power iteration for lmax(D^{-1} A) (block Jacobi), device resident and warm
 // started across setups.  One step: y = D^{-1} A x / |x|, partial sums of |y|^2;
 // |x|^2 is read from nrm2_in (device), so no host synchronisation is needed.
@@ -1539,6 +1585,7 @@ double* galerkin_work(vp_ctx c) {
 // Restart the spectral estimates from the fixed start vector at the next setup.
 void amg_reset_estimates(vp_ctx c) {
   for (int l = 0; l < kMaxLevels; ++l) c->lev[l].pv_warm = false;
+  c->pq_warm = false;
 }
 
 // Numeric setup on the current finest operator.
@@ -1551,6 +1598,52 @@ int tail_start(vp_ctx c) {
   for (int l = 1; l + 1 < c->nlev; ++l)
     if (c->lev[l].B == 3 && c->lev[l].nn <= (size_t)kTailNodes && c->nlev - l <= kTailLevels) return l;
   return -1;
+}
+
+// Q2 elements: the V-cycle smooths the finest level with the 25-point Q2
+// operator itself (the coarse levels come from the refined Q1 operator), so its
+// Chebyshev interval needs lmax(D^{-1} K2): Gershgorin bound, then the power
+// iteration warm started across setups.  FP32 V-cycles get an FP32 copy.
+void q2_smoother_setup(vp_ctx c, int precision) {
+  hipStream_t s = c->stream;
+  const size_t nn = c->nn, nd = 2 * nn;
+  const int nxn = c->ec.nxn, nyn = c->ec.nyn;
+  const unsigned g = (unsigned)((nn + kBlock - 1) / kBlock);
+  if (!c->lmax_q2) {
+    c->lmax_q2 = dalloc<double>(1);
+    c->pq0 = dalloc<double>(nd);
+    c->pq1 = dalloc<double>(nd);
+    c->pqn = dalloc<double>(2);
+  }
+  hipLaunchKernelGGL(k_gershgorin25, dim3(g), dim3(kBlock), 0, s, c->K2, nn, nxn, nyn, c->partials);
+  VP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_finish_max, dim3(1), dim3(512), 0, s, c->partials, (int)g, c->lmax_q2);
+  VP_LAUNCH_CHECK();
+  int its = c->power_its_warm;
+  if (!c->pq_warm) {
+    hipLaunchKernelGGL(k_power_init, dim3(1024), dim3(256), 0, s, c->pq0, nd);
+    VP_LAUNCH_CHECK();
+    its = c->power_its_cold;
+    c->pq_warm = true;
+  }
+  launch_dot(s, c->pq0, c->pq0, nd, c->partials);
+  launch_finish_sum(s, c->partials, kRedBlocks, 1, c->pqn);
+  for (int k = 0; k < its; ++k) {
+    double* xin = (k & 1) ? c->pq1 : c->pq0;
+    double* yout = (k & 1) ? c->pq0 : c->pq1;
+    hipLaunchKernelGGL((k_power_step<2, 1>), dim3(g), dim3(kBlock), 0, s, c->K2, nn, nxn, nyn, xin,
+                       c->pqn + (k & 1), yout, c->partials);
+    VP_LAUNCH_CHECK();
+    launch_finish_sum(s, c->partials, (int)g, 1, c->pqn + ((k + 1) & 1));
+  }
+  hipLaunchKernelGGL(k_power_final, dim3(1), dim3(64), 0, s, c->pqn + (its & 1), c->power_factor, c->lmax_q2);
+  VP_LAUNCH_CHECK();
+  if (its & 1) std::swap(c->pq0, c->pq1);
+  if (precision != VP_PREC_FP64) {
+    const size_t na = (size_t)52 * nn;
+    if (!c->K2_32) c->K2_32 = dalloc<float>(na);
+    convert(s, c->K2, c->K2_32, na);
+  }
 }
 
 void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
@@ -1661,6 +1754,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       }
     }
   }
+  if (c->order == 2) q2_smoother_setup(c, precision);
   const bool vec64 = precision == VP_PREC_FP64;
   const bool have64 = c->amg_prec == VP_PREC_FP64;
   if (c->lev[0].x == nullptr || vec64 != have64) {
@@ -1671,12 +1765,14 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   // spectral bounds to the host (one synchronisation per setup)
   for (int l = 0; l < c->nlev; ++l)
     VP_HIP(hipMemcpyAsync(c->hscal + l, c->lev[l].lmax, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (c->order == 2)
+    VP_HIP(hipMemcpyAsync(c->hscal + c->nlev, c->lmax_q2, sizeof(double), hipMemcpyDeviceToHost, s));
   VP_HIP(hipStreamSynchronize(s));
-  for (int l = 0; l < c->nlev; ++l) {
-    c->lev[l].lmax_h = c->hscal[l];
+  for (int l = 0; l < c->nlev + (c->order == 2 ? 1 : 0); ++l)
     if (!(c->hscal[l] > 0.0) || !std::isfinite(c->hscal[l]))
       throw Error(VP_ENONFINITE, "AMG setup: non-finite or non-positive spectral bound");
-  }
+  for (int l = 0; l < c->nlev; ++l) c->lev[l].lmax_h = c->hscal[l];
+  if (c->order == 2) c->lmax_q2_h = c->hscal[c->nlev];
   c->tail_level = tail_start(c);
   {
     const char* env = std::getenv("VP_AMG_PAIRS");   // VP_AMG_PAIRS=0: one launch per sweep
@@ -1690,10 +1786,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
 // ---------------------------------------------------------------------------
 namespace {
 
-template <int B, typename TM, typename TV>
+template <int B, typename TM, typename TV, int ST = 0>
 void sten_resid(vp_ctx c, int l, const Level& L, const TM* A, const TV* x, const TV* b, TV* r) {
   const int pr = l == 0 ? prof_begin(c, VP_KID_STEN_RESID0) : -1;
-  hipLaunchKernelGGL((k_sten_resid<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn,
+  hipLaunchKernelGGL((k_sten_resid<B, TM, TV, ST>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn,
                      L.nxn, L.nyn, x, b, r);
   VP_LAUNCH_CHECK();
   prof_end(c, pr);
@@ -1702,14 +1798,16 @@ void sten_resid(vp_ctx c, int l, const Level& L, const TM* A, const TV* x, const
 // Chebyshev smoothing of degree `degree` on [lmax/ratio, lmax] with the block
 // diagonal as preconditioner.  pre: x = 0 on entry and r = b - A x on exit (for
 // the restriction); otherwise x is updated in place from the residual of b.
-template <int B, typename TM, typename TV>
+// ST = 1 with lmax_h: the finest level of Q2 elements (25-point stencil, its own
+// spectral bound).
+template <int B, typename TM, typename TV, int ST = 0>
 void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bool pre, int degree,
-            double ratio) {
+            double ratio, double lmax_h = 0.0) {
   hipStream_t s = c->stream;
   using TA = typename Acc<TV>::type;
   TV* r = (TV*)L.r;
   TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
-  const double lmax = L.lmax_h, lmin = lmax / ratio;
+  const double lmax = ST == 1 ? lmax_h : L.lmax_h, lmin = lmax / ratio;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -1721,12 +1819,12 @@ void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bo
                        degree == 1 ? r : nullptr, d[0], degree == 1 ? x : nullptr, inv_theta, 0);
     VP_LAUNCH_CHECK();
   } else if (degree == 1) {
-    sten_resid<B>(c, l, L, A, (const TV*)x, b, r);
+    sten_resid<B, TM, TV, ST>(c, l, L, A, (const TV*)x, b, r);
     hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, (const TV*)r,
                        (TV*)nullptr, d[0], x, inv_theta, 1);
     VP_LAUNCH_CHECK();
   } else {
-    hipLaunchKernelGGL((k_resid_first<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
+    hipLaunchKernelGGL((k_resid_first<B, TM, TV, ST>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
                        (const TV*)x, b, r, d[0], inv_theta);
     VP_LAUNCH_CHECK();
   }
@@ -1736,14 +1834,14 @@ void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bo
     const int xmode = k > 1 ? 0 : pre ? 2 : 1;
     const TV* rin = (pre && k == 1) ? b : (const TV*)r;
     const int pr = (l == 0 && xmode == 0) ? prof_begin(c, VP_KID_CHEB_STEP0) : -1;
-    hipLaunchKernelGGL((k_cheb_step<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
+    hipLaunchKernelGGL((k_cheb_step<B, TM, TV, ST>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
                        (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], (const TV*)x, x, (TA)cdd, (TA)cdr, xmode);
     VP_LAUNCH_CHECK();
     prof_end(c, pr);
     rho = rn;
   }
   // r = b - A x after pre-smoothing (r holds the residual before the last correction)
-  if (pre) sten_resid<B>(c, l, L, A, (const TV*)d[(degree - 1) & 1], (const TV*)r, r);
+  if (pre) sten_resid<B, TM, TV, ST>(c, l, L, A, (const TV*)d[(degree - 1) & 1], (const TV*)r, r);
 }
 
 template <typename TV>
@@ -1929,6 +2027,28 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     return;
   }
   Level& N = c->lev[l + 1];
+  if (l == 0 && c->order == 2) {
+    // Q2 elements: smooth with the 25-point operator, restrict/prolong with the
+    // refined Q1 level's transfers
+    auto q2 = [&](auto tm_tag, const void* Kv) {
+      using TM = decltype(tm_tag);
+      const TM* K = (const TM*)Kv;
+      smooth<2, TM, TV, 1>(c, 0, L, K, b, x, true, c->cheb_degree, c->cheb_ratio, c->lmax_q2_h);
+      using TPv = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+      const TPv* Pp = (const TPv*)(std::is_same<TV, double>::value ? (const void*)L.P64 : (const void*)L.P32);
+      hipLaunchKernelGGL((k_restrict<2, TPv, TV>), dim3((unsigned)((N.nn * kRestrictLanes + kBlock - 1) / kBlock)),
+                         dim3(kBlock), 0, s, Pp, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)L.r, (TV*)N.b);
+      VP_LAUNCH_CHECK();
+      vcycle_level<TV>(c, 1, (const TV*)N.b, (TV*)N.x);
+      hipLaunchKernelGGL((k_prolong_add<2, TPv, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, Pp, L.nn, L.nxn,
+                         L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
+      VP_LAUNCH_CHECK();
+      smooth<2, TM, TV, 1>(c, 0, L, K, b, x, false, c->cheb_degree, c->cheb_ratio, c->lmax_q2_h);
+    };
+    if constexpr (std::is_same<TV, double>::value) q2(double(), c->K2);
+    else q2(float(), c->K2_32);
+    return;
+  }
   auto run = [&](auto bconst, auto tm_tag, auto tp_tag, const void* Av, const void* Pv) {
     constexpr int B = decltype(bconst)::value;
     using TM = decltype(tm_tag);

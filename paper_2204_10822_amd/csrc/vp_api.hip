@@ -287,6 +287,8 @@ void amg_setup(vp_ctx c, const vp_amg_opts& a) {
   require(a.cheb_degree >= 1 && a.cheb_degree <= 16, VP_EINVAL, "cheb_degree out of range");
   require(a.max_coarse >= 8 && a.max_coarse <= 1024, VP_EINVAL, "max_coarse out of range");
   require(a.precision >= 0 && a.precision <= 5, VP_EINVAL, "bad precision");
+  require(c->order == 1 || a.precision <= VP_PREC_FP32_BF16COARSE, VP_EINVAL,
+          "Q2 elements take the FP64, FP32 or FP32 + BF16-coarse V-cycle");
   require(a.cheb_ratio > 1.0 && a.omega_scale > 0.0, VP_EINVAL, "bad smoother options");
   if (!c->amg_struct || c->max_coarse != a.max_coarse) amg_build_structure(c, c->lev[0].A64, a.max_coarse);
   c->cheb_degree = a.cheb_degree;
@@ -445,6 +447,7 @@ int vp_create(const vp_problem_desc* desc, void* stream, vp_ctx* out) {
         c->P1 = dalloc<double>(4 * c->ncell);
         c->rhoH1 = dalloc<double>(4 * c->ncell);
         c->K2 = dalloc<double>((size_t)52 * c->nn);
+        c->pi1 = dalloc<double>((size_t)48 * c->ncell);
       }
     } catch (...) {
       vp_destroy(c);
@@ -462,7 +465,7 @@ void vp_destroy(vp_ctx c) {
   amg_free(c);
   if (K) (void)hipFree(K);
   void* bufs[] = {c->P, c->rhoH, c->F, c->vo, c->partials, c->dscal, c->work, c->kv, c->dense, c->P1, c->rhoH1,
-                  c->K2};
+                  c->K2, c->pi1, c->K2_32, c->lmax_q2, c->pq0, c->pq1, c->pqn};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->hscal) (void)hipHostFree(c->hscal);

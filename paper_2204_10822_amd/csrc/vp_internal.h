@@ -193,6 +193,7 @@ struct vp_ctx_s {
   vp::ElemConst ec1{};             // Q2: the Q1 refined mesh of the preconditioner
   double* P1 = nullptr;            // Q2: cell fields on the refined mesh [4*ncell]
   double* rhoH1 = nullptr;
+  double* pi1 = nullptr;           // Q2: dual variable moved to the refined mesh's points [12*4*ncell]
   double* K2 = nullptr;            // Q2: the operator, 13 blocks per node
   float* K2_32 = nullptr;          // Q2: FP32 copy for the V-cycle's finest level
   double* lmax_q2 = nullptr;       // Q2: lmax(D^{-1} K2) for the finest smoother (device)
@@ -275,6 +276,7 @@ void launch_q2_residual(vp_ctx c, const double* v, const double* dv, double alph
                         unsigned* nblocks);
 void launch_q2_assemble(vp_ctx c, const double* v, const double* pi, int variant);
 void launch_q2_apply(vp_ctx c, const double* x, double* y, double* partials);
+void launch_q2_pi_refine(vp_ctx c, const double* pi);
 void launch_q2_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
 void launch_q2_pi_init(vp_ctx c, const double* v, double* pi);
 // the Krylov operator of the context: the Q1 stencil in lev[0], or the Q2 operator
