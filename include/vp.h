@@ -121,10 +121,20 @@ int vp_operator_apply(vp_ctx ctx, const double* x, double* y);
  * transposes held by those nodes (the operator is symmetric). */
 int vp_operator_export(vp_ctx ctx, double* blocks);
 
-/* Smoothed-aggregation AMG (replaces the paper's BoomerAMG, Sec. 5.4) built on
- * the last assembled operator: structured 3x3-node aggregates, rigid-body
- * near-null space, one block-Jacobi smoothing of the prolongator, Galerkin
- * coarse operators, Chebyshev smoothing, dense coarsest solve. */
+/* AMG preconditioner built on the last assembled operator, of one of two kinds:
+ *  VP_AMG_SA (default): smoothed aggregation (the library's replacement for the
+ *    paper's BoomerAMG, Sec. 5.4): structured 3x3-node aggregates, rigid-body
+ *    near-null space, one block-Jacobi smoothing of the prolongator, Galerkin
+ *    coarse operators, Chebyshev smoothing, dense coarsest solve;
+ *  VP_AMG_RS: classical Ruge-Stueben AMG with the settings Sec. 5.4 reports for
+ *    BoomerAMG: scalar strength of connection with threshold strong_threshold
+ *    (0.5) and the max_row_sum rule for diagonally dominant rows, first-pass
+ *    coarsening (parallel rounds), classical interpolation, Galerkin coarse
+ *    operators, `sweeps` (3) symmetric Gauss-Seidel sweeps per smoothing
+ *    (multicolour ordering), Gaussian elimination once a level has <= max_coarse
+ *    rows (or 25 levels); FP64 only (precision must be VP_PREC_FP64).
+ * The Chebyshev fields apply to VP_AMG_SA only; the last four to VP_AMG_RS only. */
+enum { VP_AMG_SA = 0, VP_AMG_RS = 1 };
 typedef struct {
   int cheb_degree;       /* Chebyshev degree per pre/post smoothing (>= 1)         */
   int max_coarse;        /* coarsest level dof bound (<= 1024)                     */
@@ -135,11 +145,16 @@ typedef struct {
                             FP16 Jacobi-scaled on every level                      */
   double cheb_ratio;     /* smoothing interval [lmax/ratio, lmax]                  */
   double omega_scale;    /* prolongator damping scale (1 = 4/(3 lmax))             */
+  int kind;              /* VP_AMG_SA or VP_AMG_RS                                 */
+  int sweeps;            /* RS: symmetric Gauss-Seidel sweeps per smoothing (1..16) */
+  double strong_threshold; /* RS: strength threshold theta in (0, 1)              */
+  double max_row_sum;    /* RS: rows with |row sum| > max_row_sum |a_ii| have no
+                            strong couplings (1 switches the rule off)             */
 } vp_amg_opts;
 int vp_amg_setup(vp_ctx ctx, const vp_amg_opts* opts);
 /* z = M^{-1} r, one V-cycle.  VP_ESTATE before vp_amg_setup. */
 int vp_amg_apply(vp_ctx ctx, const double* r, double* z);
-/* Number of AMG levels (host out) and their node grids (host arrays of >= 16). */
+/* Number of AMG levels (host out) and their node grids (host arrays of >= 25). */
 int vp_amg_info(vp_ctx ctx, int* levels, int* nxn, int* nyn, int* dofs_per_node);
 /* Copy AMG level `level` (0 = finest) to device buffers, for inspection.
  *  A (nullable): the level's FP64 operator, 5*B*B*nn doubles in the layout of
@@ -154,6 +169,21 @@ int vp_amg_info(vp_ctx ctx, int* levels, int* nxn, int* nyn, int* dofs_per_node)
  * Asynchronous on the context's stream.  VP_ESTATE before vp_amg_setup; VP_EINVAL
  * for a level out of range or P asked for on the coarsest level. */
 int vp_amg_export(vp_ctx ctx, int level, double* A, double* P);
+/* Classical AMG (VP_AMG_RS) level sizes, for inspection: out (host, 5 entries) =
+ * {rows n, entries of A, coarse points nc, entries of P, colours}; nc, P entries
+ * and colours are 0 on the coarsest level.  vp_amg_info reports the rows of each
+ * level in nxn, 1 in nyn and dofs_per_node.  VP_ESTATE unless the last setup was
+ * VP_AMG_RS; VP_EINVAL for a level out of range. */
+int vp_amg_rs_info(vp_ctx ctx, int level, int64_t* out);
+/* Copy classical-AMG level `level` to device buffers (each nullable), sizes from
+ * vp_amg_rs_info: A as CSR (A_ptr n+1, A_col and A_val entries of A; columns
+ * ascending in each row; level 0 uses the vectors' dof numbering 2*node + comp);
+ * cf[n] (1 = coarse point, 0 = fine point); P as CSR (n+1 / entries of P; coarse
+ * points are numbered in fine order); colour[n] (the smoother's colour of each
+ * row).  Asynchronous except for cf.  VP_EINVAL for cf, P or colour on the
+ * coarsest level. */
+int vp_amg_rs_export(vp_ctx ctx, int level, int32_t* A_ptr, int32_t* A_col, double* A_val, int32_t* cf,
+                     int32_t* P_ptr, int32_t* P_col, double* P_val, int32_t* colour);
 
 /* Krylov solve K x = b with the last assembled operator and AMG (Sec. 5.4):
  * FGMRES(restart) right-preconditioned with classical Gram-Schmidt applied twice,

@@ -1756,10 +1756,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   }
   if (c->order == 2) q2_smoother_setup(c, precision);
   const bool vec64 = precision == VP_PREC_FP64;
-  const bool have64 = c->amg_prec == VP_PREC_FP64;
-  if (c->lev[0].x == nullptr || vec64 != have64) {
+  if (c->lev[0].x == nullptr || vec64 != c->sa_vec64) {
     if (vec64) alloc_vectors<double>(c);
     else alloc_vectors<float>(c);
+    c->sa_vec64 = vec64;
   }
   c->amg_prec = precision;
   // spectral bounds to the host (one synchronisation per setup)
@@ -2104,6 +2104,12 @@ bool scaled_finest(vp_ctx c) {
 // z = M^{-1} r (FP64 in/out; V-cycle in the setup's precision)
 void amg_apply(vp_ctx c, const double* r, double* z) {
   if (!c->amg_ready) throw Error(VP_ESTATE, "AMG not set up");
+  if (c->amg_kind == VP_AMG_RS) {
+    const int pr = prof_begin(c, VP_KID_VCYCLE);
+    rs_apply(c, r, z);
+    prof_end(c, pr);
+    return;
+  }
   Level& L = c->lev[0];
   const size_t n = (size_t)L.B * L.nn;
   struct End {
@@ -2150,7 +2156,10 @@ int amg_apply_dots(vp_ctx c, const double* r, const double* q, double* z, bool i
   hipStream_t s = c->stream;
   const int pr = prof_begin(c, VP_KID_VCYCLE);
   int nb;
-  if (c->amg_prec == VP_PREC_FP64) {
+  if (c->amg_kind == VP_AMG_RS) {
+    rs_apply(c, r, z);
+    nb = launch_out_dots<double>(s, z, nullptr, z, r, q, n, c->partials);
+  } else if (c->amg_prec == VP_PREC_FP64) {
     vcycle_level<double>(c, 0, r, z);
     nb = launch_out_dots<double>(s, z, nullptr, z, r, q, n, c->partials);
   } else {
@@ -2168,6 +2177,12 @@ int amg_apply_dots(vp_ctx c, const double* r, const double* q, double* z, bool i
   }
   prof_end(c, pr);
   return nb;
+}
+
+void launch_dense_inverse(hipStream_t s, double* M, int nd) {
+  if (nd <= kLdsGJ) hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(1024), 0, s, M, nd);
+  else hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, M, nd);
+  VP_LAUNCH_CHECK();
 }
 
 void launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials) {

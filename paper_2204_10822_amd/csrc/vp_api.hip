@@ -284,6 +284,21 @@ int krylov(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_kry
 
 void amg_setup(vp_ctx c, const vp_amg_opts& a) {
   require(c->have_K, VP_ESTATE, "no assembled operator");
+  require(a.kind == VP_AMG_SA || a.kind == VP_AMG_RS, VP_EINVAL, "bad AMG kind");
+  if (a.kind == VP_AMG_RS) {
+    require(a.precision == VP_PREC_FP64, VP_EINVAL, "classical AMG runs in FP64");
+    require(a.sweeps >= 1 && a.sweeps <= 16, VP_EINVAL, "sweeps out of range");
+    require(a.strong_threshold > 0.0 && a.strong_threshold < 1.0, VP_EINVAL, "strong threshold out of (0, 1)");
+    require(a.max_row_sum > 0.0 && a.max_row_sum <= 1.0, VP_EINVAL, "max_row_sum out of (0, 1]");
+    require(a.max_coarse >= 8 && a.max_coarse <= 1024, VP_EINVAL, "max_coarse out of range");
+    c->amg_ready = false;
+    rs_setup(c, a.strong_threshold, a.max_row_sum, a.sweeps, a.max_coarse);
+    c->amg_kind = VP_AMG_RS;
+    c->amg_prec = VP_PREC_FP64;
+    c->amg_ready = true;
+    return;
+  }
+  c->amg_kind = VP_AMG_SA;
   require(a.cheb_degree >= 1 && a.cheb_degree <= 16, VP_EINVAL, "cheb_degree out of range");
   require(a.max_coarse >= 8 && a.max_coarse <= 1024, VP_EINVAL, "max_coarse out of range");
   require(a.precision >= 0 && a.precision <= 5, VP_EINVAL, "bad precision");
@@ -399,7 +414,7 @@ extern "C" {
 
 void vp_default_opts(vp_newton_opts* n, vp_amg_opts* a, vp_krylov_opts* k) {
   if (n) *n = vp_newton_opts{VP_SVN, 1e-8, 0.1, 30, VP_LS_ENERGY};
-  if (a) *a = vp_amg_opts{4, 140, VP_PREC_FP64, 30.0, 1.0};
+  if (a) *a = vp_amg_opts{4, 140, VP_PREC_FP64, 30.0, 1.0, VP_AMG_SA, 3, 0.5, 0.9};
   if (k) *k = vp_krylov_opts{VP_KRYLOV_FCG, 30, 500, 1e-2};
 }
 
@@ -462,6 +477,7 @@ void vp_destroy(vp_ctx c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   double* K = c->lev[0].A64;
+  rs_free(c);
   amg_free(c);
   if (K) (void)hipFree(K);
   void* bufs[] = {c->P, c->rhoH, c->F, c->vo, c->partials, c->dscal, c->work, c->kv, c->dense, c->P1, c->rhoH1,
@@ -559,6 +575,18 @@ int vp_amg_apply(vp_ctx c, const double* r, double* z) {
 int vp_amg_info(vp_ctx c, int* levels, int* nxn, int* nyn, int* dpn) {
   return guarded(c, [&] {
     require(c != nullptr, VP_EINVAL, "null context");
+    if (c->amg_ready && c->amg_kind == VP_AMG_RS) {
+      const int nl = rs_levels(c);
+      if (levels) *levels = nl;
+      for (int l = 0; l < nl; ++l) {
+        long long info[5];
+        rs_info(c, l, info);
+        if (nxn) nxn[l] = (int)info[0];
+        if (nyn) nyn[l] = 1;
+        if (dpn) dpn[l] = 1;
+      }
+      return VP_OK;
+    }
     require(c->amg_struct, VP_ESTATE, "AMG not set up");
     if (levels) *levels = c->nlev;
     for (int l = 0; l < c->nlev; ++l) {
@@ -574,6 +602,7 @@ int vp_amg_export(vp_ctx c, int level, double* A, double* P) {
   return guarded(c, [&] {
     require(c != nullptr, VP_EINVAL, "null context");
     require(c->amg_ready, VP_ESTATE, "AMG not set up");
+    require(c->amg_kind == VP_AMG_SA, VP_ESTATE, "classical AMG: use vp_amg_rs_export");
     require(level >= 0 && level < c->nlev, VP_EINVAL, "level out of range");
     require(!P || level + 1 < c->nlev, VP_EINVAL, "the coarsest level has no prolongator");
     const Level& L = c->lev[level];
@@ -583,6 +612,31 @@ int vp_amg_export(vp_ctx c, int level, double* A, double* P) {
     if (P)
       VP_HIP(hipMemcpyAsync(P, L.P64, (size_t)12 * L.B * L.nn * sizeof(double), hipMemcpyDeviceToDevice,
                             c->stream));
+    return VP_OK;
+  });
+}
+
+int vp_amg_rs_info(vp_ctx c, int level, int64_t* out) {
+  return guarded(c, [&] {
+    require(c != nullptr && out, VP_EINVAL, "null argument");
+    require(c->amg_ready && c->amg_kind == VP_AMG_RS, VP_ESTATE, "classical AMG not set up");
+    require(level >= 0 && level < rs_levels(c), VP_EINVAL, "level out of range");
+    long long info[5];
+    rs_info(c, level, info);
+    for (int k = 0; k < 5; ++k) out[k] = info[k];
+    return VP_OK;
+  });
+}
+
+int vp_amg_rs_export(vp_ctx c, int level, int32_t* A_ptr, int32_t* A_col, double* A_val, int32_t* cf,
+                     int32_t* P_ptr, int32_t* P_col, double* P_val, int32_t* colour) {
+  return guarded(c, [&] {
+    require(c != nullptr, VP_EINVAL, "null context");
+    require(c->amg_ready && c->amg_kind == VP_AMG_RS, VP_ESTATE, "classical AMG not set up");
+    require(level >= 0 && level < rs_levels(c), VP_EINVAL, "level out of range");
+    require(level + 1 < rs_levels(c) || !(cf || P_ptr || P_col || P_val || colour), VP_EINVAL,
+            "the coarsest level has no splitting, prolongator or colouring");
+    rs_export(c, level, A_ptr, A_col, A_val, cf, P_ptr, P_col, P_val, colour);
     return VP_OK;
   });
 }

@@ -182,6 +182,10 @@ struct Prof {
 };
 }  // namespace vp
 
+namespace vp {
+struct RSHier;
+}
+
 struct vp_ctx_s {
   vp::Prof prof;
   vp_problem_desc desc{};
@@ -216,6 +220,9 @@ struct vp_ctx_s {
   bool amg_ready = false;
   bool amg_struct = false;
   int amg_prec = 0;
+  int amg_kind = 0;                // VP_AMG_SA or VP_AMG_RS
+  bool sa_vec64 = false;           // the SA V-cycle vectors are FP64
+  vp::RSHier* rs = nullptr;        // classical AMG hierarchy
   int cheb_degree = 3;
   int tail_level = -1;             // first level run by the single-workgroup tail kernel
   bool pair_sweeps = true;         // finest-level smoother sweeps fused in pairs
@@ -277,6 +284,14 @@ void launch_q2_residual(vp_ctx c, const double* v, const double* dv, double alph
 void launch_q2_assemble(vp_ctx c, const double* v, const double* pi, int variant);
 void launch_q2_apply(vp_ctx c, const double* x, double* y, double* partials);
 void launch_q2_pi_refine(vp_ctx c, const double* pi);
+// classical AMG (vp_rs.hip)
+void rs_setup(vp_ctx c, double theta, double max_row_sum, int sweeps, int max_coarse);
+void rs_apply(vp_ctx c, const double* r, double* z);
+void rs_free(vp_ctx c);
+int rs_levels(vp_ctx c);
+void rs_info(vp_ctx c, int level, long long* out);
+void rs_export(vp_ctx c, int level, int* A_ptr, int* A_col, double* A_val, int* cf, int* P_ptr, int* P_col,
+               double* P_val, int* colour);
 void launch_q2_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
 void launch_q2_pi_init(vp_ctx c, const double* v, double* pi);
 // the Krylov operator of the context: the Q1 stencil in lev[0], or the Q2 operator

@@ -30,7 +30,7 @@ PREC = {"fp64": vp.VP_PREC_FP64, "fp32": vp.VP_PREC_FP32, "bf16": vp.VP_PREC_FP3
 
 
 def run_problem_one(n: int, variant: str, precision: str = "fp64", tol: float = 1e-4, maxit: int = 200,
-                    warmup: bool = True, order: int = 1) -> dict:
+                    warmup: bool = True, order: int = 1, amg: str = "sa") -> dict:
     w = inputs.problem_one(n, order)
     ctx = vp.context_for(w)
     v = torch.zeros(ctx.node_shape, dtype=torch.float64, device="cuda")
@@ -39,6 +39,7 @@ def run_problem_one(n: int, variant: str, precision: str = "fp64", tol: float = 
     no.variant = vp.VP_SVN if variant == "svn" else vp.VP_STDN
     no.tol = tol
     ao.precision = PREC[precision]
+    ao.kind = vp.VP_AMG_RS if amg == "rs" else vp.VP_AMG_SA
 
     def solve():
         v.zero_()
@@ -53,7 +54,8 @@ def run_problem_one(n: int, variant: str, precision: str = "fp64", tol: float = 
         solve()
     rc, info, hist, dt = solve()
     ctx.close()
-    return dict(problem="problem_one", n=n, order=order, dx_km=512.0 / n, variant=variant, precision=precision,
+    return dict(problem="problem_one", n=n, order=order, amg=amg, dx_km=512.0 / n, variant=variant,
+                precision=precision,
                 tol=tol, maxit=maxit, rc=rc, converged=info.rel_resid <= tol,
                 newton_its=info.iterations, krylov_its=info.krylov_iters, rel_resid=info.rel_resid,
                 seconds=dt, history=[float(h) for h in hist])
@@ -71,21 +73,24 @@ def main():
     ap.add_argument("--maxit", type=int, default=200)
     ap.add_argument("--no-warmup", action="store_true")
     ap.add_argument("--order", type=int, default=1, choices=[1, 2], help="velocity elements: Q1 or Q2")
+    ap.add_argument("--amg", default="sa", choices=["sa", "rs"],
+                    help="preconditioner: smoothed aggregation or classical AMG with the paper's settings")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     for n in [int(x) for x in args.n.split(",") if x]:
         for var in [x for x in args.variants.split(",") if x]:
             if args.problem == "one":
-                r = run_problem_one(n, var, args.precision, args.tol, args.maxit, not args.no_warmup, args.order)
+                r = run_problem_one(n, var, args.precision, args.tol, args.maxit, not args.no_warmup, args.order,
+                                    args.amg)
             else:
                 r = run_problem_two(n, args.steps, var, args.precision, args.tol, args.maxit, args.delta_min,
-                                    args.order)
+                                    args.order, args.amg)
             print(json.dumps(r), flush=True)
 
 
 
 def run_problem_two(n: int, steps: int, variant: str = "svn", precision: str = "fp64", tol: float = 1e-4,
-                    maxit: int = 200, delta_min: float = 2e-9, order: int = 1) -> dict:
+                    maxit: int = 200, delta_min: float = 2e-9, order: int = 1, amg: str = "sa") -> dict:
     """The paper's Problem II (Sec. 5.3) for `steps` half-hour steps: each step
     advances A and H explicitly with the previous velocity (Sec. 3), then solves
     the momentum step from the previous (v, pi) until the residual has dropped by
@@ -101,6 +106,7 @@ def run_problem_two(n: int, steps: int, variant: str = "svn", precision: str = "
     no, ao, ko = vp.default_opts()
     no.variant = vp.VP_SVN if variant == "svn" else vp.VP_STDN
     ao.precision = PREC[precision]
+    ao.kind = vp.VP_AMG_RS if amg == "rs" else vp.VP_AMG_SA
     its, kits, fails = [], [], 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -121,7 +127,7 @@ def run_problem_two(n: int, steps: int, variant: str = "svn", precision: str = "
                   f"mean {sum(its) / len(its):.2f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out = dict(problem="problem_two", n=n, order=order, dx_km=512.0 / n, steps=steps, variant=variant,
+    out = dict(problem="problem_two", n=n, order=order, amg=amg, dx_km=512.0 / n, steps=steps, variant=variant,
                precision=precision,
                delta_min=delta_min, tol=tol, mean_newton=sum(its) / len(its), max_newton=max(its),
                total_krylov=sum(kits), failed_steps=fails, seconds=dt, newton_per_step=its,

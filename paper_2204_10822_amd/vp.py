@@ -22,10 +22,12 @@ VP_PREC_FP64, VP_PREC_FP32, VP_PREC_FP32_BF16COARSE, VP_PREC_BF16, VP_PREC_FP16_
     0, 1, 2, 3, 4, 5
 VP_KRYLOV_FGMRES, VP_KRYLOV_FCG = 0, 1
 VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
+VP_AMG_SA, VP_AMG_RS = 0, 1
 
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_residual",
             "vp_newton_assemble", "vp_operator_apply", "vp_operator_export", "vp_amg_setup",
-            "vp_amg_apply", "vp_amg_info", "vp_amg_export", "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
+            "vp_amg_apply", "vp_amg_info", "vp_amg_export", "vp_amg_rs_info", "vp_amg_rs_export",
+            "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
             "vp_newton_step", "vp_newton_solve", "vp_default_opts", "vp_advect", "vp_profile",
             "vp_profile_read"]
 EXPORTED_NET = ["vpnet_create", "vpnet_destroy", "vpnet_last_error", "vpnet_param_count",
@@ -45,7 +47,8 @@ class vp_problem_desc(C.Structure):
 
 class vp_amg_opts(C.Structure):
     _fields_ = [("cheb_degree", C.c_int), ("max_coarse", C.c_int), ("precision", C.c_int),
-                ("cheb_ratio", C.c_double), ("omega_scale", C.c_double)]
+                ("cheb_ratio", C.c_double), ("omega_scale", C.c_double), ("kind", C.c_int), ("sweeps", C.c_int),
+                ("strong_threshold", C.c_double), ("max_row_sum", C.c_double)]
 
 
 class vp_krylov_opts(C.Structure):
@@ -90,6 +93,8 @@ def _load():
         "vp_amg_apply": (I, [P, P, P]),
         "vp_amg_info": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
         "vp_amg_export": (I, [P, I, P, P]),
+        "vp_amg_rs_info": (I, [P, I, P]),
+        "vp_amg_rs_export": (I, [P, I, P, P, P, P, P, P, P, P]),
         "vp_krylov_solve": (I, [P, P, P, C.POINTER(vp_krylov_opts), C.POINTER(vp_krylov_info)]),
         "vp_pi_update": (I, [P, P, P, P, D]),
         "vp_pi_init": (I, [P, P, P]),
@@ -140,13 +145,13 @@ def default_opts():
     return n, a, k
 
 
-def _ptr(t, shape, name):
+def _ptr(t, shape, name, dtype=torch.float64):
     if t is None:
         return None
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name}: expected a CUDA tensor")
-    if t.dtype != torch.float64:
-        raise TypeError(f"{name}: expected float64, got {t.dtype}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name}: tensor must be contiguous")
     if t.numel() != int(torch.Size(shape).numel()):
@@ -238,9 +243,9 @@ class Context:
 
     def vp_amg_info(self):
         lv = C.c_int()
-        nx = (C.c_int * 16)()
-        ny = (C.c_int * 16)()
-        b = (C.c_int * 16)()
+        nx = (C.c_int * 32)()
+        ny = (C.c_int * 32)()
+        b = (C.c_int * 32)()
         self._check(LIB.vp_amg_info(self.h, C.byref(lv), nx, ny, b))
         return [(nx[i], ny[i], b[i]) for i in range(lv.value)]
 
@@ -254,6 +259,40 @@ class Context:
         pa = _ptr(A, (5 * B * B * nn,), "A") if A is not None else None
         pp = _ptr(P, (12 * B * nn,), "P") if P is not None else None
         return self._check(LIB.vp_amg_export(self.h, int(level), pa, pp))
+
+    def vp_amg_rs_info(self, level):
+        """Classical AMG level sizes: (rows, entries of A, coarse points, entries of P, colours)."""
+        out = (C.c_int64 * 5)()
+        self._check(LIB.vp_amg_rs_info(self.h, int(level), out))
+        return tuple(int(v) for v in out)
+
+    def vp_amg_rs_export(self, level):
+        """Classical AMG level `level` as device tensors: dict with A (ptr, col, val),
+        and below the coarsest level cf, P (ptr, col, val) and colour."""
+        n, nnz, nc, nnzp, ncol = self.vp_amg_rs_info(level)
+        dev = torch.device("cuda")
+        i32 = torch.int32
+        out = dict(n=n, nc=nc, ncol=ncol,
+                   A_ptr=torch.empty(n + 1, dtype=i32, device=dev), A_col=torch.empty(max(nnz, 1), dtype=i32, device=dev),
+                   A_val=torch.empty(max(nnz, 1), dtype=torch.float64, device=dev))
+        args = [_ptr(out["A_ptr"], (n + 1,), "A_ptr", i32), _ptr(out["A_col"], out["A_col"].shape, "A_col", i32),
+                _ptr(out["A_val"], out["A_val"].shape, "A_val")]
+        if nc > 0:
+            out.update(cf=torch.empty(n, dtype=i32, device=dev), P_ptr=torch.empty(n + 1, dtype=i32, device=dev),
+                       P_col=torch.empty(max(nnzp, 1), dtype=i32, device=dev),
+                       P_val=torch.empty(max(nnzp, 1), dtype=torch.float64, device=dev),
+                       colour=torch.empty(n, dtype=i32, device=dev))
+            args += [_ptr(out["cf"], (n,), "cf", i32), _ptr(out["P_ptr"], (n + 1,), "P_ptr", i32),
+                     _ptr(out["P_col"], out["P_col"].shape, "P_col", i32), _ptr(out["P_val"], out["P_val"].shape, "P_val"),
+                     _ptr(out["colour"], (n,), "colour", i32)]
+        else:
+            args += [None] * 5
+        self._check(LIB.vp_amg_rs_export(self.h, int(level), *args))
+        torch.cuda.synchronize()
+        out["A_col"], out["A_val"] = out["A_col"][:nnz], out["A_val"][:nnz]
+        if nc > 0:
+            out["P_col"], out["P_val"] = out["P_col"][:nnzp], out["P_val"][:nnzp]
+        return out
 
     def vp_krylov_solve(self, b, x, opts=None):
         if opts is None:
