@@ -42,7 +42,7 @@ namespace {
 constexpr int kRsBlock = 256;
 constexpr int kMergeBlock = 64;
 constexpr int kMaxMergeList = 480;  // longest left-factor row of a sparse product (LDS < 64 KB)
-constexpr int kRsSmall = 16384;     // levels handled by the one-workgroup tail kernel
+constexpr int kRsSmall = 2048;      // levels handled by the one-workgroup tail kernel
 constexpr int kMaxColours = 128;
 constexpr int kMaxRsLevels = 25;
 constexpr int kMaxRounds = 4096;
@@ -83,6 +83,13 @@ struct RSLevel {
   int* corder = nullptr; size_t c_corder = 0;
   int* coff = nullptr; size_t c_coff = 0;  // device copy of the colour offsets
   std::vector<int> coff_h;
+  // the rows of each colour again in ELL form (slot-major, padded with zero
+  // couplings to the row itself) for coalesced smoother reads
+  int* ecol = nullptr; size_t c_ecol = 0;
+  double* eval = nullptr; size_t c_eval = 0;
+  int* eoff = nullptr; size_t c_eoff = 0;  // device [base, width] per colour
+  std::vector<long long> ebase_h;
+  std::vector<int> ewidth_h;
   double* x = nullptr; size_t c_x = 0;
   double* b = nullptr; size_t c_b = 0;
   double* r = nullptr; size_t c_r = 0;
@@ -575,6 +582,32 @@ __global__ void k_col_scatter(int n, const int* __restrict__ colour, int* __rest
   if (i < n) order[atomicAdd(&cursor[colour[i]], 1)] = i;
 }
 
+__global__ void k_col_width(int n, const int* __restrict__ ptr, const int* __restrict__ colour,
+                            int* __restrict__ width) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicMax(&width[colour[i]], ptr[i + 1] - ptr[i]);
+}
+
+// ELL copy: position t of the colour-sorted order, row i = order[t] of colour c
+// goes to column t - coff[c] of colour c's slot-major block at base(c).
+__global__ void __launch_bounds__(kRsBlock)
+k_ell_fill(int n, const int* __restrict__ order, const int* __restrict__ colour, const int* __restrict__ coff,
+           const long long* __restrict__ ebase, const int* __restrict__ ewidth, const int* __restrict__ ptr,
+           const int* __restrict__ col, const double* __restrict__ val, int* __restrict__ ecol,
+           double* __restrict__ eval) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = order[t], c = colour[i];
+  const int cnt = coff[c + 1] - coff[c], tl = t - coff[c], w = ewidth[c];
+  const long long base = ebase[c];
+  const int lo = ptr[i], len = ptr[i + 1] - lo;
+  for (int e = 0; e < w; ++e) {
+    const long long q = base + (long long)e * cnt + tl;
+    ecol[q] = e < len ? col[lo + e] : i;
+    eval[q] = e < len ? val[lo + e] : 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // cycle kernels
 // ---------------------------------------------------------------------------
@@ -586,11 +619,16 @@ __device__ __forceinline__ void relax_row(int i, const int* __restrict__ ptr, co
   x[i] += (b[i] - ax) / diag[i];
 }
 
+// one colour's rows from its ELL block (the same sums, in the same order, as the CSR rows)
 __global__ void __launch_bounds__(kRsBlock)
-k_rs_relax(const int* __restrict__ rows, int cnt, const int* __restrict__ ptr, const int* __restrict__ col,
-           const double* __restrict__ val, const double* __restrict__ diag, const double* __restrict__ b, double* x) {
+k_rs_relax(const int* __restrict__ rows, int cnt, int w, const int* __restrict__ ecol,
+           const double* __restrict__ eval, const double* __restrict__ diag, const double* __restrict__ b, double* x) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < cnt) relax_row(rows[t], ptr, col, val, diag, b, x);
+  if (t >= cnt) return;
+  const int i = rows[t];
+  double ax = 0.0;
+  for (int e = 0; e < w; ++e) ax += eval[(size_t)e * cnt + t] * x[ecol[(size_t)e * cnt + t]];
+  x[i] += (b[i] - ax) / diag[i];
 }
 
 __global__ void __launch_bounds__(kRsBlock)
@@ -815,12 +853,31 @@ void colour_level(RSHier& H, hipStream_t s, RSLevel& L) {
   VP_HIP(hipMemcpyAsync(H.dint, L.coff_h.data(), ncol * sizeof(int), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_col_scatter, dim3(g), dim3(kRsBlock), 0, s, n, L.colour, H.dint, L.corder);
   VP_LAUNCH_CHECK();
-  VP_HIP(hipStreamSynchronize(s));  // coff_h is read by the copies above
+  // ELL blocks: widths per colour, bases, fill
+  hipLaunchKernelGGL(k_rs_zero_ints, dim3(1), dim3(kMaxColours), 0, s, H.dint, kMaxColours);
+  hipLaunchKernelGGL(k_col_width, dim3(g), dim3(kRsBlock), 0, s, n, L.ptr, L.colour, H.dint);
+  VP_LAUNCH_CHECK();
+  L.ewidth_h.assign(ncol, 0);
+  read_int(H, s, H.dint, ncol, L.ewidth_h.data());
+  L.ebase_h.assign(ncol + 1, 0);
+  for (int c = 0; c < ncol; ++c) L.ebase_h[c + 1] = L.ebase_h[c] + (long long)L.ewidth_h[c] * counts[c];
+  const size_t ne = (size_t)L.ebase_h[ncol];
+  ensure(L.ecol, L.c_ecol, ne);
+  ensure(L.eval, L.c_eval, ne);
+  ensure(L.eoff, L.c_eoff, (size_t)3 * ncol + 2);  // ebase as long long (2 ints each) then widths
+  long long* ebase_d = reinterpret_cast<long long*>(L.eoff);
+  int* ewidth_d = L.eoff + 2 * ncol;
+  VP_HIP(hipMemcpyAsync(ebase_d, L.ebase_h.data(), ncol * sizeof(long long), hipMemcpyHostToDevice, s));
+  VP_HIP(hipMemcpyAsync(ewidth_d, L.ewidth_h.data(), ncol * sizeof(int), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_ell_fill, dim3(g), dim3(kRsBlock), 0, s, n, L.corder, L.colour, L.coff, ebase_d, ewidth_d,
+                     L.ptr, L.col, L.val, L.ecol, L.eval);
+  VP_LAUNCH_CHECK();
+  VP_HIP(hipStreamSynchronize(s));  // the host vectors are read by the copies above
 }
 
 void free_level(RSLevel& L) {
-  void* bufs[] = {L.ptr, L.col, L.val, L.diag, L.cf, L.cidx, L.pptr, L.pcol, L.pval, L.rptr,
-                  L.rcol, L.rval, L.colour, L.corder, L.coff, L.x, L.b, L.r, L.Ainv};
+  void* bufs[] = {L.ptr, L.col, L.val, L.diag, L.cf, L.cidx, L.pptr, L.pcol, L.pval, L.rptr, L.rcol,
+                  L.rval, L.colour, L.corder, L.coff, L.ecol, L.eval, L.eoff, L.x, L.b, L.r, L.Ainv};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   L = RSLevel();
@@ -1018,7 +1075,7 @@ void relax_level(vp_ctx c, const RSLevel& L, const double* b, double* x, int swe
         const int cnt = L.coff_h[col + 1] - L.coff_h[col];
         if (cnt == 0) continue;
         hipLaunchKernelGGL(k_rs_relax, dim3(rs_grid(cnt)), dim3(kRsBlock), 0, s, L.corder + L.coff_h[col], cnt,
-                           L.ptr, L.col, L.val, L.diag, b, x);
+                           L.ewidth_h[col], L.ecol + L.ebase_h[col], L.eval + L.ebase_h[col], L.diag, b, x);
         VP_LAUNCH_CHECK();
       }
 }

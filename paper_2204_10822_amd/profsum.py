@@ -61,6 +61,7 @@ def _demangle_vp(name: str) -> str:
 def _short(name: str) -> str:
     if name.startswith("_Z"):
         return _demangle_vp(name)
+    name = name.replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*$", "", name)           # drop the argument list
     name = name.replace("void ", "").replace("vp::", "")
     return name
