@@ -467,23 +467,116 @@ k_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __
   if (n < nn) node_sten_resid<B, TM, TV, ST>(A, nn, nxn, nyn, x, b, r, n);
 }
 
-// y = A x (FP64 finest level), partial sums of x.y per workgroup (for CG)
+// y = A x (FP64 finest level), partial sums of x.y per workgroup (for CG).
+// Each wave covers 64 columns of a strip of kWalkRows node rows and walks up
+// it: the stored blocks of the row below (north, north-east, north-west planes)
+// and x of the rows below/at/above stay in registers from the previous step,
+// and the left and right neighbours' values come from the adjacent lanes, so
+// every stored block and x value is read from memory once per strip (lanes at a
+// wave's edge load their outside neighbour's values).  A workgroup is four
+// waves on four consecutive strips.
+constexpr int kWalkRows = 8;
+
+struct Blk4 {
+  double a, b, c, d;  // block entries (0,0), (0,1), (1,0), (1,1)
+};
+
+__device__ __forceinline__ Blk4 walk_block(const double* __restrict__ A, size_t nn, int p, int nxn, int nyn, int i,
+                                           int j) {
+  if (i < 0 || i >= nxn || j < 0 || j >= nyn) return Blk4{0.0, 0.0, 0.0, 0.0};
+  const double2* q = reinterpret_cast<const double2*>(A + aidx(2, nn, p, (size_t)j * nxn + i, 0, 0));
+  const double2 u = q[0], v = q[1];
+  return Blk4{u.x, u.y, v.x, v.y};
+}
+
+__device__ __forceinline__ double2 walk_x(const double* __restrict__ x, int nxn, int nyn, int i, int j) {
+  if (i < 0 || i >= nxn || j < 0 || j >= nyn) return make_double2(0.0, 0.0);
+  return reinterpret_cast<const double2*>(x)[(size_t)j * nxn + i];
+}
+
+__device__ __forceinline__ double2 lane_d2(double2 v, int src) {
+  return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+__device__ __forceinline__ Blk4 lane_blk(const Blk4& b, int src) {
+  return Blk4{__shfl(b.a, src, 64), __shfl(b.b, src, 64), __shfl(b.c, src, 64), __shfl(b.d, src, 64)};
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_apply_fine(const double* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
              double* __restrict__ y, double* __restrict__ partials) {
   __shared__ double lds[16];
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 64 + lane;
+  const int j0 = (blockIdx.y * (kBlock / 64) + (int)(threadIdx.x >> 6)) * kWalkRows;
+  const bool in = i < nxn;
+  const int ic = in ? i : -1;  // -1: every load of an idle lane returns zeros
+  const int lm = (lane + 63) & 63, lp = (lane + 1) & 63;
+  Blk4 cN = walk_block(A, nn, 2, nxn, nyn, ic, j0 - 1);
+  Blk4 cNE = walk_block(A, nn, 3, nxn, nyn, ic, j0 - 1);
+  Blk4 cNW = walk_block(A, nn, 4, nxn, nyn, ic, j0 - 1);
+  double2 xs = walk_x(x, nxn, nyn, ic, j0 - 1);
+  double2 xc = walk_x(x, nxn, nyn, ic, j0);
   double acc[1] = {0.0};
-  if (n < nn) {
-    const int i = (int)(n % nxn), j = (int)(n / nxn);
-    double yy[2], D[2][2];
-    stencil_row<2>(A, nn, nxn, nyn, i, j, x, yy, D);
-    reinterpret_cast<double2*>(y)[n] = make_double2(yy[0], yy[1]);
-    acc[0] = yy[0] * x[2 * n] + yy[1] * x[2 * n + 1];
+  for (int t = 0; t < kWalkRows; ++t) {
+    const int j = j0 + t;   // uniform across the wave
+    if (j >= nyn) break;
+    const Blk4 P0 = walk_block(A, nn, 0, nxn, nyn, ic, j);
+    const Blk4 PE = walk_block(A, nn, 1, nxn, nyn, ic, j);
+    const Blk4 PN = walk_block(A, nn, 2, nxn, nyn, ic, j);
+    const Blk4 PNE = walk_block(A, nn, 3, nxn, nyn, ic, j);
+    const Blk4 PNW = walk_block(A, nn, 4, nxn, nyn, ic, j);
+    const double2 xn = walk_x(x, nxn, nyn, ic, j + 1);
+    double2 xcL = lane_d2(xc, lm), xcR = lane_d2(xc, lp);
+    double2 xnL = lane_d2(xn, lm), xnR = lane_d2(xn, lp);
+    double2 xsL = lane_d2(xs, lm), xsR = lane_d2(xs, lp);
+    Blk4 PEL = lane_blk(PE, lm), cNEL = lane_blk(cNE, lm), cNWR = lane_blk(cNW, lp);
+    if (lane == 0) {
+      xcL = walk_x(x, nxn, nyn, i - 1, j);
+      xnL = walk_x(x, nxn, nyn, i - 1, j + 1);
+      xsL = walk_x(x, nxn, nyn, i - 1, j - 1);
+      PEL = walk_block(A, nn, 1, nxn, nyn, i - 1, j);
+      cNEL = walk_block(A, nn, 3, nxn, nyn, i - 1, j - 1);
+    }
+    if (lane == 63) {
+      xcR = walk_x(x, nxn, nyn, i + 1, j);
+      xnR = walk_x(x, nxn, nyn, i + 1, j + 1);
+      xsR = walk_x(x, nxn, nyn, i + 1, j - 1);
+      cNWR = walk_block(A, nn, 4, nxn, nyn, i + 1, j - 1);
+    }
+    if (i == 0) xcL = xnL = xsL = make_double2(0.0, 0.0);
+    if (i + 1 >= nxn) xcR = xnR = xsR = make_double2(0.0, 0.0);
+    if (in) {
+      double y0 = 0.0, y1 = 0.0;
+      auto fwd = [&](const Blk4& b, double2 v) {
+        y0 += b.a * v.x + b.b * v.y;
+        y1 += b.c * v.x + b.d * v.y;
+      };
+      auto bwd = [&](const Blk4& b, double2 v) {   // transpose of a block stored at the neighbour
+        y0 += b.a * v.x + b.c * v.y;
+        y1 += b.b * v.x + b.d * v.y;
+      };
+      fwd(P0, xc);
+      fwd(PE, xcR);
+      fwd(PN, xn);
+      fwd(PNE, xnR);
+      fwd(PNW, xnL);
+      bwd(PEL, xcL);
+      bwd(cN, xs);
+      bwd(cNEL, xsL);
+      bwd(cNWR, xsR);
+      reinterpret_cast<double2*>(y)[(size_t)j * nxn + i] = make_double2(y0, y1);
+      acc[0] += y0 * xc.x + y1 * xc.y;
+    }
+    cN = PN;
+    cNE = PNE;
+    cNW = PNW;
+    xs = xc;
+    xc = xn;
   }
   if (partials) {
     block_sum<1>(acc, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+    if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
   }
 }
 
@@ -2185,10 +2278,12 @@ void launch_dense_inverse(hipStream_t s, double* M, int nd) {
   VP_LAUNCH_CHECK();
 }
 
-void launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials) {
-  hipLaunchKernelGGL(k_apply_fine, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, x, y,
-                     partials);
+int launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials) {
+  const unsigned gx = (unsigned)((L.nxn + 63) / 64);
+  const unsigned gy = (unsigned)((L.nyn + kWalkRows * (kBlock / 64) - 1) / (kWalkRows * (kBlock / 64)));
+  hipLaunchKernelGGL(k_apply_fine, dim3(gx, gy), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, x, y, partials);
   VP_LAUNCH_CHECK();
+  return (int)(gx * gy);
 }
 
 }  // namespace vp

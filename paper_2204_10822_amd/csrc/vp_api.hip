@@ -111,9 +111,12 @@ void ensure_krylov(vp_ctx c, int restart) {
 // ---------------------------------------------------------------------------
 }  // namespace
 
-void vp::launch_apply_K(vp_ctx c, const double* x, double* y, double* partials) {
-  if (c->order == 2) launch_q2_apply(c, x, y, partials);
-  else launch_apply_fine(c->stream, c->lev[0], x, y, partials);
+int vp::launch_apply_K(vp_ctx c, const double* x, double* y, double* partials) {
+  if (c->order == 2) {
+    launch_q2_apply(c, x, y, partials);
+    return (int)grid_for(c->nn);
+  }
+  return launch_apply_fine(c->stream, c->lev[0], x, y, partials);
 }
 
 namespace {
@@ -252,9 +255,9 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
     launch_fcg_dir(s, c->dscal, z, p, n, 1);
     while (it < o.maxit) {
       const int pr = prof_begin(c, VP_KID_APPLY_FINE);
-      launch_apply_K(c, p, q, c->partials);  // q = K p, p.q
+      const int nbq = launch_apply_K(c, p, q, c->partials);  // q = K p, p.q
       prof_end(c, pr);
-      finish(c, (int)grid_for(c->lev[0].nn), 1, 1);
+      finish(c, nbq, 1, 1);
       nb = launch_fcg_update(s, c->dscal, x, r, p, q, n, c->partials, r32, dsc);
       finish(c, nb, 1, 4);
       fetch(c, 0, 5);

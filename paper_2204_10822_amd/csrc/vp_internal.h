@@ -295,7 +295,7 @@ void rs_export(vp_ctx c, int level, int* A_ptr, int* A_col, double* A_val, int* 
 void launch_q2_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
 void launch_q2_pi_init(vp_ctx c, const double* v, double* pi);
 // the Krylov operator of the context: the Q1 stencil in lev[0], or the Q2 operator
-void launch_apply_K(vp_ctx c, const double* x, double* y, double* partials);
+int launch_apply_K(vp_ctx c, const double* x, double* y, double* partials);
 
 // reductions / BLAS-1 (vector length n doubles)
 void launch_finish_sum(hipStream_t s, const double* partials, int nblocks, int K, double* out);
@@ -326,5 +326,6 @@ void launch_fill(hipStream_t s, double* x, double v, size_t n);
 template <typename TM, typename TV>
 void launch_stencil_residual(hipStream_t s, const Level& L, const TM* A, const TV* x, const TV* b,
                              TV* r);
-void launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials);
+// y = A x on the finest level (FP64), x.y partials; returns the number of partials
+int launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials);
 }  // namespace vp
