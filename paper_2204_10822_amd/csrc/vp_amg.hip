@@ -468,15 +468,13 @@ k_sten_resid(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __
 }
 
 // y = A x (FP64 finest level), partial sums of x.y per workgroup (for CG).
-// Each wave covers 64 columns of a strip of kWalkRows node rows and walks up
-// it: the stored blocks of the row below (north, north-east, north-west planes)
-// and x of the rows below/at/above stay in registers from the previous step,
-// and the left and right neighbours' values come from the adjacent lanes, so
-// every stored block and x value is read from memory once per strip (lanes at a
+// Each wave covers 64 columns of a strip of TR node rows and walks up it: the
+// stored blocks of the row below (north, north-east, north-west planes) and x
+// of the rows below/at/above stay in registers from the previous step, and the
+// left and right neighbours' values come from the adjacent lanes, so every
+// stored block and x value is read from memory once per strip (lanes at a
 // wave's edge load their outside neighbour's values).  A workgroup is four
-// waves on four consecutive strips.
-constexpr int kWalkRows = 8;
-
+// waves: WX side by side along x times 4/WX strips along y.
 struct Blk4 {
   double a, b, c, d;  // block entries (0,0), (0,1), (1,0), (1,1)
 };
@@ -502,13 +500,16 @@ __device__ __forceinline__ Blk4 lane_blk(const Blk4& b, int src) {
   return Blk4{__shfl(b.a, src, 64), __shfl(b.b, src, 64), __shfl(b.c, src, 64), __shfl(b.d, src, 64)};
 }
 
+template <int TR, int WX>
 __global__ void __launch_bounds__(kBlock)
 k_apply_fine(const double* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
              double* __restrict__ y, double* __restrict__ partials) {
+  constexpr int kWalkRows = TR;
+  constexpr int WY = kBlock / 64 / WX;   // waves along y
   __shared__ double lds[16];
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 64 + lane;
-  const int j0 = (blockIdx.y * (kBlock / 64) + (int)(threadIdx.x >> 6)) * kWalkRows;
+  const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6);
+  const int i = (blockIdx.x * WX + wv % WX) * 64 + lane;
+  const int j0 = (blockIdx.y * WY + wv / WX) * kWalkRows;
   const bool in = i < nxn;
   const int ic = in ? i : -1;  // -1: every load of an idle lane returns zeros
   const int lm = (lane + 63) & 63, lp = (lane + 1) & 63;
@@ -518,6 +519,7 @@ k_apply_fine(const double* __restrict__ A, size_t nn, int nxn, int nyn, const do
   double2 xs = walk_x(x, nxn, nyn, ic, j0 - 1);
   double2 xc = walk_x(x, nxn, nyn, ic, j0);
   double acc[1] = {0.0};
+#pragma unroll
   for (int t = 0; t < kWalkRows; ++t) {
     const int j = j0 + t;   // uniform across the wave
     if (j >= nyn) break;
@@ -1511,6 +1513,7 @@ void amg_free(vp_ctx c) {
     dfree(L.Ptent);
     dfree(L.P64);
     dfree(L.P32);
+    dfree(L.Ph);
     dfree(L.Bnull);
     dfree(L.lmax);
     dfree(L.pv0);
@@ -1651,6 +1654,10 @@ void bf16_copies(vp_ctx c, hipStream_t s, int finest, bool coarse_fp16) {
       hipLaunchKernelGGL(k_scale_p<3>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          (const double*)L.dsc64, (const double*)N.dsc64, L.P32);
     VP_LAUNCH_CHECK();
+    if (l == 0 && finest == 2) {   // the finest transfers read the scaled prolongator in FP16
+      if (!L.Ph) L.Ph = dalloc<_Float16>(np);
+      convert(s, (const float*)L.P32, L.Ph, np);
+    }
   }
   Level& C = c->lev[c->nlev - 1];
   const int nd = C.B * (int)C.nn;
@@ -1870,6 +1877,9 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   {
     const char* env = std::getenv("VP_AMG_PAIRS");   // VP_AMG_PAIRS=0: one launch per sweep
     c->pair_sweeps = !(env && env[0] == '0');
+    const char* ph = std::getenv("VP_AMG_P16");      // VP_AMG_P16=0: FP32 finest transfers in the FP16 modes
+    c->ph_transfers = !(ph && ph[0] == '0') && c->lev[0].Ph != nullptr &&
+                      (precision == VP_PREC_FP16_BF16COARSE || precision == VP_PREC_FP16);
   }
   c->amg_ready = true;
 }
@@ -2178,7 +2188,8 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     const bool bf = ((c->amg_prec == VP_PREC_FP32_BF16COARSE || c->amg_prec == VP_PREC_FP16_BF16COARSE) && l > 0) ||
                     c->amg_prec == VP_PREC_BF16;
     if ((l == 0 && c->amg_prec == VP_PREC_FP16_BF16COARSE) || c->amg_prec == VP_PREC_FP16) {
-      if (L.B == 2) run(std::integral_constant<int, 2>(), _Float16(), float(), L.Ah, L.P32);
+      if (l == 0 && c->ph_transfers) run(std::integral_constant<int, 2>(), _Float16(), _Float16(), L.Ah, L.Ph);
+      else if (L.B == 2) run(std::integral_constant<int, 2>(), _Float16(), float(), L.Ah, L.P32);
       else run(std::integral_constant<int, 3>(), _Float16(), float(), L.Ah, L.P32);
     } else if (L.B == 2 && bf) run(std::integral_constant<int, 2>(), __hip_bfloat16(), float(), L.Abf, L.P32);
     else if (L.B == 2) run(std::integral_constant<int, 2>(), float(), float(), L.A32, L.P32);
@@ -2278,12 +2289,21 @@ void launch_dense_inverse(hipStream_t s, double* M, int nd) {
   VP_LAUNCH_CHECK();
 }
 
-int launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials) {
-  const unsigned gx = (unsigned)((L.nxn + 63) / 64);
-  const unsigned gy = (unsigned)((L.nyn + kWalkRows * (kBlock / 64) - 1) / (kWalkRows * (kBlock / 64)));
-  hipLaunchKernelGGL(k_apply_fine, dim3(gx, gy), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, x, y, partials);
+template <int TR, int WX>
+int launch_walk(hipStream_t s, const Level& L, const double* x, double* y, double* partials) {
+  constexpr int WY = kBlock / 64 / WX;
+  const unsigned gx = (unsigned)((L.nxn + 64 * WX - 1) / (64 * WX));
+  const unsigned gy = (unsigned)((L.nyn + TR * WY - 1) / (TR * WY));
+  hipLaunchKernelGGL((k_apply_fine<TR, WX>), dim3(gx, gy), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, x, y,
+                     partials);
   VP_LAUNCH_CHECK();
   return (int)(gx * gy);
+}
+
+int launch_apply_fine(hipStream_t s, const Level& L, const double* x, double* y, double* partials) {
+  // two-row strips, four waves side by side (256 columns): measured best of strip
+  // heights 2-16 and 1-4 waves across on 2049^2 nodes
+  return launch_walk<2, 4>(s, L, x, y, partials);
 }
 
 }  // namespace vp

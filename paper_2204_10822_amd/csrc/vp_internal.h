@@ -148,6 +148,7 @@ struct Level {
   float* A32 = nullptr;
   __hip_bfloat16* Abf = nullptr; // Jacobi-scaled values (mixed+bf16 mode, levels >= 1)
   _Float16* Ah = nullptr;         // Jacobi-scaled FP16 values (finest level, FP16 mode)
+  _Float16* Ph = nullptr;         // FP16 copy of the scaled prolongator (finest level, FP16 modes)
   double* dsc64 = nullptr;       // sqrt(diag A) per dof (bf16 mode, levels >= 1)
   bool own_A64 = true;
   // transfer to the next level (aggregation of 3x3 nodes)
@@ -222,6 +223,7 @@ struct vp_ctx_s {
   int amg_prec = 0;
   int amg_kind = 0;                // VP_AMG_SA or VP_AMG_RS
   bool sa_vec64 = false;           // the SA V-cycle vectors are FP64
+  bool ph_transfers = false;       // finest restriction/prolongation read the FP16 prolongator
   vp::RSHier* rs = nullptr;        // classical AMG hierarchy
   int cheb_degree = 3;
   int tail_level = -1;             // first level run by the single-workgroup tail kernel
