@@ -1996,20 +1996,31 @@ void launch_tail(vp_ctx c, int l0) {
 // Finest-level smoothing with the sweeps fused in pairs (k_cheb_pair); the same
 // sequence of per-node operations as smooth().  Pre-smoothing from x = 0 returns
 // the buffer holding r = b - A x; post-smoothing leaves x updated in place.
-// Tile shape and workgroup per value type (measured at 2049^2: FP32 vectors
-// 64 x 16 tiles, 1024 threads, at most 4 waves per SIMD; FP64 128 x 8, 256 threads).
+// Tile shape and workgroup per value type, measured at 2049^2 nodes: FP32
+// vectors 62 x 14 tiles, 1024 threads, at most 4 waves per SIMD (5% faster
+// V-cycles than 64 x 16); FP64 30 x 30 tiles, 256 threads (1.5% faster than
+// 128 x 8).  Ringed tiles of 32^2 and 64 x 16 nodes fill whole rounds of threads.
 template <int MODE, int XM, typename TM, typename TV>
 void launch_pair(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV* rin, const TV* xin, TV* rout,
                  TV* dout, TV* xout, double c1a, double c1b, double c2a, double c2b) {
   using TA = typename Acc<TV>::type;
-  constexpr bool f64 = std::is_same<TV, double>::value;
-  constexpr int TX = f64 ? 128 : 64, TY = f64 ? 8 : 16, NT = f64 ? 256 : 1024, W = f64 ? 8 : 4;
-  const int tx = (L.nxn + TX - 1) / TX, ty = (L.nyn + TY - 1) / TY;
-  const int tiles = tx * ty;
-  const unsigned g = (unsigned)((tiles + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_cheb_pair<MODE, XM, TM, TV, TX, TY, NT, W>), dim3(g), dim3(NT), 0, c->stream, A, L.nn, L.nxn,
-                     L.nyn, tx, tiles, vin, rin, xin, rout, dout, xout, (TA)c1a, (TA)c1b, (TA)c2a, (TA)c2b);
-  VP_LAUNCH_CHECK();
+  auto go = [&](auto tx_, auto ty_, auto nt_, auto w_) {
+    constexpr int TX = decltype(tx_)::value, TY = decltype(ty_)::value, NT = decltype(nt_)::value,
+                  W = decltype(w_)::value;
+    const int tx = (L.nxn + TX - 1) / TX, ty = (L.nyn + TY - 1) / TY;
+    const int tiles = tx * ty;
+    const unsigned g = (unsigned)((tiles + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_cheb_pair<MODE, XM, TM, TV, TX, TY, NT, W>), dim3(g), dim3(NT), 0, c->stream, A, L.nn,
+                       L.nxn, L.nyn, tx, tiles, vin, rin, xin, rout, dout, xout, (TA)c1a, (TA)c1b, (TA)c2a, (TA)c2b);
+    VP_LAUNCH_CHECK();
+  };
+  using std::integral_constant;
+  if constexpr (std::is_same<TV, double>::value)
+    go(integral_constant<int, 30>(), integral_constant<int, 30>(), integral_constant<int, 256>(),
+       integral_constant<int, 8>());
+  else  // the ringed tile (64 x 16) is exactly one node per thread for the first sweep
+    go(integral_constant<int, 62>(), integral_constant<int, 14>(), integral_constant<int, 1024>(),
+       integral_constant<int, 4>());
 }
 
 struct ChebCoef {
