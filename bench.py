@@ -103,11 +103,11 @@ _STORAGE = {"fp64": ("double", "double"), "fp32": ("float", "float"), "fp16": ("
 def kernel_name(kid, kind):
     """Name in the rocprofv3 summaries of the kernel behind a profiled kernel id."""
     tm, tv = _STORAGE[kind]
-    return {"apply_fine": "k_apply_fine",
-            "cheb_step0": f"k_cheb_step<2, {tm}, {tv}>",
-            "sten_resid0": f"k_sten_resid<2, {tm}, {tv}>",
-            "cheb_pair0": (f"k_cheb_pair<0, 0, {tm}, {tv}, 128, 8, 256, 8>" if tv == "double"
-                           else f"k_cheb_pair<0, 0, {tm}, {tv}, 64, 16, 1024, 4>"),
+    return {"apply_fine": "k_apply_fine<2, 4>",
+            "cheb_step0": f"k_cheb_step<2, {tm}, {tv}, 0>",
+            "sten_resid0": f"k_sten_resid<2, {tm}, {tv}, 0>",
+            "cheb_pair0": (f"k_cheb_pair<0, 0, {tm}, {tv}, 30, 30, 256, 8>" if tv == "double"
+                           else f"k_cheb_pair<0, 0, {tm}, {tv}, 62, 14, 1024, 4>"),
             "residual": "k_residual",
             "assemble": "k_assemble"}.get(kid)
 
