@@ -23,8 +23,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16+learned": 2, "bf16all": 3, "bf16all+learned": 3,
-        "fp16": 4, "fp16+learned": 4, "fp16all": 5, "fp16all+learned": 5}
+PREC = {"fp64": 0, "fp32": 1, "fp32+learned": 1, "bf16": 2, "bf16+learned": 2, "bf16all": 3, "bf16all+learned": 3,
+        "fp16": 4, "fp16+learned": 4, "fp16all": 5, "fp16all+learned": 5, "fp16c32": 6, "fp16c32+learned": 6}
 METRIC = "time-to-1e-8 residual, 2048^2 mesh: plain FP64 vs mixed+learned; SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak
@@ -112,6 +112,16 @@ def kernel_name(kid, kind):
             "assemble": "k_assemble"}.get(kid)
 
 
+def dtype_of(path):
+    """Arithmetic types a path computes in: the V-cycle's storage and arithmetic, plus
+    BF16 for the learned start's network."""
+    t = {0: "f64", 1: "f64+f32", 2: "f64+f32+bf16", 3: "f64+f32+bf16", 4: "f64+f32+fp16+bf16",
+         5: "f64+f32+fp16", 6: "f64+f32+fp16"}[PREC[path]]
+    if path.endswith("learned") and "bf16" not in t:
+        t += "+bf16"
+    return t
+
+
 def storage_kind(path):
     """Finest-level operator storage of a benchmark path."""
     p = PREC[path]
@@ -157,8 +167,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--paths", default="fp64,fp32,fp16,fp16all,fp16all+learned",
-                    help="comma list of fp64, fp32, bf16, bf16+learned, bf16all, bf16all+learned, fp16, fp16+learned, fp16all, fp16all+learned")
+    ap.add_argument("--paths", default="fp64,fp32,fp16,fp16all+learned,fp16c32",
+                    help="comma list of fp64, fp32, fp32+learned, bf16, bf16+learned, bf16all, bf16all+learned, fp16, fp16+learned, fp16all, "
+                         "fp16all+learned, fp16c32 (FP16 finest, FP32 coarse), fp16c32+learned")
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels"],
@@ -273,8 +284,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f64+f32"}.get(best, "f64+f32+fp16+bf16" if best.startswith("fp16")
-                                                        else "f64+f32+bf16"),
+        "dtype": dtype_of(best),
         "data": "synthetic",
         "config": {"workload": w.name, "mesh": f"{n}x{n} Q1", "unknowns": 2 * nn,
                    "tol": 1e-8, "path": best, "newton_its": R["newton"], "krylov_its": R["krylov"]},

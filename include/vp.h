@@ -78,7 +78,7 @@ enum {
 };
 enum { VP_SVN = 0, VP_STDN = 1 };                         /* linearisation          */
 enum { VP_PREC_FP64 = 0, VP_PREC_FP32 = 1, VP_PREC_FP32_BF16COARSE = 2, VP_PREC_BF16 = 3,
-       VP_PREC_FP16_BF16COARSE = 4, VP_PREC_FP16 = 5 };
+       VP_PREC_FP16_BF16COARSE = 4, VP_PREC_FP16 = 5, VP_PREC_FP16_FP32COARSE = 6 };
 enum { VP_KRYLOV_FGMRES = 0, VP_KRYLOV_FCG = 1 };
 enum { VP_LS_ENERGY = 0, VP_LS_RESIDUAL = 1 };
 
@@ -142,7 +142,10 @@ typedef struct {
                             FP64; FP32; FP32 finest + BF16 Jacobi-scaled coarse levels;
                             BF16 Jacobi-scaled on every level (FP32 arithmetic);
                             FP16 Jacobi-scaled finest + BF16 Jacobi-scaled coarse;
-                            FP16 Jacobi-scaled on every level                      */
+                            FP16 Jacobi-scaled on every level;
+                            FP16 Jacobi-scaled finest smoothing with the residual
+                            after the coarse-grid correction in FP32, and FP32
+                            Jacobi-scaled coarse levels                            */
   double cheb_ratio;     /* smoothing interval [lmax/ratio, lmax]                  */
   double omega_scale;    /* prolongator damping scale (1 = 4/(3 lmax))             */
   int kind;              /* VP_AMG_SA or VP_AMG_RS                                 */

@@ -1317,6 +1317,7 @@ __global__ void k_diag_sqrt(const double* __restrict__ A, size_t nn, double* __r
 
 __device__ __forceinline__ void store16(__hip_bfloat16* p, double v) { *p = __float2bfloat16((float)v); }
 __device__ __forceinline__ void store16(_Float16* p, double v) { *p = (_Float16)(float)v; }
+__device__ __forceinline__ void store16(float* p, double v) { *p = (float)v; }
 
 // S = D^{-1/2} A D^{-1/2} stored in 16 bits (BF16 or FP16; same 5-block layout)
 template <int B, typename T16>
@@ -1602,10 +1603,11 @@ void alloc_vectors(vp_ctx c) {
 // S_l = D_l^{-1/2} A_l D_l^{-1/2} in BF16 and the V-cycle works there in the
 // scaled variables, with prolongators P^_l = D_l^{1/2} P_l D_{l+1}^{-1/2} (FP32;
 // D_0 = I) and the coarsest inverse D^{1/2} A^{-1} D^{1/2} (FP32).
-// 16-bit copies of the operators for the mixed modes.  finest: 0 FP32 (unscaled),
-// 1 BF16 Jacobi-scaled, 2 FP16 Jacobi-scaled; coarse levels are Jacobi-scaled in
-// FP16 (coarse_fp16) or BF16.
-void bf16_copies(vp_ctx c, hipStream_t s, int finest, bool coarse_fp16) {
+// Reduced-precision copies of the operators for the mixed modes.  finest: 0 FP32
+// (unscaled), 1 BF16 Jacobi-scaled, 2 FP16 Jacobi-scaled; coarse levels are
+// Jacobi-scaled in BF16 (coarse 0), FP16 (1) or FP32 (2).
+void bf16_copies(vp_ctx c, hipStream_t s, int finest, int coarse) {
+  const bool coarse_fp16 = coarse == 1;
   const bool finest_scaled = finest != 0;
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
@@ -1622,7 +1624,15 @@ void bf16_copies(vp_ctx c, hipStream_t s, int finest, bool coarse_fp16) {
     else
       hipLaunchKernelGGL(k_diag_sqrt<3>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
     VP_LAUNCH_CHECK();
-    if ((l == 0 && finest == 2) || (l > 0 && coarse_fp16)) {
+    if (l > 0 && coarse == 2) {
+      if (!L.A32) L.A32 = dalloc<float>(na);
+      if (L.B == 2)
+        hipLaunchKernelGGL((k_scale_to_16<2, float>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
+                           L.A32);
+      else
+        hipLaunchKernelGGL((k_scale_to_16<3, float>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
+                           L.A32);
+    } else if ((l == 0 && finest == 2) || (l > 0 && coarse_fp16)) {
       if (!L.Ah) L.Ah = dalloc<_Float16>(na);
       if (L.B == 2)
         hipLaunchKernelGGL((k_scale_to_16<2, _Float16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
@@ -1834,9 +1844,18 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   VP_LAUNCH_CHECK();
   // reduced-precision copies
   if (precision == VP_PREC_FP32_BF16COARSE || precision == VP_PREC_BF16 || precision == VP_PREC_FP16_BF16COARSE ||
-      precision == VP_PREC_FP16) {
+      precision == VP_PREC_FP16 || precision == VP_PREC_FP16_FP32COARSE) {
     const int finest = precision == VP_PREC_BF16 ? 1 : precision == VP_PREC_FP32_BF16COARSE ? 0 : 2;
-    bf16_copies(c, s, finest, precision == VP_PREC_FP16);
+    const int coarse = precision == VP_PREC_FP16 ? 1 : precision == VP_PREC_FP16_FP32COARSE ? 2 : 0;
+    bf16_copies(c, s, finest, coarse);
+    if (precision == VP_PREC_FP16_FP32COARSE) {   // FP32 scaled finest operator for the post-correction residual
+      Level& L0 = c->lev[0];
+      const size_t na0 = (size_t)20 * L0.nn;
+      if (!L0.A32) L0.A32 = dalloc<float>(na0);
+      hipLaunchKernelGGL((k_scale_to_16<2, float>), dim3((unsigned)((L0.nn + 255) / 256)), dim3(256), 0, s, L0.A64,
+                         L0.nn, L0.nxn, L0.nyn, L0.dsc64, L0.A32);
+      VP_LAUNCH_CHECK();
+    }
   } else if (precision != VP_PREC_FP64) {
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
@@ -1879,7 +1898,8 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     c->pair_sweeps = !(env && env[0] == '0');
     const char* ph = std::getenv("VP_AMG_P16");      // VP_AMG_P16=0: FP32 finest transfers in the FP16 modes
     c->ph_transfers = !(ph && ph[0] == '0') && c->lev[0].Ph != nullptr &&
-                      (precision == VP_PREC_FP16_BF16COARSE || precision == VP_PREC_FP16);
+                      (precision == VP_PREC_FP16_BF16COARSE || precision == VP_PREC_FP16 ||
+                       precision == VP_PREC_FP16_FP32COARSE);
   }
   c->amg_ready = true;
 }
@@ -1905,7 +1925,7 @@ void sten_resid(vp_ctx c, int l, const Level& L, const TM* A, const TV* x, const
 // spectral bound).
 template <int B, typename TM, typename TV, int ST = 0>
 void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bool pre, int degree,
-            double ratio, double lmax_h = 0.0) {
+            double ratio, double lmax_h = 0.0, const float* Ares = nullptr) {
   hipStream_t s = c->stream;
   using TA = typename Acc<TV>::type;
   TV* r = (TV*)L.r;
@@ -1922,13 +1942,27 @@ void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bo
                        degree == 1 ? r : nullptr, d[0], degree == 1 ? x : nullptr, inv_theta, 0);
     VP_LAUNCH_CHECK();
   } else if (degree == 1) {
-    sten_resid<B, TM, TV, ST>(c, l, L, A, (const TV*)x, b, r);
+    if constexpr (std::is_same<TV, float>::value && ST == 0) {
+      if (Ares) sten_resid<B, float, TV, ST>(c, l, L, Ares, (const TV*)x, b, r);
+      else sten_resid<B, TM, TV, ST>(c, l, L, A, (const TV*)x, b, r);
+    } else {
+      sten_resid<B, TM, TV, ST>(c, l, L, A, (const TV*)x, b, r);
+    }
     hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(g), dim3(kBlock), 0, s, A, L.nn, (const TV*)r,
                        (TV*)nullptr, d[0], x, inv_theta, 1);
     VP_LAUNCH_CHECK();
   } else {
-    hipLaunchKernelGGL((k_resid_first<B, TM, TV, ST>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
-                       (const TV*)x, b, r, d[0], inv_theta);
+    bool done = false;
+    if constexpr (std::is_same<TV, float>::value && ST == 0) {
+      if (Ares) {   // post-correction residual from the FP32 operator (see smooth_post_pairs)
+        hipLaunchKernelGGL((k_resid_first<B, float, TV, ST>), dim3(g), dim3(kBlock), 0, s, Ares, L.nn, L.nxn, L.nyn,
+                           (const TV*)x, b, r, d[0], inv_theta);
+        done = true;
+      }
+    }
+    if (!done)
+      hipLaunchKernelGGL((k_resid_first<B, TM, TV, ST>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
+                         (const TV*)x, b, r, d[0], inv_theta);
     VP_LAUNCH_CHECK();
   }
   for (int k = 1; k < degree; ++k) {
@@ -1937,8 +1971,17 @@ void smooth(vp_ctx c, int l, const Level& L, const TM* A, const TV* b, TV* x, bo
     const int xmode = k > 1 ? 0 : pre ? 2 : 1;
     const TV* rin = (pre && k == 1) ? b : (const TV*)r;
     const int pr = (l == 0 && xmode == 0) ? prof_begin(c, VP_KID_CHEB_STEP0) : -1;
-    hipLaunchKernelGGL((k_cheb_step<B, TM, TV, ST>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
-                       (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], (const TV*)x, x, (TA)cdd, (TA)cdr, xmode);
+    bool done = false;
+    if constexpr (std::is_same<TV, float>::value && ST == 0) {
+      if (Ares && !pre && k == 1) {   // the first post-correction pass: residual and step 1 in FP32
+        hipLaunchKernelGGL((k_cheb_step<B, float, TV, ST>), dim3(g), dim3(kBlock), 0, s, Ares, L.nn, L.nxn, L.nyn,
+                           (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], (const TV*)x, x, (TA)cdd, (TA)cdr, xmode);
+        done = true;
+      }
+    }
+    if (!done)
+      hipLaunchKernelGGL((k_cheb_step<B, TM, TV, ST>), dim3(g), dim3(kBlock), 0, s, A, L.nn, L.nxn, L.nyn,
+                         (const TV*)d[(k - 1) & 1], rin, r, d[k & 1], (const TV*)x, x, (TA)cdd, (TA)cdr, xmode);
     VP_LAUNCH_CHECK();
     prof_end(c, pr);
     rho = rn;
@@ -1962,7 +2005,7 @@ void launch_tail(vp_ctx c, int l0) {
     T.b = L.b; T.x = L.x; T.r = L.r; T.d0 = L.d0; T.d1 = L.d1;
     T.P = fp64 ? (const void*)L.P64 : (const void*)L.P32;
     if (fp64) T.A = L.A64;
-    else if (prec == VP_PREC_FP32) T.A = L.A32;
+    else if (prec == VP_PREC_FP32 || prec == VP_PREC_FP16_FP32COARSE) T.A = L.A32;
     else if (prec == VP_PREC_FP16) T.A = L.Ah;
     else T.A = L.Abf;
     // the coefficients of smooth(), in the same arithmetic
@@ -1984,7 +2027,7 @@ void launch_tail(vp_ctx c, int l0) {
   hipStream_t s = c->stream;
   if (fp64)
     hipLaunchKernelGGL((k_vcycle_tail<double, double, double>), dim3(1), dim3(kTailThreads), 0, s, a);
-  else if (prec == VP_PREC_FP32)
+  else if (prec == VP_PREC_FP32 || prec == VP_PREC_FP16_FP32COARSE)
     hipLaunchKernelGGL((k_vcycle_tail<float, float, float>), dim3(1), dim3(kTailThreads), 0, s, a);
   else if (prec == VP_PREC_FP16)
     hipLaunchKernelGGL((k_vcycle_tail<_Float16, float, float>), dim3(1), dim3(kTailThreads), 0, s, a);
@@ -2086,15 +2129,27 @@ const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, T
 }
 
 template <typename TM, typename TV>
-void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x) {
+// Ares (FP32 vectors only, nullable): operator for the first pass (the residual
+// b - A x after the coarse-grid correction and the first Chebyshev step).  That
+// residual is small next to A x, so a 16-bit operator's rounding would dominate it.
+void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x, const float* Ares = nullptr) {
   using TA = typename Acc<TV>::type;
   const int m = c->cheb_degree - 1;
   const ChebCoef k = cheb_coefficients(L.lmax_h, c->cheb_ratio, c->cheb_degree);
   TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
   TV* rb[2] = {(TV*)L.r, (TV*)L.r2};
   TV* x2 = (TV*)L.x2;
-  launch_pair<PAIR_RFIRST_STEP, 1>(c, L, A, (const TV*)x, b, (const TV*)x, rb[0], d[1], x2, k.inv_theta, 0.0,
-                                   k.cdd[1], k.cdr[1]);
+  bool done = false;
+  if constexpr (std::is_same<TV, float>::value) {
+    if (Ares) {
+      launch_pair<PAIR_RFIRST_STEP, 1>(c, L, Ares, (const TV*)x, b, (const TV*)x, rb[0], d[1], x2, k.inv_theta, 0.0,
+                                       k.cdd[1], k.cdr[1]);
+      done = true;
+    }
+  }
+  if (!done)
+    launch_pair<PAIR_RFIRST_STEP, 1>(c, L, A, (const TV*)x, b, (const TV*)x, rb[0], d[1], x2, k.inv_theta, 0.0,
+                                     k.cdd[1], k.cdr[1]);
   const TV* xcur = x2;
   TV* rcur = rb[0];
   int di = 1, ri = 1;
@@ -2186,8 +2241,9 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
                        L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
     VP_LAUNCH_CHECK();
     if constexpr (B == 2) {
-      if (pairs) smooth_post_pairs<TM, TV>(c, L, A, b, x);
-      else smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
+      const float* Ares = (l == 0 && c->amg_prec == VP_PREC_FP16_FP32COARSE) ? L.A32 : nullptr;
+      if (pairs) smooth_post_pairs<TM, TV>(c, L, A, b, x, Ares);
+      else smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio, 0.0, Ares);
     } else {
       smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
     }
@@ -2198,7 +2254,8 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
   } else {
     const bool bf = ((c->amg_prec == VP_PREC_FP32_BF16COARSE || c->amg_prec == VP_PREC_FP16_BF16COARSE) && l > 0) ||
                     c->amg_prec == VP_PREC_BF16;
-    if ((l == 0 && c->amg_prec == VP_PREC_FP16_BF16COARSE) || c->amg_prec == VP_PREC_FP16) {
+    if ((l == 0 && (c->amg_prec == VP_PREC_FP16_BF16COARSE || c->amg_prec == VP_PREC_FP16_FP32COARSE)) ||
+        c->amg_prec == VP_PREC_FP16) {
       if (l == 0 && c->ph_transfers) run(std::integral_constant<int, 2>(), _Float16(), _Float16(), L.Ah, L.Ph);
       else if (L.B == 2) run(std::integral_constant<int, 2>(), _Float16(), float(), L.Ah, L.P32);
       else run(std::integral_constant<int, 3>(), _Float16(), float(), L.Ah, L.P32);
@@ -2213,7 +2270,8 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
 
 // The finest level runs in Jacobi-scaled variables (16-bit finest storage).
 bool scaled_finest(vp_ctx c) {
-  return c->amg_prec == VP_PREC_BF16 || c->amg_prec == VP_PREC_FP16_BF16COARSE || c->amg_prec == VP_PREC_FP16;
+  return c->amg_prec == VP_PREC_BF16 || c->amg_prec == VP_PREC_FP16_BF16COARSE || c->amg_prec == VP_PREC_FP16 ||
+         c->amg_prec == VP_PREC_FP16_FP32COARSE;
 }
 
 // z = M^{-1} r (FP64 in/out; V-cycle in the setup's precision)

@@ -304,7 +304,7 @@ void amg_setup(vp_ctx c, const vp_amg_opts& a) {
   c->amg_kind = VP_AMG_SA;
   require(a.cheb_degree >= 1 && a.cheb_degree <= 16, VP_EINVAL, "cheb_degree out of range");
   require(a.max_coarse >= 8 && a.max_coarse <= 1024, VP_EINVAL, "max_coarse out of range");
-  require(a.precision >= 0 && a.precision <= 5, VP_EINVAL, "bad precision");
+  require(a.precision >= 0 && a.precision <= VP_PREC_FP16_FP32COARSE, VP_EINVAL, "bad precision");
   require(c->order == 1 || a.precision <= VP_PREC_FP32_BF16COARSE, VP_EINVAL,
           "Q2 elements take the FP64, FP32 or FP32 + BF16-coarse V-cycle");
   require(a.cheb_ratio > 1.0 && a.omega_scale > 0.0, VP_EINVAL, "bad smoother options");

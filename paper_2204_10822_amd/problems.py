@@ -26,7 +26,7 @@ import torch
 from . import inputs, vp
 
 PREC = {"fp64": vp.VP_PREC_FP64, "fp32": vp.VP_PREC_FP32, "bf16": vp.VP_PREC_FP32_BF16COARSE,
-        "fp16": vp.VP_PREC_FP16_BF16COARSE, "fp16all": vp.VP_PREC_FP16}
+        "fp16": vp.VP_PREC_FP16_BF16COARSE, "fp16all": vp.VP_PREC_FP16, "fp16c32": vp.VP_PREC_FP16_FP32COARSE}
 
 
 def run_problem_one(n: int, variant: str, precision: str = "fp64", tol: float = 1e-4, maxit: int = 200,

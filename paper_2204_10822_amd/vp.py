@@ -20,6 +20,7 @@ VP_EINVAL, VP_EHIP, VP_ENOMEM, VP_ESTATE, VP_ENONFINITE, VP_EBREAKDOWN = -1, -2,
 VP_SVN, VP_STDN = 0, 1
 VP_PREC_FP64, VP_PREC_FP32, VP_PREC_FP32_BF16COARSE, VP_PREC_BF16, VP_PREC_FP16_BF16COARSE, VP_PREC_FP16 = \
     0, 1, 2, 3, 4, 5
+VP_PREC_FP16_FP32COARSE = 6
 VP_KRYLOV_FGMRES, VP_KRYLOV_FCG = 0, 1
 VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
 VP_AMG_SA, VP_AMG_RS = 0, 1

@@ -131,7 +131,7 @@ def test_pi_update_and_init_parity(vp, nx, ny, seed):
 
 
 @pytest.mark.parametrize("method", ["fgmres", "fcg"])
-@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5, 6])
 def test_krylov_solves_assembled_system(vp, method, prec):
     nx, ny, seed = 64, 48, 5
     w, prob, ctx = _case(vp, nx, ny, seed)
@@ -224,11 +224,12 @@ def test_vcycle_reduced_precision_close_to_fp64(vp):
     """The FP32 V-cycle applies the same operator as the FP64 one up to FP32
     rounding; with BF16 coarse operators (Jacobi-scaled) the difference is of the
     order of BF16 rounding, with an FP16 finest level below that, and FP16 on
-    every level of the order of FP16 rounding.  Fresh contexts give all the same
-    spectral estimates."""
+    every level of the order of FP16 rounding; FP16 finest smoothing with the
+    post-correction residual and the coarse levels in FP32 lies between FP32 and
+    FP16.  Fresh contexts give all the same spectral estimates."""
     nx, ny, seed = 64, 48, 5
     outs = {}
-    for prec in (0, 1, 2, 3, 4, 5):
+    for prec in (0, 1, 2, 3, 4, 5, 6):
         w, prob, ctx = _case(vp, nx, ny, seed)
         v = O.newton_solve(prob, maxit=2).v
         ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
@@ -246,13 +247,16 @@ def test_vcycle_reduced_precision_close_to_fp64(vp):
     dba = _relerr(outs[3], outs[0])
     dh = _relerr(outs[4], outs[0])
     dha = _relerr(outs[5], outs[0])
+    dhc = _relerr(outs[6], outs[0])
     print(f"[vcycle] fp32 vs fp64 {d32:.2e}  bf16-coarse vs fp64 {dbf:.2e}  bf16-all vs fp64 {dba:.2e}  "
-          f"fp16-finest vs fp64 {dh:.2e}  fp16-all vs fp64 {dha:.2e}", flush=True)
+          f"fp16-finest vs fp64 {dh:.2e}  fp16-all vs fp64 {dha:.2e}  fp16-finest-fp32-coarse vs fp64 {dhc:.2e}",
+          flush=True)
     assert d32 < 1e-4
     assert dbf < 5e-2
     assert dba < 1e-1
     assert dh < 5e-2
     assert dha < 1e-2
+    assert dhc < dha
 
 
 def _stencil_matrix(blocks, nxn, nyn, B):
@@ -351,7 +355,7 @@ def test_galerkin_coarse_operators(vp, nx, ny, seed):
         assert err < 1e-12
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 5])
+@pytest.mark.parametrize("prec", [0, 1, 2, 5, 6])
 def test_vcycle_tail_kernel_matches_per_sweep_launches(vp, prec, monkeypatch):
     """The single-workgroup kernel for the smallest levels runs the same per-node
     arithmetic as the one-launch-per-sweep path: the V-cycle outputs are bitwise
@@ -378,7 +382,7 @@ def test_vcycle_tail_kernel_matches_per_sweep_launches(vp, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("degree", [2, 3, 4, 5])
-@pytest.mark.parametrize("prec", [0, 1, 5])
+@pytest.mark.parametrize("prec", [0, 1, 5, 6])
 def test_paired_sweeps_match_single_sweeps(vp, prec, degree, monkeypatch):
     """The finest-level smoother with its sweeps fused in pairs (two Chebyshev
     steps per pass, the ring of each tile recomputed) gives bitwise the V-cycle of
