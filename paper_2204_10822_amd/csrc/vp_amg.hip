@@ -1303,6 +1303,85 @@ k_galerkin_ptw(const double* __restrict__ P, const double* __restrict__ W, size_
   }
 }
 
+// ---- Q2 elements: unsmoothed first level --------------------------------------
+// P = Ptent in slot 0 (the node's own aggregate), the other slots zero.
+__global__ void k_tent_to_p(const double* __restrict__ Ptent, size_t nn, double* __restrict__ P) {
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  for (int sl = 0; sl < 4; ++sl)
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c) P[pidx(2, nn, sl, n, r, c)] = sl == 0 ? Ptent[(size_t)(r * 3 + c) * nn + n] : 0.0;
+}
+
+// storage plane of the forward offset (ox, oy) of the Q2 25-point stencil
+__device__ __forceinline__ int q2_plane(int ox, int oy) { return oy == 0 ? ox : 3 + (oy - 1) * 5 + (ox + 2); }
+
+// Level-1 operator of Q2 elements: Ac = Ptent^T K2 Ptent with the tentative
+// (unsmoothed) prolongator, one thread per coarse node.  Nodes of aggregates I and
+// J couple through K2 only within two nodes of each other, so Ac is again a block
+// 9-point stencil (5 stored 3x3 blocks); the diagonal block is symmetrised and
+// empty coarse dofs get a unit diagonal, as in the smoothed Galerkin product.
+__global__ void __launch_bounds__(kBlock)
+k_galerkin_tent25(const double* __restrict__ K, const double* __restrict__ Ptent, size_t nn, int nxn, int nyn,
+                  int ncx, int ncy, double* __restrict__ Ac) {
+  const size_t ncn = (size_t)ncx * ncy;
+  const size_t I = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= ncn) return;
+  const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
+#pragma unroll 1
+  for (int t = 0; t < 5; ++t) {
+    const int Jx = Ix + (t == 1 || t == 3 ? 1 : t == 4 ? -1 : 0);
+    const int Jy = Iy + (t >= 2 ? 1 : 0);
+    const bool valid = !(Jx < 0 || Jx >= ncx || Jy >= ncy);
+    double acc[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) acc[a][c] = 0.0;
+    if (valid) {
+      for (int j = 3 * Iy; j <= agg_last(Iy, nyn, ncy); ++j)
+        for (int i = 3 * Ix; i <= agg_last(Ix, nxn, ncx); ++i) {
+          const size_t n = (size_t)j * nxn + i;
+          double W[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+          for (int jj = max(3 * Jy, j - 2); jj <= min(agg_last(Jy, nyn, ncy), j + 2); ++jj)
+            for (int ii = max(3 * Jx, i - 2); ii <= min(agg_last(Jx, nxn, ncx), i + 2); ++ii) {
+              const int ox = ii - i, oy = jj - j;
+              const size_t m = (size_t)jj * nxn + ii;
+              double kb[2][2];
+              if (oy > 0 || (oy == 0 && ox >= 0)) {
+                const int pl = q2_plane(ox, oy);
+                for (int r = 0; r < 2; ++r)
+                  for (int c = 0; c < 2; ++c) kb[r][c] = K[aidx(2, nn, pl, n, r, c)];
+              } else {
+                const int pl = q2_plane(-ox, -oy);
+                for (int r = 0; r < 2; ++r)
+                  for (int c = 0; c < 2; ++c) kb[r][c] = K[aidx(2, nn, pl, m, c, r)];
+              }
+              for (int k = 0; k < 2; ++k)
+                for (int c = 0; c < 3; ++c) {
+                  const double pv = Ptent[(size_t)(k * 3 + c) * nn + m];
+                  for (int r = 0; r < 2; ++r) W[r][c] += kb[r][k] * pv;
+                }
+            }
+          for (int k = 0; k < 2; ++k)
+            for (int c = 0; c < 3; ++c) {
+              const double wv = W[k][c];
+              for (int a = 0; a < 3; ++a) acc[a][c] += Ptent[(size_t)(k * 3 + a) * nn + n] * wv;
+            }
+        }
+    }
+    if (t == 0) {
+      for (int a = 0; a < 3; ++a)
+        for (int c = a + 1; c < 3; ++c) {
+          const double sv = 0.5 * (acc[a][c] + acc[c][a]);
+          acc[a][c] = acc[c][a] = sv;
+        }
+      for (int a = 0; a < 3; ++a)
+        if (acc[a][a] == 0.0) acc[a][a] = 1.0;
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) Ac[aidx(3, ncn, t, I, a, c)] = valid ? acc[a][c] : 0.0;
+  }
+}
+
 // ---- BF16 coarse storage: Jacobi-scaled operators --------------------------
 // dsc = sqrt(diag(A)) per dof (point diagonal of the self block)
 template <int B>
@@ -1614,8 +1693,10 @@ void bf16_copies(vp_ctx c, hipStream_t s, int finest, int coarse) {
     const size_t na = (size_t)5 * L.B * L.B * L.nn;
     const unsigned g = (unsigned)((L.nn + 255) / 256);
     if (l == 0 && finest == 0) {
-      if (!L.A32) L.A32 = dalloc<float>(na);
-      convert(s, L.A64, L.A32, na);
+      if (c->order == 1) {   // Q2: the finest level runs on K2_32
+        if (!L.A32) L.A32 = dalloc<float>(na);
+        convert(s, L.A64, L.A32, na);
+      }
       continue;
     }
     if (!L.dsc64) L.dsc64 = dalloc<double>((size_t)L.B * L.nn);
@@ -1759,9 +1840,24 @@ void q2_smoother_setup(vp_ctx c, int precision) {
 void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   if (!c->amg_struct) throw Error(VP_ESTATE, "AMG structure missing");
   hipStream_t s = c->stream;
+  const bool q2u = c->order == 2;
+  if (c->order == 2) q2_smoother_setup(c, precision);
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const unsigned g = (unsigned)((L.nn + kBlock - 1) / kBlock);
+    if (l == 0 && q2u) {
+      // Q2 elements: the finest level is smoothed with K2 (its bound from
+      // q2_smoother_setup) and restricted with the tentative prolongator
+      VP_HIP(hipMemcpyAsync(L.lmax, c->lmax_q2, sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (c->nlev == 1) break;
+      hipLaunchKernelGGL(k_tent_to_p, dim3(g), dim3(kBlock), 0, s, L.Ptent, L.nn, L.P64);
+      VP_LAUNCH_CHECK();
+      Level& N = c->lev[1];
+      hipLaunchKernelGGL(k_galerkin_tent25, dim3((unsigned)((N.nn + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                         (const double*)c->K2, (const double*)L.Ptent, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
+      VP_LAUNCH_CHECK();
+      continue;
+    }
     if (L.B == 2)
       hipLaunchKernelGGL(k_gershgorin<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, c->partials);
     else
@@ -1860,8 +1956,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
       const size_t na = (size_t)5 * L.B * L.B * L.nn;
-      if (!L.A32) L.A32 = dalloc<float>(na);
-      convert(s, L.A64, L.A32, na);
+      if (l > 0 || c->order == 1) {   // Q2: the finest level runs on K2_32
+        if (!L.A32) L.A32 = dalloc<float>(na);
+        convert(s, L.A64, L.A32, na);
+      }
       if (L.P64) {
         const size_t np = (size_t)4 * L.B * 3 * L.nn;
         if (!L.P32) L.P32 = dalloc<float>(np);
@@ -1873,7 +1971,6 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       }
     }
   }
-  if (c->order == 2) q2_smoother_setup(c, precision);
   const bool vec64 = precision == VP_PREC_FP64;
   if (c->lev[0].x == nullptr || vec64 != c->sa_vec64) {
     if (vec64) alloc_vectors<double>(c);
@@ -2198,7 +2295,7 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
   Level& N = c->lev[l + 1];
   if (l == 0 && c->order == 2) {
     // Q2 elements: smooth with the 25-point operator, restrict/prolong with the
-    // refined Q1 level's transfers
+    // tentative prolongator (stored in slot 0 of P)
     auto q2 = [&](auto tm_tag, const void* Kv) {
       using TM = decltype(tm_tag);
       const TM* K = (const TM*)Kv;

@@ -457,15 +457,9 @@ int vp_create(const vp_problem_desc* desc, void* stream, vp_ctx* out) {
       c->lev[0].A64 = dalloc<double>(20 * c->nn);
       c->lev[0].nxn = e.nxn; c->lev[0].nyn = e.nyn; c->lev[0].B = 2; c->lev[0].nn = c->nn;
       if (c->order == 2) {
-        // the refined Q1 mesh (same nodes) whose standard-Newton operator builds the AMG
-        ElemConst& r = c->ec1;
-        r = e;
-        r.nx = 2 * e.nx; r.ny = 2 * e.ny;
-        r.hx = 0.5 * e.hx; r.hy = 0.5 * e.hy; r.wq = 0.25 * r.hx * r.hy;
-        c->P1 = dalloc<double>(4 * c->ncell);
-        c->rhoH1 = dalloc<double>(4 * c->ncell);
         c->K2 = dalloc<double>((size_t)52 * c->nn);
-        c->pi1 = dalloc<double>((size_t)48 * c->ncell);
+        // the Q1 stencil storage only carries the AMG structure for Q2 elements
+        VP_HIP(hipMemsetAsync(c->lev[0].A64, 0, 20 * c->nn * sizeof(double), c->stream));
       }
     } catch (...) {
       vp_destroy(c);
@@ -483,8 +477,8 @@ void vp_destroy(vp_ctx c) {
   rs_free(c);
   amg_free(c);
   if (K) (void)hipFree(K);
-  void* bufs[] = {c->P, c->rhoH, c->F, c->vo, c->partials, c->dscal, c->work, c->kv, c->dense, c->P1, c->rhoH1,
-                  c->K2, c->pi1, c->K2_32, c->lmax_q2, c->pq0, c->pq1, c->pqn};
+  void* bufs[] = {c->P, c->rhoH, c->F, c->vo, c->partials, c->dscal, c->work, c->kv, c->dense,
+                  c->K2, c->K2_32, c->lmax_q2, c->pq0, c->pq1, c->pqn};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->hscal) (void)hipHostFree(c->hscal);

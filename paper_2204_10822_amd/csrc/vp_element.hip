@@ -376,18 +376,11 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
   }
 }
 
-// K receives the Q1 operator; with Q2 elements the Krylov operator goes to c->K2 and
-// K receives the preconditioner's operator: the standard-Newton Q1 Jacobian of the
-// refined mesh (same nodes, cells halved, cell fields copied to the four children).
+// K receives the Q1 operator; with Q2 elements the operator goes to c->K2 (the AMG
+// builds its first coarse level from it and K is not used).
 void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, double* K) {
   if (c->order == 2) {
     launch_q2_assemble(c, v, pi, variant);
-    // the preconditioner's fine level: the same Newton variant on the refined Q1
-    // mesh, svN with the dual variable interpolated to its points
-    if (variant == VP_SVN) launch_q2_pi_refine(c, pi);
-    hipLaunchKernelGGL(k_assemble, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec1, v,
-                       variant == VP_SVN ? (const double*)c->pi1 : nullptr, variant, c->vo, c->P1, c->rhoH1, K);
-    VP_LAUNCH_CHECK();
     return;
   }
   hipLaunchKernelGGL(k_assemble, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec, v, pi,

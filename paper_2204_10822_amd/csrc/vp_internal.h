@@ -195,10 +195,6 @@ struct vp_ctx_s {
   vp::ElemConst ec{};
   size_t nn = 0, ncell = 0, ndof = 0;
   int order = 1;                   // velocity elements: 1 = Q1, 2 = Q2
-  vp::ElemConst ec1{};             // Q2: the Q1 refined mesh of the preconditioner
-  double* P1 = nullptr;            // Q2: cell fields on the refined mesh [4*ncell]
-  double* rhoH1 = nullptr;
-  double* pi1 = nullptr;           // Q2: dual variable moved to the refined mesh's points [12*4*ncell]
   double* K2 = nullptr;            // Q2: the operator, 13 blocks per node
   float* K2_32 = nullptr;          // Q2: FP32 copy for the V-cycle's finest level
   double* lmax_q2 = nullptr;       // Q2: lmax(D^{-1} K2) for the finest smoother (device)
@@ -285,7 +281,6 @@ void launch_q2_residual(vp_ctx c, const double* v, const double* dv, double alph
                         unsigned* nblocks);
 void launch_q2_assemble(vp_ctx c, const double* v, const double* pi, int variant);
 void launch_q2_apply(vp_ctx c, const double* x, double* y, double* partials);
-void launch_q2_pi_refine(vp_ctx c, const double* pi);
 // classical AMG (vp_rs.hip)
 void rs_setup(vp_ctx c, double theta, double max_row_sum, int sweeps, int max_coarse);
 void rs_apply(vp_ctx c, const double* r, double* z);

@@ -135,53 +135,7 @@ __host__ __device__ constexpr int q2_dir(int ox, int oy) {
 }
 
 // ---------------------------------------------------------------------------
-// per-step precompute: refined cell fields for the Q1 preconditioner; load vector
-// ---------------------------------------------------------------------------
-__global__ void k_refine_cells(int nx, int ny, const double* __restrict__ P, const double* __restrict__ rhoH,
-                               double* __restrict__ P1, double* __restrict__ rhoH1) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (size_t)4 * nx * ny) return;
-  const int i1 = (int)(e % (2 * nx)), j1 = (int)(e / (2 * nx));
-  const size_t p = (size_t)(j1 / 2) * nx + i1 / 2;
-  P1[e] = P[p];
-  rhoH1[e] = rhoH[p];
-}
-
-// The dual variable of the refined mesh's svN operator (the preconditioner's
-// fine level): the biquadratic interpolant of a cell's 3x3 Gauss-point values,
-// evaluated at the 2x2 Gauss points of each of its four sub-cells.  Layout of
-// the result: [(q * 3 + k) * 4 ncell + e1], e1 the refined cell, q its point.
-__device__ __forceinline__ double lag_gauss3(int k, double t) {
-  double r = 1.0;
-  for (int m = 0; m < 3; ++m)
-    if (m != k) r *= (t - gauss3_pt(m)) / (gauss3_pt(k) - gauss3_pt(m));
-  return r;
-}
-
-__global__ void k_q2_pi_refine(int nx, int ny, const double* __restrict__ pi, double* __restrict__ pi1) {
-  const size_t ncell = (size_t)nx * ny, n1 = 4 * ncell;
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n1) return;
-  const int i1 = (int)(e % (2 * nx)), j1 = (int)(e / (2 * nx));
-  const size_t p = (size_t)(j1 / 2) * nx + i1 / 2;
-  constexpr double g0 = 0.21132486540518711775, g1 = 0.78867513459481288225;  // 1/2 -+ 1/(2 sqrt 3)
-  for (int q = 0; q < 4; ++q) {
-    const double tx = 0.5 * ((i1 & 1) + ((q & 1) ? g1 : g0));
-    const double ty = 0.5 * ((j1 & 1) + ((q & 2) ? g1 : g0));
-    double lx[3], ly[3];
-    for (int k = 0; k < 3; ++k) {
-      lx[k] = lag_gauss3(k, tx);
-      ly[k] = lag_gauss3(k, ty);
-    }
-    for (int k = 0; k < 3; ++k) {
-      double acc = 0.0;
-      for (int b = 0; b < 3; ++b)
-        for (int a = 0; a < 3; ++a) acc += lx[a] * ly[b] * pi[(size_t)((a + 3 * b) * 3 + k) * ncell + p];
-      pi1[(size_t)(q * 3 + k) * n1 + e] = acc;
-    }
-  }
-}
-
+// per-step precompute: the load vector
 __global__ void __launch_bounds__(kBlock)
 k_q2_load_vector(ElemConst c, const double* __restrict__ rhoH, const double* __restrict__ va,
                  const double* __restrict__ vo, const double* __restrict__ vn, double* __restrict__ F) {
@@ -520,17 +474,6 @@ __global__ void k_q2_pi_init(ElemConst c, const double* __restrict__ v, double* 
 void launch_q2_precompute(vp_ctx c, const double* va, const double* vo, const double* vprev) {
   hipLaunchKernelGGL(k_q2_load_vector, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec, c->rhoH, va, vo,
                      vprev, c->F);
-  VP_LAUNCH_CHECK();
-  const size_t n1 = 4 * c->ncell;
-  hipLaunchKernelGGL(k_refine_cells, dim3((unsigned)((n1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
-                     c->ec.nx, c->ec.ny, c->P, c->rhoH, c->P1, c->rhoH1);
-  VP_LAUNCH_CHECK();
-}
-
-void launch_q2_pi_refine(vp_ctx c, const double* pi) {
-  const size_t n1 = 4 * c->ncell;
-  hipLaunchKernelGGL(k_q2_pi_refine, dim3((unsigned)((n1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
-                     c->ec.nx, c->ec.ny, pi, c->pi1);
   VP_LAUNCH_CHECK();
 }
 

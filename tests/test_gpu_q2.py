@@ -134,10 +134,10 @@ def test_q2_pi_update_and_init_parity(vp, nx, ny, seed):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_q2_krylov_with_refined_q1_amg(vp, prec):
+def test_q2_krylov_with_amg(vp, prec):
     """FCG on the Q2 svN system: the V-cycle smooths the finest level with the Q2
-    operator and takes its coarse levels from the standard-Newton Q1 operator of
-    the refined mesh; converges to the direct solution."""
+    operator, restricts with the tentative prolongator and continues on
+    Ptent^T K2 Ptent; converges to the direct solution."""
     nx, ny, seed = 24, 20, 4
     w, prob, ctx = _case(vp, nx, ny, seed)
     v = O.newton_solve(prob, maxit=2).v
@@ -155,6 +155,65 @@ def test_q2_krylov_with_refined_q1_amg(vp, prec):
     xd = spla.spsolve(prob.jacobian_svn(v, pi).tocsc(), b)
     assert _relerr(_host(x), xd) < 1e-6
     assert info.iters < 120  # measured 80-87
+
+
+def _stencil9(blocks, nxn, nyn, B):
+    """CSR matrix of a symmetric block 9-point stencil (5 stored blocks: self, E, N, NE, NW)."""
+    nn = nxn * nyn
+    A = blocks.reshape(5, nn, B, B)
+    jj, ii = np.divmod(np.arange(nn), nxn)
+    rows, cols, vals = [], [], []
+    for b, (di, dj) in enumerate([(0, 0), (1, 0), (0, 1), (1, 1), (-1, 1)]):
+        ok = (ii + di >= 0) & (ii + di < nxn) & (jj + dj < nyn)
+        n = np.nonzero(ok)[0]
+        m = (jj[n] + dj) * nxn + ii[n] + di
+        for r in range(B):
+            for c in range(B):
+                rows.append(B * n + r); cols.append(B * m + c); vals.append(A[b, n, r, c])
+                if b > 0:
+                    rows.append(B * m + c); cols.append(B * n + r); vals.append(A[b, n, r, c])
+    M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(B * nn, B * nn)).tocsr()
+    M.sum_duplicates()
+    return M
+
+
+@pytest.mark.parametrize("nx,ny,seed", [(16, 16, 3), (23, 14, 4)])
+def test_q2_first_coarse_level_is_tentative_galerkin(vp, nx, ny, seed):
+    """Level 1 of the Q2 hierarchy is Ptent^T K2 Ptent: the exported prolongator has
+    only its own-aggregate slot, and the exported level-1 operator equals the
+    product formed here from it and the exported K2 (empty coarse dofs aside)."""
+    w, prob, ctx = _case(vp, nx, ny, seed)
+    v = _rand_v(prob, 8, 0.05)
+    ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
+    ctx.vp_amg_setup()
+    levels = ctx.vp_amg_info()
+    (nxn, nyn, B0), (cx, cy, B1) = levels[0], levels[1]
+    assert (nxn, nyn, B0) == (2 * nx + 1, 2 * ny + 1, 2) and B1 == 3
+    nn, ncn = nxn * nyn, cx * cy
+    P = torch.zeros(12 * B0, nn, dtype=torch.float64, device="cuda")
+    A1 = torch.zeros(5 * 9 * ncn, dtype=torch.float64, device="cuda")
+    ctx.vp_amg_export(0, None, P)
+    ctx.vp_amg_export(1, A1, None)
+    Pm = _host(P).reshape(4, B0, 3, nn)
+    assert np.all(Pm[1:] == 0.0)
+    agg = lambda i, na: np.minimum(i // 3, na - 1)
+    jj, ii = np.divmod(np.arange(nn), nxn)
+    I = agg(jj, cy) * cx + agg(ii, cx)
+    rows, cols, vals = [], [], []
+    for r in range(B0):
+        for c in range(3):
+            rows.append(B0 * np.arange(nn) + r); cols.append(3 * I + c); vals.append(Pm[0, r, c])
+    Pt = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(B0 * nn, 3 * ncn))
+    K2 = _q2_matrix(vp, ctx, nxn, nyn)
+    G = (Pt.T @ K2 @ Pt).toarray()
+    d = np.diag(G).copy()
+    d[d == 0.0] = 1.0
+    np.fill_diagonal(G, d)
+    Ac = _stencil9(_host(A1), cx, cy, 3).toarray()
+    err = np.linalg.norm(Ac - G) / np.linalg.norm(G)
+    print(f"[q2 galerkin] {levels[:2]} rel err {err:.2e}", flush=True)
+    assert err < 1e-13
 
 
 def test_q2_rejects_scaled_16bit_vcycle(vp):
