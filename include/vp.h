@@ -57,9 +57,9 @@ typedef struct {
   int32_t order;           /* velocity elements: 1 (or 0) = Q1 with 2x2 Gauss, 2 = Q2 */
                            /* (biquadratic, 3x3 Gauss; Sec. 5).  With Q2 the          */
                            /* operator is a block 25-point stencil, pi has 9 points   */
-                           /* per cell, and the AMG preconditioner is built on the    */
-                           /* standard-Newton Q1 operator of the 2nx x 2ny refined    */
-                           /* mesh, which has the same nodes                          */
+                           /* per cell, and the AMG smooths with the Q2 operator and   */
+                           /* coarsens it with the unsmoothed aggregation prolongator  */
+                           /* (level 1 = Ptent^T K2 Ptent, a 9-point block stencil)    */
 } vp_problem_desc;
 
 typedef struct vp_ctx_s* vp_ctx;

@@ -1792,8 +1792,8 @@ int tail_start(vp_ctx c) {
 }
 
 // Q2 elements: the V-cycle smooths the finest level with the 25-point Q2
-// operator itself (the coarse levels come from the refined Q1 operator), so its
-// Chebyshev interval needs lmax(D^{-1} K2): Gershgorin bound, then the power
+// operator itself (level 1 is Ptent^T K2 Ptent), so its Chebyshev interval
+// needs lmax(D^{-1} K2): Gershgorin bound, then the power
 // iteration warm started across setups.  FP32 V-cycles get an FP32 copy.
 void q2_smoother_setup(vp_ctx c, int precision) {
   hipStream_t s = c->stream;

@@ -1,7 +1,7 @@
 """Q2 (biquadratic) velocity elements through the C ABI against the oracle's Q2
 discretisation (Sec. 5): residual and energy, the svN and stdN operators (block
-25-point stencil), the dual update, Krylov solves preconditioned by AMG on the
-refined-mesh Q1 operator, and full Newton solves."""
+25-point stencil), the dual update, the AMG's first coarse level (tentative
+Galerkin product of the Q2 operator), Krylov solves and full Newton solves."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
