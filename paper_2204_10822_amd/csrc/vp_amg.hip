@@ -771,6 +771,198 @@ k_cheb_pair(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, 
   }
 }
 
+// The same two sweeps by column walks, for operators stored in the vector type
+// (FP64 and FP32 finest levels): a wave covers 64 columns, the 62 inner ones its
+// outputs, and walks up a strip of TR rows, evaluating the first sweep one row
+// ahead of the second (on the strip and one row on each side).  The stored blocks
+// of the last three rows, the first-sweep results of the last three rows and the
+// input vector's last three rows stay in registers; left and right neighbours come
+// from the adjacent lanes (the outer lanes load their outside neighbours).  No LDS,
+// no barrier, every value read once per strip.  Per node the operations are those
+// of k_cheb_pair in the same order, so the outputs are bitwise the same.
+template <typename TA>
+struct WBlk {
+  TA a, b, c, d;   // block entries (0,0), (0,1), (1,0), (1,1)
+};
+template <typename TA>
+struct WVec {
+  TA x, y;
+};
+template <typename TA>
+__device__ __forceinline__ WBlk<TA> wshb(const WBlk<TA>& v, int src) {
+  return WBlk<TA>{__shfl(v.a, src, 64), __shfl(v.b, src, 64), __shfl(v.c, src, 64), __shfl(v.d, src, 64)};
+}
+template <typename TA>
+__device__ __forceinline__ WVec<TA> wshv(WVec<TA> v, int src) {
+  return WVec<TA>{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
+}
+template <typename TA>
+__device__ __forceinline__ WBlk<TA> wblk(const TA* __restrict__ A, size_t nn, int p, int nxn, int nyn, int i, int j) {
+  if (i < 0 || i >= nxn || j < 0 || j >= nyn) return WBlk<TA>{TA(0), TA(0), TA(0), TA(0)};
+  const TA* q = A + aidx(2, nn, p, (size_t)j * nxn + i, 0, 0);
+  if constexpr (std::is_same<TA, double>::value) {
+    const double2 u = reinterpret_cast<const double2*>(q)[0], w = reinterpret_cast<const double2*>(q)[1];
+    return WBlk<TA>{u.x, u.y, w.x, w.y};
+  } else {
+    const float4 v = *reinterpret_cast<const float4*>(q);
+    return WBlk<TA>{v.x, v.y, v.z, v.w};
+  }
+}
+template <typename TA>
+__device__ __forceinline__ WVec<TA> wvec(const TA* __restrict__ p, int nxn, int nyn, int i, int j) {
+  if (i < 0 || i >= nxn || j < 0 || j >= nyn) return WVec<TA>{TA(0), TA(0)};
+  const size_t n = (size_t)j * nxn + i;
+  return WVec<TA>{p[2 * n], p[2 * n + 1]};
+}
+// y += b x, or b^T x for a block stored at the neighbour (the order of stencil_row_f)
+template <typename TA>
+__device__ __forceinline__ void wfwd(TA (&y)[2], const WBlk<TA>& b, WVec<TA> x) {
+  y[0] += b.a * x.x; y[0] += b.b * x.y;
+  y[1] += b.c * x.x; y[1] += b.d * x.y;
+}
+template <typename TA>
+__device__ __forceinline__ void wbwd(TA (&y)[2], const WBlk<TA>& b, WVec<TA> x) {
+  y[0] += b.a * x.x; y[0] += b.c * x.y;
+  y[1] += b.b * x.x; y[1] += b.d * x.y;
+}
+
+template <int MODE, int XM, typename TV, int TR>
+__global__ void __launch_bounds__(256)
+k_cheb_walk(const TV* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __restrict__ vin,
+            const TV* __restrict__ rin, const TV* xin, TV* __restrict__ rout, TV* __restrict__ dout, TV* xout,
+            TV c1a, TV c1b, TV c2a, TV c2b) {
+  using Bk = WBlk<TV>;
+  using Vc = WVec<TV>;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 62 - 1 + lane;
+  const int j0 = (blockIdx.y * 4 + (int)(threadIdx.x >> 6)) * TR;
+  const bool in = i >= 0 && i < nxn;
+  const int ic = in ? i : -(1 << 29);   // idle lanes load nothing
+  const int lm = (lane + 63) & 63, lp = (lane + 1) & 63;
+  const Bk z{TV(0), TV(0), TV(0), TV(0)};
+  // rows r-1 (q*) and r-2 (s*: north, north-east, north-west) of the stored blocks
+  Bk q0 = wblk(A, nn, 0, nxn, nyn, ic, j0 - 2), qE = wblk(A, nn, 1, nxn, nyn, ic, j0 - 2),
+     qN = wblk(A, nn, 2, nxn, nyn, ic, j0 - 2), qNE = wblk(A, nn, 3, nxn, nyn, ic, j0 - 2),
+     qNW = wblk(A, nn, 4, nxn, nyn, ic, j0 - 2);
+  Bk sN = z, sNE = z, sNW = z;
+  Vc vS = wvec(vin, nxn, nyn, ic, j0 - 2), vC = wvec(vin, nxn, nyn, ic, j0 - 1);
+  Vc d1pp{TV(0), TV(0)}, d1p{TV(0), TV(0)}, r1p{TV(0), TV(0)};
+  for (int r = j0 - 1; r <= j0 + TR; ++r) {
+    if (r > nyn) break;   // uniform across the wave
+    const Bk P0 = wblk(A, nn, 0, nxn, nyn, ic, r), PE = wblk(A, nn, 1, nxn, nyn, ic, r),
+             PN = wblk(A, nn, 2, nxn, nyn, ic, r), PNE = wblk(A, nn, 3, nxn, nyn, ic, r),
+             PNW = wblk(A, nn, 4, nxn, nyn, ic, r);
+    const Vc vN = wvec(vin, nxn, nyn, ic, r + 1);
+    const Vc rC = wvec(rin, nxn, nyn, ic, r);
+    // first sweep at row r
+    Vc vCL = wshv(vC, lm), vCR = wshv(vC, lp), vNL = wshv(vN, lm), vNR = wshv(vN, lp), vSL = wshv(vS, lm),
+       vSR = wshv(vS, lp);
+    Bk PEL = wshb(PE, lm), qNEL = wshb(qNE, lm), qNWR = wshb(qNW, lp);
+    if (lane == 0) {
+      vCL = wvec(vin, nxn, nyn, i - 1, r);
+      vNL = wvec(vin, nxn, nyn, i - 1, r + 1);
+      vSL = wvec(vin, nxn, nyn, i - 1, r - 1);
+      PEL = wblk(A, nn, 1, nxn, nyn, i - 1, r);
+      qNEL = wblk(A, nn, 3, nxn, nyn, i - 1, r - 1);
+    }
+    if (lane == 63) {
+      vCR = wvec(vin, nxn, nyn, i + 1, r);
+      vNR = wvec(vin, nxn, nyn, i + 1, r + 1);
+      vSR = wvec(vin, nxn, nyn, i + 1, r - 1);
+      qNWR = wblk(A, nn, 4, nxn, nyn, i + 1, r - 1);
+    }
+    Vc d1c{TV(0), TV(0)}, r1c{TV(0), TV(0)};
+    if (in && r >= 0 && r < nyn) {
+      TV y[2] = {TV(0), TV(0)};
+      const bool hE = i + 1 < nxn, hW = i > 0, hN = r + 1 < nyn, hS = r > 0;
+      wfwd(y, P0, vC);
+      if (hE) wfwd(y, PE, vCR);
+      if (hN) wfwd(y, PN, vN);
+      if (hE && hN) wfwd(y, PNE, vNR);
+      if (hW && hN) wfwd(y, PNW, vNL);
+      if (hW) wbwd(y, PEL, vCL);
+      if (hS) wbwd(y, qN, vS);
+      if (hW && hS) wbwd(y, qNEL, vSL);
+      if (hE && hS) wbwd(y, qNWR, vSR);
+      TV D[2][2] = {{P0.a, P0.b}, {P0.c, P0.d}}, Di[2][2];
+      invert_block<2>(D, Di);
+      const TV rn[2] = {rC.x - y[0], rC.y - y[1]};
+      TV t[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        t[q] = TV(0);
+        t[q] += Di[q][0] * rn[0];
+        t[q] += Di[q][1] * rn[1];
+      }
+      if constexpr (MODE == PAIR_RFIRST_STEP) d1c = Vc{t[0] * c1a, t[1] * c1a};
+      else d1c = Vc{c1a * vC.x + c1b * t[0], c1a * vC.y + c1b * t[1]};
+      r1c = Vc{rn[0], rn[1]};
+    }
+    // second sweep at row j = r - 1, inner lanes
+    const int j = r - 1;
+    const Vc dL = wshv(d1p, lm), dR = wshv(d1p, lp), dNL = wshv(d1c, lm), dNR = wshv(d1c, lp), dSL = wshv(d1pp, lm),
+             dSR = wshv(d1pp, lp);
+    const Bk qEL = wshb(qE, lm), sNEL = wshb(sNE, lm), sNWR = wshb(sNW, lp);
+    if (j >= j0 && j < nyn && in && lane >= 1 && lane <= 62) {
+      const size_t n = (size_t)j * nxn + i;
+      TV x1[2];
+      if constexpr (MODE == PAIR_RFIRST_STEP) {
+        x1[0] = xin[2 * n]; x1[1] = xin[2 * n + 1];      // the first sweep leaves x unchanged
+      } else {
+        const Vc dpn = vS;                                 // vin at row j
+        if constexpr (XM == 2) {
+          x1[0] = dpn.x; x1[1] = dpn.y;
+        } else {
+          x1[0] = xin[2 * n]; x1[1] = xin[2 * n + 1];
+          if constexpr (XM == 1) {
+            x1[0] += dpn.x; x1[1] += dpn.y;
+          }
+        }
+        x1[0] = x1[0] + d1p.x; x1[1] = x1[1] + d1p.y;
+      }
+      TV y[2] = {TV(0), TV(0)};
+      const bool hE = i + 1 < nxn, hW = i > 0, hN = j + 1 < nyn, hS = j > 0;
+      wfwd(y, q0, d1p);
+      if (hE) wfwd(y, qE, dR);
+      if (hN) wfwd(y, qN, d1c);
+      if (hE && hN) wfwd(y, qNE, dNR);
+      if (hW && hN) wfwd(y, qNW, dNL);
+      if (hW) wbwd(y, qEL, dL);
+      if (hS) wbwd(y, sN, d1pp);
+      if (hW && hS) wbwd(y, sNEL, dSL);
+      if (hE && hS) wbwd(y, sNWR, dSR);
+      const TV r2[2] = {r1p.x - y[0], r1p.y - y[1]};
+      rout[2 * n] = r2[0];
+      rout[2 * n + 1] = r2[1];
+      if constexpr (MODE == PAIR_STEP_RESID) {
+        xout[2 * n] = x1[0];
+        xout[2 * n + 1] = x1[1];
+      } else {
+        TV D[2][2] = {{q0.a, q0.b}, {q0.c, q0.d}}, Di[2][2];
+        invert_block<2>(D, Di);
+        if constexpr (MODE == PAIR_RFIRST_STEP) {
+          x1[0] += d1p.x;                                 // step 1 in xmode 1: (x + d0) + d1
+          x1[1] += d1p.y;
+        }
+        const TV d1v[2] = {d1p.x, d1p.y};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          TV t = TV(0);
+          t += Di[q][0] * r2[0];
+          t += Di[q][1] * r2[1];
+          const TV d2 = c2a * d1v[q] + c2b * t;
+          dout[2 * n + q] = d2;
+          xout[2 * n + q] = x1[q] + d2;
+        }
+      }
+    }
+    sN = qN; sNE = qNE; sNW = qNW;
+    q0 = P0; qE = PE; qN = PN; qNE = PNE; qNW = PNW;
+    vS = vC; vC = vN;
+    d1pp = d1p; d1p = d1c; r1p = r1c;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the smallest levels in one workgroup
 // ---------------------------------------------------------------------------
@@ -2155,12 +2347,20 @@ void launch_pair(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV*
     VP_LAUNCH_CHECK();
   };
   using std::integral_constant;
-  if constexpr (std::is_same<TV, double>::value)
+  if constexpr (std::is_same<TM, TV>::value) {
+    // operator in the vector type: column walks (strips of 12 rows FP64, 10 FP32)
+    constexpr int TR = std::is_same<TV, double>::value ? 12 : 10;
+    const dim3 g((unsigned)((L.nxn + 61) / 62), (unsigned)((L.nyn + 4 * TR - 1) / (4 * TR)));
+    hipLaunchKernelGGL((k_cheb_walk<MODE, XM, TV, TR>), g, dim3(256), 0, c->stream, A, L.nn, L.nxn, L.nyn, vin, rin,
+                       xin, rout, dout, xout, (TV)c1a, (TV)c1b, (TV)c2a, (TV)c2b);
+    VP_LAUNCH_CHECK();
+  } else if constexpr (std::is_same<TV, double>::value) {
     go(integral_constant<int, 30>(), integral_constant<int, 30>(), integral_constant<int, 256>(),
        integral_constant<int, 8>());
-  else  // the ringed tile (64 x 16) is exactly one node per thread for the first sweep
+  } else {  // the ringed tile (64 x 16) is exactly one node per thread for the first sweep
     go(integral_constant<int, 62>(), integral_constant<int, 14>(), integral_constant<int, 1024>(),
        integral_constant<int, 4>());
+  }
 }
 
 struct ChebCoef {
