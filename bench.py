@@ -108,6 +108,7 @@ def kernel_name(kid, kind):
             "sten_resid0": f"k_sten_resid<2, {tm}, {tv}, 0>",
             "cheb_pair0": (f"k_cheb_walk<0, 0, {tv}, {12 if tv == 'double' else 10}>" if tm == tv
                            else f"k_cheb_pair<0, 0, {tm}, {tv}, 62, 14, 1024, 4>"),
+            "cheb_walk4": f"k_cheb_walk4<0, {tv}>",
             "residual": "k_residual",
             "assemble": "k_assemble"}.get(kid)
 

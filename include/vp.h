@@ -267,7 +267,9 @@ enum {
   VP_KID_ASSEMBLE = 4,     /* operator assembly                                      */
   VP_KID_VCYCLE = 5,       /* one whole V-cycle (composite, not a single kernel)     */
   VP_KID_CHEB_PAIR0 = 6,   /* two fused Chebyshev steps on the finest level          */
-  VP_KID_COUNT = 7
+  VP_KID_CHEB_WALK4 = 7,   /* a whole degree-4 pre- or post-smoothing on the finest
+                              level in one kernel (FP64 and FP32 operators)          */
+  VP_KID_COUNT = 8
 };
 int vp_profile(vp_ctx ctx, int enable);
 int vp_profile_read(vp_ctx ctx, int kid, double* total_ms, int* launches, double* bytes_per_launch);

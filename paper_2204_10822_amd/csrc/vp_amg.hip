@@ -424,14 +424,14 @@ __device__ __forceinline__ void group_restrict(const TP* __restrict__ P, size_t 
 // x += P xc at fine node n
 template <int B, typename TP, typename TV>
 __device__ __forceinline__ void node_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx,
-                                                 int ncy, const TV* __restrict__ xc, TV* __restrict__ x, size_t n) {
+                                                 int ncy, const TV* __restrict__ xc, const TV* xi, TV* x, size_t n) {
   using TA = typename Acc<TV>::type;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   const int ax[2] = {agg_of(i, ncx), agg_other(i, nxn, ncx)};
   const int ay[2] = {agg_of(j, ncy), agg_other(j, nyn, ncy)};
   TA acc[B];
 #pragma unroll
-  for (int rr = 0; rr < B; ++rr) acc[rr] = (TA)x[n * B + rr];
+  for (int rr = 0; rr < B; ++rr) acc[rr] = (TA)xi[n * B + rr];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int Jx = ax[s & 1], Jy = ay[s >> 1];
@@ -621,9 +621,9 @@ k_restrict(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int n
 template <int B, typename TP, typename TV>
 __global__ void __launch_bounds__(kBlock)
 k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
-              const TV* __restrict__ xc, TV* __restrict__ x) {
+              const TV* __restrict__ xc, const TV* xi, TV* x) {
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n < nn) node_prolong_add<B>(P, nn, nxn, nyn, ncx, ncy, xc, x, n);
+  if (n < nn) node_prolong_add<B>(P, nn, nxn, nyn, ncx, ncy, xc, xi, x, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -963,6 +963,186 @@ k_cheb_walk(const TV* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __r
   }
 }
 
+// All four sweeps of a degree-4 Chebyshev smoothing in one column walk (operators
+// stored in the vector type).  A wave covers 64 columns and walks up a strip of TR
+// rows; at the step to row R it loads row R and evaluates stage k (k = 1..4) at row
+// R - k, so stage k finds the previous stage's result at rows R - k - 1, R - k and
+// R - k + 1 in registers (the last two rows kept, the newest just computed).  Each
+// stage narrows the valid lanes by one per side: lanes 4..59 of a wave are its
+// outputs (56 columns per wave) and the strip is evaluated 4 rows beyond its ends by
+// the earlier stages.  The blocks of the last five rows, their block inverses and each
+// stage's last two rows are register-resident (no LDS, no barrier).  Every node's
+// arithmetic is that of the paired kernels in the same order, so the results are
+// bitwise the same as two paired or four single sweeps.
+//   W4_PRE:  x = 0 on entry.  d0 = D^-1 b / theta, three Chebyshev steps, then the
+//            residual: writes x and r = b - A x.
+//   W4_POST: four Chebyshev steps from x (the first from r = b - A x): writes x.
+//            x is read around the strip, so the output goes to another buffer.
+// c0 = 1/theta; (a_k, b_k) are the (cdd, cdr) of steps 1..3.
+enum { W4_PRE = 0, W4_POST = 1 };
+template <typename T>
+struct WRow {
+  WBlk<T> p0, e, n, ne, nw;
+};
+template <typename T>
+__device__ __forceinline__ WRow<T> wrow(const T* __restrict__ A, size_t nn, int nxn, int nyn, int i, int j) {
+  return WRow<T>{wblk(A, nn, 0, nxn, nyn, i, j), wblk(A, nn, 1, nxn, nyn, i, j), wblk(A, nn, 2, nxn, nyn, i, j),
+                 wblk(A, nn, 3, nxn, nyn, i, j), wblk(A, nn, 4, nxn, nyn, i, j)};
+}
+template <typename T>
+__device__ __forceinline__ WBlk<T> winv(const WBlk<T>& p) {
+  T D[2][2] = {{p.a, p.b}, {p.c, p.d}}, Di[2][2];
+  invert_block<2>(D, Di);
+  return WBlk<T>{Di[0][0], Di[0][1], Di[1][0], Di[1][1]};
+}
+// y = (A u) at one node in the order of stencil_row_f: own row o, south row s (its
+// n, ne, nw blocks), u at rows j - 1, j, j + 1.  Every lane takes part in the shuffles.
+template <typename T>
+__device__ __forceinline__ void wapply(T (&y)[2], const WRow<T>& o, const WRow<T>& s, WVec<T> uS, WVec<T> uC,
+                                       WVec<T> uN, int lm, int lp, bool hE, bool hW, bool hN, bool hS) {
+  const WVec<T> uCL = wshv(uC, lm), uCR = wshv(uC, lp), uNL = wshv(uN, lm), uNR = wshv(uN, lp), uSL = wshv(uS, lm),
+                uSR = wshv(uS, lp);
+  const WBlk<T> eL = wshb(o.e, lm), sneL = wshb(s.ne, lm), snwR = wshb(s.nw, lp);
+  y[0] = T(0);
+  y[1] = T(0);
+  wfwd(y, o.p0, uC);
+  if (hE) wfwd(y, o.e, uCR);
+  if (hN) wfwd(y, o.n, uN);
+  if (hE && hN) wfwd(y, o.ne, uNR);
+  if (hW && hN) wfwd(y, o.nw, uNL);
+  if (hW) wbwd(y, eL, uCL);
+  if (hS) wbwd(y, s.n, uS);
+  if (hW && hS) wbwd(y, sneL, uSL);
+  if (hE && hS) wbwd(y, snwR, uSR);
+}
+template <typename T>
+__device__ __forceinline__ WVec<T> wsolve(const WBlk<T>& Di, const T (&r)[2]) {
+  T t0 = T(0), t1 = T(0);
+  t0 += Di.a * r[0];
+  t0 += Di.b * r[1];
+  t1 += Di.c * r[0];
+  t1 += Di.d * r[1];
+  return WVec<T>{t0, t1};
+}
+
+template <int KIND, typename T>
+__global__ void __launch_bounds__(256)
+k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const T* __restrict__ b,
+             const T* __restrict__ xin, T* __restrict__ rout, T* __restrict__ xout, T c0, T a1, T b1, T a2, T b2,
+             T a3, T b3) {
+  using Bk = WBlk<T>;
+  using Vc = WVec<T>;
+  using Rw = WRow<T>;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 56 - 4 + lane;
+  const int j0 = (blockIdx.y * 4 + (int)(threadIdx.x >> 6)) * TR;
+  const bool in = i >= 0 && i < nxn;
+  const int ic = in ? i : -(1 << 29);   // idle lanes load nothing
+  const int lm = (lane + 63) & 63, lp = (lane + 1) & 63;
+  const bool hE = i + 1 < nxn, hW = i > 0;
+  const Bk z{T(0), T(0), T(0), T(0)};
+  const Vc zv{T(0), T(0)};
+  const Rw zr{z, z, z, z, z};
+  Rw W1 = zr, W2 = zr, W3 = zr, W4 = zr, W5 = zr;   // blocks of rows R-1 .. R-5
+  Bk D1 = z, D2 = z, D3 = z, D4 = z;                  // block inverses of rows R-1 .. R-4
+  // stage k's input vector at its row minus one (uS) and its row (uC)
+  Vc uS1 = zv, uC1 = zv, uS2 = zv, uC2 = zv, uS3 = zv, uC3 = zv, uS4 = zv, uC4 = zv;
+  Vc rc1 = zv, rc2 = zv, rc3 = zv, rc4 = zv;          // residual entering stage k at its row
+  Vc xc2 = zv, xc3 = zv, xc4 = zv;                    // iterate entering stage k at its row
+  const int Rend = min(j0 + TR + 3, nyn + 3);
+  for (int R = j0 - 4; R <= Rend; ++R) {   // R is uniform across the wave
+    const Rw W0 = wrow(A, nn, nxn, nyn, ic, R);
+    const Vc bR = wvec(b, nxn, nyn, ic, R);
+    const Bk D0 = winv(W0.p0);
+    Vc u0;   // stage 1's input at row R
+    if constexpr (KIND == W4_PRE) {
+      const T bb[2] = {bR.x, bR.y};
+      const Vc t = wsolve(D0, bb);
+      u0 = Vc{t.x * c0, t.y * c0};
+    } else {
+      u0 = wvec(xin, nxn, nyn, ic, R);
+    }
+    Vc d1 = zv, r1 = zv, x1 = zv;
+    {
+      const int j = R - 1;
+      if (j >= 0 && j < nyn && j >= j0 - 3) {
+        T y[2];
+        wapply(y, W1, W2, uS1, uC1, u0, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+        const T r[2] = {rc1.x - y[0], rc1.y - y[1]};
+        const Vc t = wsolve(D1, r);
+        if constexpr (KIND == W4_PRE) {
+          d1 = Vc{a1 * uC1.x + b1 * t.x, a1 * uC1.y + b1 * t.y};
+          x1 = Vc{uC1.x + d1.x, uC1.y + d1.y};
+        } else {
+          d1 = Vc{t.x * c0, t.y * c0};
+          {
+            // the paired kernels add this step to x in their next sweep, to the
+            // rounded product: no contraction into a fused multiply-add here
+#pragma clang fp contract(off)
+            x1 = Vc{uC1.x + d1.x, uC1.y + d1.y};
+          }
+        }
+        r1 = Vc{r[0], r[1]};
+      }
+    }
+    Vc d2 = zv, r2 = zv, x2 = zv;
+    {
+      const int j = R - 2;
+      if (j >= 0 && j < nyn && j >= j0 - 2) {
+        T y[2];
+        wapply(y, W2, W3, uS2, uC2, d1, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+        const T r[2] = {rc2.x - y[0], rc2.y - y[1]};
+        const Vc t = wsolve(D2, r);
+        const T a = KIND == W4_PRE ? a2 : a1, bq = KIND == W4_PRE ? b2 : b1;
+        d2 = Vc{a * uC2.x + bq * t.x, a * uC2.y + bq * t.y};
+        x2 = Vc{xc2.x + d2.x, xc2.y + d2.y};
+        r2 = Vc{r[0], r[1]};
+      }
+    }
+    Vc d3 = zv, r3 = zv, x3 = zv;
+    {
+      const int j = R - 3;
+      if (j >= 0 && j < nyn && j >= j0 - 1) {
+        T y[2];
+        wapply(y, W3, W4, uS3, uC3, d2, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+        const T r[2] = {rc3.x - y[0], rc3.y - y[1]};
+        const Vc t = wsolve(D3, r);
+        const T a = KIND == W4_PRE ? a3 : a2, bq = KIND == W4_PRE ? b3 : b2;
+        d3 = Vc{a * uC3.x + bq * t.x, a * uC3.y + bq * t.y};
+        x3 = Vc{xc3.x + d3.x, xc3.y + d3.y};
+        r3 = Vc{r[0], r[1]};
+      }
+    }
+    {
+      const int j = R - 4;   // stage 4: the outputs
+      if (j >= j0 && j < nyn) {
+        T y[2];
+        wapply(y, W4, W5, uS4, uC4, d3, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+        const T r[2] = {rc4.x - y[0], rc4.y - y[1]};
+        if (in && lane >= 4 && lane < 60) {
+          const size_t n = (size_t)j * nxn + i;
+          if constexpr (KIND == W4_PRE) {
+            rout[2 * n] = r[0];
+            rout[2 * n + 1] = r[1];
+            xout[2 * n] = xc4.x;
+            xout[2 * n + 1] = xc4.y;
+          } else {
+            const Vc t = wsolve(D4, r);
+            const T d[2] = {a3 * uC4.x + b3 * t.x, a3 * uC4.y + b3 * t.y};
+            xout[2 * n] = xc4.x + d[0];
+            xout[2 * n + 1] = xc4.y + d[1];
+          }
+        }
+      }
+    }
+    W5 = W4; W4 = W3; W3 = W2; W2 = W1; W1 = W0;
+    D4 = D3; D3 = D2; D2 = D1; D1 = D0;
+    uS4 = uC4; uC4 = d3; uS3 = uC3; uC3 = d2; uS2 = uC2; uC2 = d1; uS1 = uC1; uC1 = u0;
+    rc4 = r3; rc3 = r2; rc2 = r1; rc1 = bR;
+    xc4 = x3; xc3 = x2; xc2 = x1;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the smallest levels in one workgroup
 // ---------------------------------------------------------------------------
@@ -1047,7 +1227,8 @@ __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs a) {
     const TailLevel& L = a.L[l];
     const TailLevel& N = a.L[l + 1];
     for (size_t n = t0; n < L.nn; n += nt)
-      node_prolong_add<3>((const TP*)L.P, (size_t)L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)N.x, (TV*)L.x, n);
+      node_prolong_add<3>((const TP*)L.P, (size_t)L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const TV*)N.x, (const TV*)L.x,
+                          (TV*)L.x, n);
     __syncthreads();
     tail_smooth<TM, TV>(L, (const TV*)L.b, (TV*)L.x, false, a.degree);
   }
@@ -2383,11 +2564,43 @@ inline ChebCoef cheb_coefficients(double lmax_h, double ratio, int degree) {
   return k;
 }
 
+// Degree-4 smoothing by one four-sweep column walk.  The strip height is the
+// smallest whose workgroups are all resident at once: a second, partial round of
+// workgroups costs up to half the kernel's time.
+template <int KIND, typename T>
+void launch_walk4(vp_ctx c, const Level& L, const T* A, const T* b, const T* xin, T* rout, T* xout,
+                  const ChebCoef& k) {
+  int& resident = c->walk4_resident[std::is_same<T, double>::value ? 1 : 0][KIND];
+  if (resident == 0) {
+    int ncu = 0, per_cu = 0;
+    VP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    VP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_cheb_walk4<KIND, T>), 256, 0));
+    resident = std::max(1, ncu * per_cu);
+  }
+  const int gx = (L.nxn + 55) / 56;
+  const int gy_fit = std::max(1, resident / gx);   // workgroup rows (4 strips each) that fit
+  const int tr = std::max(8, (L.nyn + 4 * gy_fit - 1) / (4 * gy_fit));
+  const int gy = (L.nyn + 4 * tr - 1) / (4 * tr);
+  hipLaunchKernelGGL((k_cheb_walk4<KIND, T>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, c->stream, tr, A, L.nn,
+                     L.nxn, L.nyn, b, xin, rout, xout, (T)k.inv_theta, (T)k.cdd[1], (T)k.cdr[1], (T)k.cdd[2],
+                     (T)k.cdr[2], (T)k.cdd[3], (T)k.cdr[3]);
+  VP_LAUNCH_CHECK();
+}
+
 template <typename TM, typename TV>
 const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x) {
   using TA = typename Acc<TV>::type;
   const int m = c->cheb_degree - 1;
   const ChebCoef k = cheb_coefficients(L.lmax_h, c->cheb_ratio, c->cheb_degree);
+  if constexpr (std::is_same<TM, TV>::value) {
+    if (c->cheb_degree == 4) {
+      const int pr = prof_begin(c, VP_KID_CHEB_WALK4);
+      launch_walk4<W4_PRE, TV>(c, L, A, b, nullptr, (TV*)L.r, x, k);
+      prof_end(c, pr);
+      return (const TV*)L.r;
+    }
+  }
   TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
   TV* rb[2] = {(TV*)L.r, (TV*)L.r2};
   hipLaunchKernelGGL((k_cheb_first<2, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, b,
@@ -2429,13 +2642,22 @@ template <typename TM, typename TV>
 // Ares (FP32 vectors only, nullable): operator for the first pass (the residual
 // b - A x after the coarse-grid correction and the first Chebyshev step).  That
 // residual is small next to A x, so a 16-bit operator's rounding would dominate it.
-void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x, const float* Ares = nullptr) {
+void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x, const float* Ares = nullptr,
+                       const TV* xin = nullptr) {
   using TA = typename Acc<TV>::type;
   const int m = c->cheb_degree - 1;
   const ChebCoef k = cheb_coefficients(L.lmax_h, c->cheb_ratio, c->cheb_degree);
   TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
   TV* rb[2] = {(TV*)L.r, (TV*)L.r2};
   TV* x2 = (TV*)L.x2;
+  if constexpr (std::is_same<TM, TV>::value) {
+    if (c->cheb_degree == 4 && !Ares && xin) {
+      const int pr = prof_begin(c, VP_KID_CHEB_WALK4);
+      launch_walk4<W4_POST, TV>(c, L, A, b, xin, nullptr, x, k);
+      prof_end(c, pr);
+      return;
+    }
+  }
   bool done = false;
   if constexpr (std::is_same<TV, float>::value) {
     if (Ares) {
@@ -2507,7 +2729,7 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
       VP_LAUNCH_CHECK();
       vcycle_level<TV>(c, 1, (const TV*)N.b, (TV*)N.x);
       hipLaunchKernelGGL((k_prolong_add<2, TPv, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, Pp, L.nn, L.nxn,
-                         L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
+                         L.nyn, L.ncx, L.ncy, (const TV*)N.x, (const TV*)x, x);
       VP_LAUNCH_CHECK();
       smooth<2, TM, TV, 1>(c, 0, L, K, b, x, false, c->cheb_degree, c->cheb_ratio, c->lmax_q2_h);
     };
@@ -2534,12 +2756,17 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
                        s, P, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, rres, (TV*)N.b);
     VP_LAUNCH_CHECK();
     vcycle_level<TV>(c, l + 1, (const TV*)N.b, (TV*)N.x);
+    const float* Ares = (B == 2 && l == 0 && c->amg_prec == VP_PREC_FP16_FP32COARSE) ? L.A32 : nullptr;
+    // the four-sweep walk reads the corrected x around its strips, so the correction
+    // goes to a second buffer and the walk writes x
+    const bool walk4 = pairs && std::is_same<TM, TV>::value && c->cheb_degree == 4 && !Ares;
+    TV* xcor = walk4 ? (TV*)L.x2 : x;
     hipLaunchKernelGGL((k_prolong_add<B, TP, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
-                       L.nyn, L.ncx, L.ncy, (const TV*)N.x, x);
+                       L.nyn, L.ncx, L.ncy, (const TV*)N.x, (const TV*)x, xcor);
     VP_LAUNCH_CHECK();
     if constexpr (B == 2) {
-      const float* Ares = (l == 0 && c->amg_prec == VP_PREC_FP16_FP32COARSE) ? L.A32 : nullptr;
-      if (pairs) smooth_post_pairs<TM, TV>(c, L, A, b, x, Ares);
+      if (walk4) smooth_post_pairs<TM, TV>(c, L, A, b, x, nullptr, (const TV*)xcor);
+      else if (pairs) smooth_post_pairs<TM, TV>(c, L, A, b, x, Ares);
       else smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio, 0.0, Ares);
     } else {
       smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);

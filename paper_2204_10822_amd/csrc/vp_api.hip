@@ -708,6 +708,9 @@ int vp_profile_read(vp_ctx c, int kid, double* total_ms, int* launches, double* 
       case VP_KID_CHEB_PAIR0:   // A once + three vectors read and three written, for two steps
         b = c->amg_prec >= VP_PREC_BF16 ? nn * (20 * 2 + 6 * 8) : f32 ? nn * (20 * 4 + 6 * 8) : nn * (20 * 8 + 6 * 16);
         break;
+      case VP_KID_CHEB_WALK4:   // A once, b, and x in + x out (post) or x and r out (pre)
+        b = f32 ? nn * (20 * 4 + 3 * 8) : nn * (20 * 8 + 3 * 16);
+        break;
       case VP_KID_RESIDUAL: b = nn * 64 + nc * 16; break;
       case VP_KID_ASSEMBLE: b = nn * (32 + 160) + nc * (16 + 96); break;
       default: b = 0.0;

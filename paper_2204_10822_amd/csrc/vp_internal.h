@@ -192,6 +192,7 @@ struct vp_ctx_s {
   vp_problem_desc desc{};
   hipStream_t stream = nullptr;
   int device = 0;
+  int walk4_resident[2][2] = {{0, 0}, {0, 0}};   // workgroups of k_cheb_walk4 resident at once ([FP64][kind])
   vp::ElemConst ec{};
   size_t nn = 0, ncell = 0, ndof = 0;
   int order = 1;                   // velocity elements: 1 = Q1, 2 = Q2

@@ -35,7 +35,8 @@ EXPORTED_NET = ["vpnet_create", "vpnet_destroy", "vpnet_last_error", "vpnet_para
                 "vpnet_set_params", "vpnet_get_params", "vpnet_get_grads", "vpnet_forward",
                 "vpnet_backward", "vpnet_adam", "vpnet_train_step", "vpnet_features",
                 "vpnet_targets", "vpnet_guess", "vpnet_gemm"]
-VP_KID = dict(apply_fine=0, cheb_step0=1, sten_resid0=2, residual=3, assemble=4, vcycle=5, cheb_pair0=6)
+VP_KID = dict(apply_fine=0, cheb_step0=1, sten_resid0=2, residual=3, assemble=4, vcycle=5, cheb_pair0=6,
+              cheb_walk4=7)
 
 
 class vp_problem_desc(C.Structure):
