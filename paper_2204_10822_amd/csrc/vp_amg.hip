@@ -973,7 +973,8 @@ k_cheb_walk(const TV* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __r
 // the earlier stages.  The blocks of the last five rows, their block inverses and each
 // stage's last two rows are register-resident (no LDS, no barrier).  Every node's
 // arithmetic is that of the paired kernels in the same order, so the results are
-// bitwise the same as two paired or four single sweeps.
+// bitwise the same as two paired or four single sweeps.  The next row's loads are
+// issued before the current row is evaluated.
 //   W4_PRE:  x = 0 on entry.  d0 = D^-1 b / theta, three Chebyshev steps, then the
 //            residual: writes x and r = b - A x.
 //   W4_POST: four Chebyshev steps from x (the first from r = b - A x): writes x.
@@ -1050,9 +1051,16 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
   Vc rc1 = zv, rc2 = zv, rc3 = zv, rc4 = zv;          // residual entering stage k at its row
   Vc xc2 = zv, xc3 = zv, xc4 = zv;                    // iterate entering stage k at its row
   const int Rend = min(j0 + TR + 3, nyn + 3);
+  // row R + 1 is loaded while row R is evaluated
+  Rw Wn = wrow(A, nn, nxn, nyn, ic, j0 - 4);
+  Vc bn = wvec(b, nxn, nyn, ic, j0 - 4), xn = zv;
+  if constexpr (KIND == W4_POST) xn = wvec(xin, nxn, nyn, ic, j0 - 4);
   for (int R = j0 - 4; R <= Rend; ++R) {   // R is uniform across the wave
-    const Rw W0 = wrow(A, nn, nxn, nyn, ic, R);
-    const Vc bR = wvec(b, nxn, nyn, ic, R);
+    const Rw W0 = Wn;
+    const Vc bR = bn, xR = xn;
+    Wn = wrow(A, nn, nxn, nyn, ic, R + 1);
+    bn = wvec(b, nxn, nyn, ic, R + 1);
+    if constexpr (KIND == W4_POST) xn = wvec(xin, nxn, nyn, ic, R + 1);
     const Bk D0 = winv(W0.p0);
     Vc u0;   // stage 1's input at row R
     if constexpr (KIND == W4_PRE) {
@@ -1060,7 +1068,7 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
       const Vc t = wsolve(D0, bb);
       u0 = Vc{t.x * c0, t.y * c0};
     } else {
-      u0 = wvec(xin, nxn, nyn, ic, R);
+      u0 = xR;
     }
     Vc d1 = zv, r1 = zv, x1 = zv;
     {
