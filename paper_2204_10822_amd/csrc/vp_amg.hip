@@ -1151,6 +1151,217 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
   }
 }
 
+// Paired sweeps by column walks on the structured coarse levels (3 x 3 blocks, FP32
+// operator and vectors): the scheme of k_cheb_walk with runtime strip height TR and
+// register blocks of 9 values.  The two Chebyshev combinations are written as
+// explicit fused multiply-adds, fma(c_dd, d, c_dr * t), which is how the single-sweep
+// kernels contract them, so the outputs are bitwise those of two single sweeps.
+struct W3Blk {
+  float v[9];
+};
+struct W3Vec {
+  float v[3];
+};
+__device__ __forceinline__ W3Blk w3shb(const W3Blk& x, int src) {
+  W3Blk o;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) o.v[k] = __shfl(x.v[k], src, 64);
+  return o;
+}
+__device__ __forceinline__ W3Vec w3shv(const W3Vec& x, int src) {
+  W3Vec o;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) o.v[k] = __shfl(x.v[k], src, 64);
+  return o;
+}
+__device__ __forceinline__ W3Blk w3blk(const float* __restrict__ A, size_t nn, int p, int nxn, int nyn, int i,
+                                       int j) {
+  W3Blk o;
+  if (i < 0 || i >= nxn || j < 0 || j >= nyn) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o.v[k] = 0.0f;
+    return o;
+  }
+  const float* q = A + aidx(3, nn, p, (size_t)j * nxn + i, 0, 0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) o.v[k] = q[k];
+  return o;
+}
+__device__ __forceinline__ W3Vec w3vec(const float* __restrict__ p, int nxn, int nyn, int i, int j) {
+  W3Vec o;
+  if (i < 0 || i >= nxn || j < 0 || j >= nyn) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o.v[k] = 0.0f;
+    return o;
+  }
+  const size_t n = (size_t)j * nxn + i;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) o.v[k] = p[3 * n + k];
+  return o;
+}
+// y += b x, or b^T x for a block stored at the neighbour (the order of stencil_row_f)
+__device__ __forceinline__ void w3fwd(float (&y)[3], const W3Blk& b, const W3Vec& x) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[r] += b.v[r * 3 + c] * x.v[c];
+}
+__device__ __forceinline__ void w3bwd(float (&y)[3], const W3Blk& b, const W3Vec& x) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[r] += b.v[c * 3 + r] * x.v[c];
+}
+
+template <int MODE, int XM>
+__global__ void __launch_bounds__(256)
+k_cheb_walk3(int TR, const float* __restrict__ A, size_t nn, int nxn, int nyn, const float* __restrict__ vin,
+             const float* __restrict__ rin, const float* xin, float* __restrict__ rout, float* __restrict__ dout,
+             float* xout, float c1a, float c1b, float c2a, float c2b) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 62 - 1 + lane;
+  const int j0 = (blockIdx.y * 4 + (int)(threadIdx.x >> 6)) * TR;
+  const bool in = i >= 0 && i < nxn;
+  const int ic = in ? i : -(1 << 29);   // idle lanes load nothing
+  const int lm = (lane + 63) & 63, lp = (lane + 1) & 63;
+  W3Vec zv;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) zv.v[k] = 0.0f;
+  W3Blk z;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) z.v[k] = 0.0f;
+  // rows r-1 (q*) and r-2 (s*: north, north-east, north-west) of the stored blocks
+  W3Blk q0 = w3blk(A, nn, 0, nxn, nyn, ic, j0 - 2), qE = w3blk(A, nn, 1, nxn, nyn, ic, j0 - 2),
+        qN = w3blk(A, nn, 2, nxn, nyn, ic, j0 - 2), qNE = w3blk(A, nn, 3, nxn, nyn, ic, j0 - 2),
+        qNW = w3blk(A, nn, 4, nxn, nyn, ic, j0 - 2);
+  W3Blk sN = z, sNE = z, sNW = z;
+  W3Vec vS = w3vec(vin, nxn, nyn, ic, j0 - 2), vC = w3vec(vin, nxn, nyn, ic, j0 - 1);
+  W3Vec d1pp = zv, d1p = zv, r1p = zv;
+  for (int r = j0 - 1; r <= j0 + TR; ++r) {
+    if (r > nyn) break;   // uniform across the wave
+    const W3Blk P0 = w3blk(A, nn, 0, nxn, nyn, ic, r), PE = w3blk(A, nn, 1, nxn, nyn, ic, r),
+                PN = w3blk(A, nn, 2, nxn, nyn, ic, r), PNE = w3blk(A, nn, 3, nxn, nyn, ic, r),
+                PNW = w3blk(A, nn, 4, nxn, nyn, ic, r);
+    const W3Vec vN = w3vec(vin, nxn, nyn, ic, r + 1);
+    const W3Vec rC = w3vec(rin, nxn, nyn, ic, r);
+    // first sweep at row r
+    W3Vec vCL = w3shv(vC, lm), vCR = w3shv(vC, lp), vNL = w3shv(vN, lm), vNR = w3shv(vN, lp), vSL = w3shv(vS, lm),
+          vSR = w3shv(vS, lp);
+    W3Blk PEL = w3shb(PE, lm), qNEL = w3shb(qNE, lm), qNWR = w3shb(qNW, lp);
+    if (lane == 0) {
+      vCL = w3vec(vin, nxn, nyn, i - 1, r);
+      vNL = w3vec(vin, nxn, nyn, i - 1, r + 1);
+      vSL = w3vec(vin, nxn, nyn, i - 1, r - 1);
+      PEL = w3blk(A, nn, 1, nxn, nyn, i - 1, r);
+      qNEL = w3blk(A, nn, 3, nxn, nyn, i - 1, r - 1);
+    }
+    if (lane == 63) {
+      vCR = w3vec(vin, nxn, nyn, i + 1, r);
+      vNR = w3vec(vin, nxn, nyn, i + 1, r + 1);
+      vSR = w3vec(vin, nxn, nyn, i + 1, r - 1);
+      qNWR = w3blk(A, nn, 4, nxn, nyn, i + 1, r - 1);
+    }
+    W3Vec d1c = zv, r1c = zv;
+    if (in && r >= 0 && r < nyn) {
+      float y[3] = {0.0f, 0.0f, 0.0f};
+      const bool hE = i + 1 < nxn, hW = i > 0, hN = r + 1 < nyn, hS = r > 0;
+      w3fwd(y, P0, vC);
+      if (hE) w3fwd(y, PE, vCR);
+      if (hN) w3fwd(y, PN, vN);
+      if (hE && hN) w3fwd(y, PNE, vNR);
+      if (hW && hN) w3fwd(y, PNW, vNL);
+      if (hW) w3bwd(y, PEL, vCL);
+      if (hS) w3bwd(y, qN, vS);
+      if (hW && hS) w3bwd(y, qNEL, vSL);
+      if (hE && hS) w3bwd(y, qNWR, vSR);
+      float D[3][3], Di[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) D[a][c] = P0.v[a * 3 + c];
+      invert_block<3>(D, Di);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float rn = rC.v[k] - y[k];
+        r1c.v[k] = rn;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float t = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t += Di[k][c] * r1c.v[c];
+        if constexpr (MODE == PAIR_RFIRST_STEP) d1c.v[k] = t * c1a;
+        else d1c.v[k] = fmaf(c1a, vC.v[k], c1b * t);
+      }
+    }
+    // second sweep at row j = r - 1, inner lanes
+    const int j = r - 1;
+    const W3Vec dL = w3shv(d1p, lm), dR = w3shv(d1p, lp), dNL = w3shv(d1c, lm), dNR = w3shv(d1c, lp),
+                dSL = w3shv(d1pp, lm), dSR = w3shv(d1pp, lp);
+    const W3Blk qEL = w3shb(qE, lm), sNEL = w3shb(sNE, lm), sNWR = w3shb(sNW, lp);
+    if (j >= j0 && j < nyn && in && lane >= 1 && lane <= 62) {
+      const size_t n = (size_t)j * nxn + i;
+      float x1[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if constexpr (MODE == PAIR_RFIRST_STEP) {
+          x1[k] = xin[3 * n + k];   // the first sweep leaves x unchanged
+        } else {
+          if constexpr (XM == 2) {
+            x1[k] = vS.v[k];        // vin at row j
+          } else {
+            x1[k] = xin[3 * n + k];
+            if constexpr (XM == 1) x1[k] += vS.v[k];
+          }
+          x1[k] = x1[k] + d1p.v[k];
+        }
+      }
+      float y[3] = {0.0f, 0.0f, 0.0f};
+      const bool hE = i + 1 < nxn, hW = i > 0, hN = j + 1 < nyn, hS = j > 0;
+      w3fwd(y, q0, d1p);
+      if (hE) w3fwd(y, qE, dR);
+      if (hN) w3fwd(y, qN, d1c);
+      if (hE && hN) w3fwd(y, qNE, dNR);
+      if (hW && hN) w3fwd(y, qNW, dNL);
+      if (hW) w3bwd(y, qEL, dL);
+      if (hS) w3bwd(y, sN, d1pp);
+      if (hW && hS) w3bwd(y, sNEL, dSL);
+      if (hE && hS) w3bwd(y, sNWR, dSR);
+      float r2[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        r2[k] = r1p.v[k] - y[k];
+        rout[3 * n + k] = r2[k];
+      }
+      if constexpr (MODE == PAIR_STEP_RESID) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xout[3 * n + k] = x1[k];
+      } else {
+        float D[3][3], Di[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) D[a][c] = q0.v[a * 3 + c];
+        invert_block<3>(D, Di);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if constexpr (MODE == PAIR_RFIRST_STEP) x1[k] += d1p.v[k];   // (x + d0) + d1
+          float t = 0.0f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) t += Di[k][c] * r2[c];
+          const float d2 = fmaf(c2a, d1p.v[k], c2b * t);
+          dout[3 * n + k] = d2;
+          xout[3 * n + k] = x1[k] + d2;
+        }
+      }
+    }
+    sN = qN; sNE = qNE; sNW = qNW;
+    q0 = P0; qE = PE; qN = PN; qNE = PNE; qNW = PNW;
+    vS = vC; vC = vN;
+    d1pp = d1p; d1p = d1c; r1p = r1c;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the smallest levels in one workgroup
 // ---------------------------------------------------------------------------
@@ -2050,10 +2261,8 @@ void alloc_vectors(vp_ctx c) {
     L.r = dalloc<TV>(n);
     L.d0 = dalloc<TV>(n);
     L.d1 = dalloc<TV>(n);
-    if (l == 0) {
-      L.r2 = dalloc<TV>(n);
-      L.x2 = dalloc<TV>(n);
-    }
+    L.r2 = dalloc<TV>(n);   // paired sweeps (finest level; coarse levels in FP32)
+    L.x2 = dalloc<TV>(n);
   }
 }
 
@@ -2552,6 +2761,43 @@ void launch_pair(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV*
   }
 }
 
+// Paired sweeps on a structured coarse level (B = 3, FP32): column walks whose strip
+// height is the smallest with every workgroup resident at once.  Used on levels of
+// at least kCoarsePairNodes nodes.
+constexpr size_t kCoarsePairNodes = 100000;
+template <int MODE, int XM>
+void launch_walk3(vp_ctx c, const Level& L, const float* A, const float* vin, const float* rin, const float* xin,
+                  float* rout, float* dout, float* xout, double c1a, double c1b, double c2a, double c2b) {
+  int& resident = c->walk3_resident;
+  if (resident == 0) {
+    int ncu = 0, per_cu = 0;
+    VP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    VP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_cheb_walk3<PAIR_STEP_STEP, 0>), 256, 0));
+    resident = std::max(1, ncu * per_cu);
+  }
+  const int gx = (L.nxn + 61) / 62;
+  const int gy_fit = std::max(1, resident / gx);
+  const int tr = std::max(2, (L.nyn + 4 * gy_fit - 1) / (4 * gy_fit));
+  const int gy = (L.nyn + 4 * tr - 1) / (4 * tr);
+  hipLaunchKernelGGL((k_cheb_walk3<MODE, XM>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, c->stream, tr, A, L.nn,
+                     L.nxn, L.nyn, vin, rin, xin, rout, dout, xout, (float)c1a, (float)c1b, (float)c2a, (float)c2b);
+  VP_LAUNCH_CHECK();
+}
+
+// Two Chebyshev steps in one pass: the finest level (B = 2, any storage) or a
+// structured coarse level (B = 3, FP32 operator and vectors only).
+template <int B, int MODE, int XM, typename TM, typename TV>
+void launch_pairb(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV* rin, const TV* xin, TV* rout,
+                  TV* dout, TV* xout, double c1a, double c1b, double c2a, double c2b) {
+  if constexpr (B == 2) {
+    launch_pair<MODE, XM>(c, L, A, vin, rin, xin, rout, dout, xout, c1a, c1b, c2a, c2b);
+  } else {
+    static_assert(std::is_same<TM, float>::value && std::is_same<TV, float>::value, "coarse pairs are FP32");
+    launch_walk3<MODE, XM>(c, L, A, vin, rin, xin, rout, dout, xout, c1a, c1b, c2a, c2b);
+  }
+}
+
 struct ChebCoef {
   double inv_theta;
   double cdd[32], cdr[32];   // index 1..degree-1
@@ -2596,12 +2842,13 @@ void launch_walk4(vp_ctx c, const Level& L, const T* A, const T* b, const T* xin
   VP_LAUNCH_CHECK();
 }
 
-template <typename TM, typename TV>
+template <int B, typename TM, typename TV>
 const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x) {
   using TA = typename Acc<TV>::type;
+  const bool fine = &L == &c->lev[0];
   const int m = c->cheb_degree - 1;
   const ChebCoef k = cheb_coefficients(L.lmax_h, c->cheb_ratio, c->cheb_degree);
-  if constexpr (std::is_same<TM, TV>::value) {
+  if constexpr (B == 2 && std::is_same<TM, TV>::value) {
     if (c->cheb_degree == 4) {
       const int pr = prof_begin(c, VP_KID_CHEB_WALK4);
       launch_walk4<W4_PRE, TV>(c, L, A, b, nullptr, (TV*)L.r, x, k);
@@ -2611,7 +2858,7 @@ const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, T
   }
   TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
   TV* rb[2] = {(TV*)L.r, (TV*)L.r2};
-  hipLaunchKernelGGL((k_cheb_first<2, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, b,
+  hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, b,
                      (TV*)nullptr, d[0], (TV*)nullptr, (TA)k.inv_theta, 0);
   VP_LAUNCH_CHECK();
   const TV* rcur = b;
@@ -2619,12 +2866,12 @@ const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, T
   for (int s = 1; s <= m;) {
     if (s + 1 <= m) {
       if (s == 1)
-        launch_pair<PAIR_STEP_STEP, 2>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], d[di ^ 1], x,
-                                       k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
+        launch_pairb<B, PAIR_STEP_STEP, 2>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], d[di ^ 1], x,
+                                           k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
       else {
-        const int pr = prof_begin(c, VP_KID_CHEB_PAIR0);
-        launch_pair<PAIR_STEP_STEP, 0>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], d[di ^ 1], x,
-                                       k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
+        const int pr = fine ? prof_begin(c, VP_KID_CHEB_PAIR0) : -1;
+        launch_pairb<B, PAIR_STEP_STEP, 0>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], d[di ^ 1], x,
+                                           k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
         prof_end(c, pr);
       }
       rcur = rb[ri];
@@ -2633,32 +2880,34 @@ const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, T
       s += 2;
     } else {
       if (s == 1)
-        launch_pair<PAIR_STEP_RESID, 2>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], (TV*)nullptr, x,
-                                        k.cdd[s], k.cdr[s], 0.0, 0.0);
+        launch_pairb<B, PAIR_STEP_RESID, 2>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], (TV*)nullptr, x,
+                                            k.cdd[s], k.cdr[s], 0.0, 0.0);
       else
-        launch_pair<PAIR_STEP_RESID, 0>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], (TV*)nullptr, x,
-                                        k.cdd[s], k.cdr[s], 0.0, 0.0);
+        launch_pairb<B, PAIR_STEP_RESID, 0>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], (TV*)nullptr, x,
+                                            k.cdd[s], k.cdr[s], 0.0, 0.0);
       return rb[ri];
     }
   }
   // even number of steps: the final residual alone, in place
-  sten_resid<2>(c, 0, L, A, (const TV*)d[di], rcur, (TV*)rcur);
+  sten_resid<B>(c, fine ? 0 : 1, L, A, (const TV*)d[di], rcur, (TV*)rcur);
   return rcur;
 }
 
-template <typename TM, typename TV>
 // Ares (FP32 vectors only, nullable): operator for the first pass (the residual
 // b - A x after the coarse-grid correction and the first Chebyshev step).  That
 // residual is small next to A x, so a 16-bit operator's rounding would dominate it.
+// xin (nullable): the corrected x in another buffer, for the four-sweep walk.
+template <int B, typename TM, typename TV>
 void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x, const float* Ares = nullptr,
                        const TV* xin = nullptr) {
   using TA = typename Acc<TV>::type;
+  const bool fine = &L == &c->lev[0];
   const int m = c->cheb_degree - 1;
   const ChebCoef k = cheb_coefficients(L.lmax_h, c->cheb_ratio, c->cheb_degree);
   TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
   TV* rb[2] = {(TV*)L.r, (TV*)L.r2};
   TV* x2 = (TV*)L.x2;
-  if constexpr (std::is_same<TM, TV>::value) {
+  if constexpr (B == 2 && std::is_same<TM, TV>::value) {
     if (c->cheb_degree == 4 && !Ares && xin) {
       const int pr = prof_begin(c, VP_KID_CHEB_WALK4);
       launch_walk4<W4_POST, TV>(c, L, A, b, xin, nullptr, x, k);
@@ -2667,7 +2916,7 @@ void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x
     }
   }
   bool done = false;
-  if constexpr (std::is_same<TV, float>::value) {
+  if constexpr (B == 2 && std::is_same<TV, float>::value) {
     if (Ares) {
       launch_pair<PAIR_RFIRST_STEP, 1>(c, L, Ares, (const TV*)x, b, (const TV*)x, rb[0], d[1], x2, k.inv_theta, 0.0,
                                        k.cdd[1], k.cdr[1]);
@@ -2675,23 +2924,23 @@ void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x
     }
   }
   if (!done)
-    launch_pair<PAIR_RFIRST_STEP, 1>(c, L, A, (const TV*)x, b, (const TV*)x, rb[0], d[1], x2, k.inv_theta, 0.0,
-                                     k.cdd[1], k.cdr[1]);
+    launch_pairb<B, PAIR_RFIRST_STEP, 1>(c, L, A, (const TV*)x, b, (const TV*)x, rb[0], d[1], x2, k.inv_theta, 0.0,
+                                         k.cdd[1], k.cdr[1]);
   const TV* xcur = x2;
   TV* rcur = rb[0];
   int di = 1, ri = 1;
   for (int s = 2; s <= m;) {
     if (s + 1 <= m) {
-      const int pr = prof_begin(c, VP_KID_CHEB_PAIR0);
-      launch_pair<PAIR_STEP_STEP, 0>(c, L, A, (const TV*)d[di], (const TV*)rcur, xcur, rb[ri], d[di ^ 1], x,
-                                     k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
+      const int pr = fine ? prof_begin(c, VP_KID_CHEB_PAIR0) : -1;
+      launch_pairb<B, PAIR_STEP_STEP, 0>(c, L, A, (const TV*)d[di], (const TV*)rcur, xcur, rb[ri], d[di ^ 1], x,
+                                         k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
       prof_end(c, pr);
       rcur = rb[ri];
       ri ^= 1;
       di ^= 1;
       s += 2;
     } else {
-      hipLaunchKernelGGL((k_cheb_step<2, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, L.nxn,
+      hipLaunchKernelGGL((k_cheb_step<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, L.nxn,
                          L.nyn, (const TV*)d[di], (const TV*)rcur, rcur, d[di ^ 1], xcur, x, (TA)k.cdd[s],
                          (TA)k.cdr[s], 0);
       VP_LAUNCH_CHECK();
@@ -2700,7 +2949,7 @@ void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x
     }
     xcur = x;
   }
-  if (xcur != x) VP_HIP(hipMemcpyAsync(x, xcur, sizeof(TV) * 2 * L.nn, hipMemcpyDeviceToDevice, c->stream));
+  if (xcur != x) VP_HIP(hipMemcpyAsync(x, xcur, sizeof(TV) * B * L.nn, hipMemcpyDeviceToDevice, c->stream));
 }
 
 template <typename TV>
@@ -2751,10 +3000,16 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     using TP = decltype(tp_tag);
     const TM* A = (const TM*)Av;
     const TP* P = (const TP*)Pv;
-    const bool pairs = B == 2 && l == 0 && c->pair_sweeps && c->cheb_degree >= 2 && c->cheb_degree <= 32;
+    // paired sweeps: the finest level, and the large structured coarse levels in FP32
+    // (on levels of a few ten thousand nodes a walk's strips are a few rows long and
+    // load latency makes a pair slower than two single sweeps: 15 us against 10 us at
+    // 227^2 nodes, 36 us against 50 us at 683^2)
+    constexpr bool pairable = B == 2 || (std::is_same<TM, float>::value && std::is_same<TV, float>::value);
+    const bool pairs = pairable && (B == 2 ? l == 0 : (l > 0 && L.nn >= kCoarsePairNodes)) && c->pair_sweeps &&
+                       c->cheb_degree >= 2 && c->cheb_degree <= 32;
     const TV* rres = (const TV*)L.r;
-    if constexpr (B == 2) {
-      if (pairs) rres = smooth_pre_pairs<TM, TV>(c, L, A, b, x);
+    if constexpr (pairable) {
+      if (pairs) rres = smooth_pre_pairs<B, TM, TV>(c, L, A, b, x);
       else smooth<B, TM, TV>(c, l, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
     } else {
       smooth<B, TM, TV>(c, l, L, A, b, x, true, c->cheb_degree, c->cheb_ratio);
@@ -2767,15 +3022,18 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     const float* Ares = (B == 2 && l == 0 && c->amg_prec == VP_PREC_FP16_FP32COARSE) ? L.A32 : nullptr;
     // the four-sweep walk reads the corrected x around its strips, so the correction
     // goes to a second buffer and the walk writes x
-    const bool walk4 = pairs && std::is_same<TM, TV>::value && c->cheb_degree == 4 && !Ares;
+    const bool walk4 = B == 2 && pairs && std::is_same<TM, TV>::value && c->cheb_degree == 4 && !Ares;
     TV* xcor = walk4 ? (TV*)L.x2 : x;
     hipLaunchKernelGGL((k_prolong_add<B, TP, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
                        L.nyn, L.ncx, L.ncy, (const TV*)N.x, (const TV*)x, xcor);
     VP_LAUNCH_CHECK();
     if constexpr (B == 2) {
-      if (walk4) smooth_post_pairs<TM, TV>(c, L, A, b, x, nullptr, (const TV*)xcor);
-      else if (pairs) smooth_post_pairs<TM, TV>(c, L, A, b, x, Ares);
+      if (walk4) smooth_post_pairs<B, TM, TV>(c, L, A, b, x, nullptr, (const TV*)xcor);
+      else if (pairs) smooth_post_pairs<B, TM, TV>(c, L, A, b, x, Ares);
       else smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio, 0.0, Ares);
+    } else if constexpr (pairable) {
+      if (pairs) smooth_post_pairs<B, TM, TV>(c, L, A, b, x);
+      else smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
     } else {
       smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
     }

@@ -193,6 +193,7 @@ struct vp_ctx_s {
   hipStream_t stream = nullptr;
   int device = 0;
   int walk4_resident[2][2] = {{0, 0}, {0, 0}};   // workgroups of k_cheb_walk4 resident at once ([FP64][kind])
+  int walk3_resident = 0;                          // workgroups of k_cheb_walk3 resident at once
   vp::ElemConst ec{};
   size_t nn = 0, ncell = 0, ndof = 0;
   int order = 1;                   // velocity elements: 1 = Q1, 2 = Q2

@@ -384,9 +384,9 @@ def test_vcycle_tail_kernel_matches_per_sweep_launches(vp, prec, monkeypatch):
 @pytest.mark.parametrize("degree", [2, 3, 4, 5])
 @pytest.mark.parametrize("prec", [0, 1, 5, 6])
 def test_paired_sweeps_match_single_sweeps(vp, prec, degree, monkeypatch):
-    """The finest-level smoother with its sweeps fused in pairs (two Chebyshev
-    steps per pass, the ring of each tile recomputed) gives bitwise the V-cycle of
-    one launch per sweep (VP_AMG_PAIRS=0), for even and odd step counts."""
+    """The finest-level smoother with its sweeps fused (two Chebyshev steps per
+    pass, or all four of a degree-4 smoothing in one column walk) gives bitwise the
+    V-cycle of one launch per sweep (VP_AMG_PAIRS=0), for even and odd step counts."""
     nx, ny, seed = 200, 150, 8
     outs = []
     for env in ("0", "1"):   # fresh contexts: identical spectral estimates
@@ -406,4 +406,34 @@ def test_paired_sweeps_match_single_sweeps(vp, prec, degree, monkeypatch):
         outs.append(_host(z).ravel())
     print(f"[pairs] prec={prec} degree={degree} max |diff| {np.abs(outs[0] - outs[1]).max():.2e} "
           f"|z| {np.abs(outs[1]).max():.2e}", flush=True)
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("degree", [3, 4])
+@pytest.mark.parametrize("prec", [1, 6])
+def test_coarse_paired_sweeps_match_single_sweeps(vp, prec, degree, monkeypatch):
+    """On a mesh whose first coarse level has over 10^5 nodes (961^2 -> 321^2) the
+    FP32 coarse levels smooth with paired column walks (3 x 3 blocks) too; the
+    V-cycle is bitwise the one of single sweeps on every level."""
+    nx = ny = 960
+    outs = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("VP_AMG_PAIRS", env)
+        w, prob, ctx = _case(vp, nx, ny, 9)
+        v = _rand_v(prob, 3, 0.05)
+        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
+        rng = np.random.default_rng(6)
+        r = rng.standard_normal(2 * prob.mesh.nnode)
+        r[~prob.mesh.free_dof] = 0.0
+        n, a, k = vp.default_opts()
+        a.precision = prec
+        a.cheb_degree = degree
+        ctx.vp_amg_setup(a)
+        levels = ctx.vp_amg_info()
+        assert levels[1][0] * levels[1][1] >= 100000
+        z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+        ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
+        outs.append(_host(z).ravel())
+    print(f"[coarse pairs] prec={prec} degree={degree} max |diff| {np.abs(outs[0] - outs[1]).max():.2e}",
+          flush=True)
     assert np.array_equal(outs[0], outs[1])
