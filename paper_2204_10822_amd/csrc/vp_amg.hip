@@ -369,7 +369,7 @@ __device__ __forceinline__ void node_cheb_step(const TM* __restrict__ A, size_t 
     TA t = TA(0);
 #pragma unroll
     for (int c = 0; c < B; ++c) t += Di[k][c] * rn[c];
-    dk[k] = cdd * dpn[k] + cdr * t;
+    dk[k] = fma(cdd, dpn[k], cdr * t);   // the contraction every sweep kernel writes
     xn[k] += dk[k];
   }
   store_node<B>(dn, n, dk);
@@ -694,7 +694,7 @@ k_cheb_pair(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, 
         TA t = TA(0);
 #pragma unroll
         for (int c = 0; c < B; ++c) t += Di[q][c] * rn[c];
-        dk[q] = c1a * dpn[q] + c1b * t;
+        dk[q] = fma(c1a, dpn[q], c1b * t);
       }
     }
 #pragma unroll
@@ -762,7 +762,7 @@ k_cheb_pair(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, 
         TA t = TA(0);
 #pragma unroll
         for (int c = 0; c < B; ++c) t += Di[q][c] * r2[c];
-        d2[q] = c2a * d1[q] + c2b * t;
+        d2[q] = fma(c2a, d1[q], c2b * t);
         x2[q] = x1[q] + d2[q];
       }
       store_node<B>(dout, n, d2);
@@ -895,7 +895,7 @@ k_cheb_walk(const TV* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __r
         t[q] += Di[q][1] * rn[1];
       }
       if constexpr (MODE == PAIR_RFIRST_STEP) d1c = Vc{t[0] * c1a, t[1] * c1a};
-      else d1c = Vc{c1a * vC.x + c1b * t[0], c1a * vC.y + c1b * t[1]};
+      else d1c = Vc{fma(c1a, vC.x, c1b * t[0]), fma(c1a, vC.y, c1b * t[1])};
       r1c = Vc{rn[0], rn[1]};
     }
     // second sweep at row j = r - 1, inner lanes
@@ -950,7 +950,7 @@ k_cheb_walk(const TV* __restrict__ A, size_t nn, int nxn, int nyn, const TV* __r
           TV t = TV(0);
           t += Di[q][0] * r2[0];
           t += Di[q][1] * r2[1];
-          const TV d2 = c2a * d1v[q] + c2b * t;
+          const TV d2 = fma(c2a, d1v[q], c2b * t);
           dout[2 * n + q] = d2;
           xout[2 * n + q] = x1[q] + d2;
         }
@@ -1079,7 +1079,7 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
         const T r[2] = {rc1.x - y[0], rc1.y - y[1]};
         const Vc t = wsolve(D1, r);
         if constexpr (KIND == W4_PRE) {
-          d1 = Vc{a1 * uC1.x + b1 * t.x, a1 * uC1.y + b1 * t.y};
+          d1 = Vc{fma(a1, uC1.x, b1 * t.x), fma(a1, uC1.y, b1 * t.y)};
           x1 = Vc{uC1.x + d1.x, uC1.y + d1.y};
         } else {
           d1 = Vc{t.x * c0, t.y * c0};
@@ -1102,7 +1102,7 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
         const T r[2] = {rc2.x - y[0], rc2.y - y[1]};
         const Vc t = wsolve(D2, r);
         const T a = KIND == W4_PRE ? a2 : a1, bq = KIND == W4_PRE ? b2 : b1;
-        d2 = Vc{a * uC2.x + bq * t.x, a * uC2.y + bq * t.y};
+        d2 = Vc{fma(a, uC2.x, bq * t.x), fma(a, uC2.y, bq * t.y)};
         x2 = Vc{xc2.x + d2.x, xc2.y + d2.y};
         r2 = Vc{r[0], r[1]};
       }
@@ -1116,7 +1116,7 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
         const T r[2] = {rc3.x - y[0], rc3.y - y[1]};
         const Vc t = wsolve(D3, r);
         const T a = KIND == W4_PRE ? a3 : a2, bq = KIND == W4_PRE ? b3 : b2;
-        d3 = Vc{a * uC3.x + bq * t.x, a * uC3.y + bq * t.y};
+        d3 = Vc{fma(a, uC3.x, bq * t.x), fma(a, uC3.y, bq * t.y)};
         x3 = Vc{xc3.x + d3.x, xc3.y + d3.y};
         r3 = Vc{r[0], r[1]};
       }
@@ -1136,7 +1136,7 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
             xout[2 * n + 1] = xc4.y;
           } else {
             const Vc t = wsolve(D4, r);
-            const T d[2] = {a3 * uC4.x + b3 * t.x, a3 * uC4.y + b3 * t.y};
+            const T d[2] = {fma(a3, uC4.x, b3 * t.x), fma(a3, uC4.y, b3 * t.y)};
             xout[2 * n] = xc4.x + d[0];
             xout[2 * n + 1] = xc4.y + d[1];
           }
@@ -1291,7 +1291,7 @@ k_cheb_walk3(int TR, const float* __restrict__ A, size_t nn, int nxn, int nyn, c
 #pragma unroll
         for (int c = 0; c < 3; ++c) t += Di[k][c] * r1c.v[c];
         if constexpr (MODE == PAIR_RFIRST_STEP) d1c.v[k] = t * c1a;
-        else d1c.v[k] = fmaf(c1a, vC.v[k], c1b * t);
+        else d1c.v[k] = fma(c1a, vC.v[k], c1b * t);
       }
     }
     // second sweep at row j = r - 1, inner lanes
@@ -1349,7 +1349,7 @@ k_cheb_walk3(int TR, const float* __restrict__ A, size_t nn, int nxn, int nyn, c
           float t = 0.0f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) t += Di[k][c] * r2[c];
-          const float d2 = fmaf(c2a, d1p.v[k], c2b * t);
+          const float d2 = fma(c2a, d1p.v[k], c2b * t);
           dout[3 * n + k] = d2;
           xout[3 * n + k] = x1[k] + d2;
         }
@@ -3109,9 +3109,18 @@ float* amg_input32(vp_ctx c, const double** dsc) {
   return c->amg_prec == VP_PREC_FP64 ? nullptr : (float*)c->lev[0].b;
 }
 
+// The FP32 V-cycle output (SA hierarchy in a mixed precision) and its scaling, or
+// null where the V-cycle works in FP64.
+const float* amg_output32(vp_ctx c, const double** dsc) {
+  const bool f32 = c->amg_kind == VP_AMG_SA && c->amg_prec != VP_PREC_FP64;
+  if (dsc) *dsc = f32 && scaled_finest(c) ? c->lev[0].dsc64 : nullptr;
+  return f32 ? (const float*)c->lev[0].x : nullptr;
+}
+
 // z = M^{-1} r followed, in the same pass as the V-cycle's output conversion, by
 // the per-workgroup partials of z.r and (q given) z.q.  Returns the number of
-// workgroups (the partials hold 1 or 2 values each).
+// workgroups (the partials hold 1 or 2 values each).  z may be null for an FP32
+// V-cycle (the caller reads its output through amg_output32).
 int amg_apply_dots(vp_ctx c, const double* r, const double* q, double* z, bool input_ready) {
   if (!c->amg_ready) throw Error(VP_ESTATE, "AMG not set up");
   Level& L = c->lev[0];

@@ -12,6 +12,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale);
 void amg_apply(vp_ctx c, const double* r, double* z);
 int amg_apply_dots(vp_ctx c, const double* r, const double* q, double* z, bool input_ready);
 float* amg_input32(vp_ctx c, const double** dsc);
+const float* amg_output32(vp_ctx c, const double** dsc);
 void amg_reset_estimates(vp_ctx c);
 }  // namespace vp
 
@@ -250,9 +251,15 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
   if (rel > o.rtol) {
     const double* dsc = nullptr;
     float* r32 = amg_input32(c, &dsc);  // the update writes the V-cycle's FP32 input directly
-    int nb = amg_apply_dots(c, r, nullptr, z, false);  // r.z
+    const double* zdsc = nullptr;
+    const float* z32 = amg_output32(c, &zdsc);  // the direction reads the V-cycle's FP32 output directly
+    auto direction = [&](int first) {
+      if (z32) launch_fcg_dir32(s, c->dscal, z32, zdsc, p, n, first);
+      else launch_fcg_dir(s, c->dscal, z, p, n, first);
+    };
+    int nb = amg_apply_dots(c, r, nullptr, z32 ? nullptr : z, false);  // r.z
     finish(c, nb, 1, 0);
-    launch_fcg_dir(s, c->dscal, z, p, n, 1);
+    direction(1);
     while (it < o.maxit) {
       const int pr = prof_begin(c, VP_KID_APPLY_FINE);
       const int nbq = launch_apply_K(c, p, q, c->partials);  // q = K p, p.q
@@ -267,9 +274,9 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
       if (c->hscal[1] <= 0.0) throw Error(VP_EBREAKDOWN, "FCG breakdown: p.Kp <= 0");
       rel = std::sqrt(std::max(c->hscal[4], 0.0)) / bnorm;
       if (rel <= o.rtol) break;
-      nb = amg_apply_dots(c, r, q, z, r32 != nullptr);  // z.r, z.q
+      nb = amg_apply_dots(c, r, q, z32 ? nullptr : z, r32 != nullptr);  // z.r, z.q
       finish(c, nb, 2, 5);
-      launch_fcg_dir(s, c->dscal, z, p, n, 0);
+      direction(0);
     }
   }
   if (info) { info->iters = it; info->rel_resid = rel; }

@@ -286,8 +286,9 @@ int launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, co
 }
 
 // The V-cycle's output to the Krylov solver: z = x (widened, divided by dsc if
-// given; z may alias x), with per-workgroup partials of z.r and, if q is given,
-// z.q (partials[block*K + k], K = 1 or 2).
+// given; z may alias x, or be null when the caller reads x itself), with
+// per-workgroup partials of z.r and, if q is given, z.q (partials[block*K + k],
+// K = 1 or 2).
 template <typename TX>
 __global__ void __launch_bounds__(kBlock)
 k_out_dots(const TX* x, const double* __restrict__ dsc, double* z, const double* __restrict__ r,
@@ -297,7 +298,7 @@ k_out_dots(const TX* x, const double* __restrict__ dsc, double* z, const double*
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     double ze = (double)x[e];
     if (dsc) ze /= dsc[e];
-    if ((const void*)z != (const void*)x) z[e] = ze;
+    if (z && (const void*)z != (const void*)x) z[e] = ze;
     a[0] = fma(ze, r[e], a[0]);
     if (q) a[1] = fma(ze, q[e], a[1]);
   }
@@ -333,6 +334,26 @@ __global__ void k_fcg_dir(double* __restrict__ dev, const double* __restrict__ z
 
 void launch_fcg_dir(hipStream_t s, double* dev, const double* z, double* p, size_t n, int first) {
   hipLaunchKernelGGL(k_fcg_dir, dim3(grid_for(n)), dim3(kBlock), 0, s, dev, z, p, n, first);
+  VP_LAUNCH_CHECK();
+}
+
+// The same update with z read from the FP32 V-cycle output: z = x32 (divided by
+// dsc if given), widened exactly as the output conversion does it, so p is bitwise
+// the one computed from the FP64 copy, without that copy's write and read.
+__global__ void k_fcg_dir32(double* __restrict__ dev, const float* __restrict__ x32, const double* __restrict__ dsc,
+                            double* __restrict__ p, size_t n, int first) {
+  const double beta = (first || dev[1] == 0.0) ? 0.0 : -dev[6] / dev[1];
+  for (size_t e = (size_t)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double ze = (double)x32[e];
+    if (dsc) ze /= dsc[e];
+    p[e] = first ? ze : fma(beta, p[e], ze);
+  }
+  if (!first && blockIdx.x == 0 && threadIdx.x == 0) dev[0] = dev[5];
+}
+
+void launch_fcg_dir32(hipStream_t s, double* dev, const float* x32, const double* dsc, double* p, size_t n,
+                      int first) {
+  hipLaunchKernelGGL(k_fcg_dir32, dim3(grid_for(n)), dim3(kBlock), 0, s, dev, x32, dsc, p, n, first);
   VP_LAUNCH_CHECK();
 }
 

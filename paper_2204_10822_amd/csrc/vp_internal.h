@@ -314,6 +314,8 @@ int launch_fcg_update(hipStream_t s, const double* dev, double* x, double* r, co
                       const double* q, size_t n, double* partials, float* r32 = nullptr,
                       const double* dsc = nullptr);
 void launch_fcg_dir(hipStream_t s, double* dev, const double* z, double* p, size_t n, int first);
+void launch_fcg_dir32(hipStream_t s, double* dev, const float* x32, const double* dsc, double* p, size_t n,
+                      int first);
 void launch_cast(hipStream_t s, const double* x, float* y, size_t n);
 template <typename TX>
 int launch_out_dots(hipStream_t s, const TX* x, const double* dsc, double* z, const double* r, const double* q,
