@@ -1453,6 +1453,201 @@ __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs a) {
   }
 }
 
+// The same V-cycle over the tail levels with FP32 vectors, restructured for
+// latency: every vector of every tail level lives in LDS (read through generic
+// pointers by the shared restriction, prolongation and dense-solve helpers), and
+// each thread keeps its node's nine stencil blocks and its diagonal inverse in
+// registers for the whole smoothing of a level, so a sweep waits only on LDS and the
+// barrier.  Per node the arithmetic is that of the node kernels in the same order
+// (stencil_row_f's neighbour order, the same fused multiply-adds): bitwise the
+// results of k_vcycle_tail.  Chebyshev degree >= 2; the levels' vectors must fit
+// kTailLdsFloats (15 floats per node) and the first tail level kTailLdsThreads nodes
+// (one node per thread; 768 threads leave 170 registers per thread, enough to hold
+// the 81 block entries without spilling, which 1024 threads' 128 are not).
+constexpr int kTailLdsFloats = 18000;
+constexpr int kTailLdsThreads = 768;
+
+__device__ __forceinline__ float* tail_vec(float* sv, const TailArgs& a, int l, int q) {
+  int off = 0;
+  for (int k = 0; k < l; ++k) off += 15 * (int)a.L[k].nn;
+  return sv + off + q * 3 * (int)a.L[l].nn;
+}
+
+template <typename TM>
+__device__ void tail_smooth_reg(const TailLevel& L, float* b, float* x, float* r, float* d0, float* d1, bool pre,
+                                int degree) {
+  const int t = (int)threadIdx.x;
+  const int nn = (int)L.nn, nxn = L.nxn, nyn = L.nyn;
+  const bool own = t < nn;
+  const int i = own ? t % nxn : 0, j = own ? t / nxn : 0;
+  float blk[9][3][3];
+  unsigned valid = 0u;
+  float Di[3][3];
+  if (own) {
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+      valid |= 1u << d;
+      load_block<3>((const TM*)L.A, (size_t)nn, nxn, i, j, d, blk[d]);
+    }
+    invert_block<3>(blk[0], Di);
+  }
+  auto stencil = [&](const float* v, float (&y)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y[k] = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      if (!((valid >> d) & 1u)) continue;
+      const int m = (j + kDJ[d]) * nxn + (i + kDI[d]);
+      float xm[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xm[c] = v[3 * m + c];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) y[k] += blk[d][k][c] * xm[c];
+    }
+  };
+  const float inv_theta = (float)L.inv_theta;
+  float* d[2] = {d0, d1};
+  if (own) {
+    if (pre) {   // d0 = D^-1 b / theta
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float tt = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tt += Di[k][c] * b[3 * t + c];
+        d0[3 * t + k] = tt * inv_theta;
+      }
+    } else {     // r = b - A x, d0 = D^-1 r / theta
+      float y[3], rn[3];
+      stencil(x, y);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rn[k] = b[3 * t + k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rn[k] -= y[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r[3 * t + k] = rn[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float tt = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tt += Di[k][c] * rn[c];
+        d0[3 * t + k] = tt * inv_theta;
+      }
+    }
+  }
+  __syncthreads();
+  for (int s = 1; s < degree; ++s) {
+    const int xmode = s > 1 ? 0 : pre ? 2 : 1;
+    const float* dp = d[(s - 1) & 1];
+    float* dn = d[s & 1];
+    const float* rin = (pre && s == 1) ? b : r;
+    if (own) {
+      float y[3], rn[3], dpn[3], xn[3], dk[3];
+      stencil(dp, y);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        rn[k] = rin[3 * t + k];
+        dpn[k] = dp[3 * t + k];
+      }
+      if (xmode == 2) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xn[k] = dpn[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xn[k] = x[3 * t + k];
+        if (xmode == 1) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) xn[k] += dpn[k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rn[k] -= y[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r[3 * t + k] = rn[k];
+      const float cdd = (float)L.cdd[s], cdr = (float)L.cdr[s];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float tt = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tt += Di[k][c] * rn[c];
+        dk[k] = fma(cdd, dpn[k], cdr * tt);
+        xn[k] += dk[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        dn[3 * t + k] = dk[k];
+        x[3 * t + k] = xn[k];
+      }
+    }
+    __syncthreads();
+  }
+  if (pre) {   // r = r - A d: the residual after the last step
+    if (own) {
+      float y[3], bb[3];
+      stencil(d[(degree - 1) & 1], y);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) bb[k] = r[3 * t + k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) bb[k] = bb[k] - y[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r[3 * t + k] = bb[k];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename TM, typename TP>
+__global__ void __launch_bounds__(kTailLdsThreads) k_vcycle_tail_lds(TailArgs a) {
+  __shared__ float sv[kTailLdsFloats];
+  const int t0 = (int)threadIdx.x, nt = (int)blockDim.x;
+  {
+    const float* b0 = (const float*)a.L[0].b;
+    float* vb = tail_vec(sv, a, 0, 0);
+    for (int e = t0; e < 3 * (int)a.L[0].nn; e += nt) vb[e] = b0[e];
+  }
+  __syncthreads();
+  for (int l = 0; l + 1 < a.nlev; ++l) {
+    const TailLevel& L = a.L[l];
+    const TailLevel& N = a.L[l + 1];
+    tail_smooth_reg<TM>(L, tail_vec(sv, a, l, 0), tail_vec(sv, a, l, 1), tail_vec(sv, a, l, 2),
+                        tail_vec(sv, a, l, 3), tail_vec(sv, a, l, 4), true, a.degree);
+    const float* rl = tail_vec(sv, a, l, 2);
+    float* bn = tail_vec(sv, a, l + 1, 0);
+    const size_t ng = (size_t)N.nn * kRestrictLanes;
+    for (size_t g = t0; g < ng; g += nt)
+      group_restrict<3>((const TP*)L.P, (size_t)L.nn, L.nxn, L.nyn, L.ncx, L.ncy, rl, bn, g / kRestrictLanes,
+                        (int)(g % kRestrictLanes));
+    __syncthreads();
+  }
+  {
+    const int lc = a.nlev - 1;
+    const float* bc = tail_vec(sv, a, lc, 0);
+    float* xc = tail_vec(sv, a, lc, 1);
+    for (int rw = t0; rw < a.nd; rw += nt) row_dense_apply((const float*)a.Ainv, a.nd, bc, xc, rw);
+  }
+  __syncthreads();
+  for (int l = a.nlev - 2; l >= 0; --l) {
+    const TailLevel& L = a.L[l];
+    const TailLevel& N = a.L[l + 1];
+    float* xl = tail_vec(sv, a, l, 1);
+    const float* xn = tail_vec(sv, a, l + 1, 1);
+    for (int n = t0; n < (int)L.nn; n += nt)
+      node_prolong_add<3>((const TP*)L.P, (size_t)L.nn, L.nxn, L.nyn, L.ncx, L.ncy, xn, (const float*)xl, xl,
+                          (size_t)n);
+    __syncthreads();
+    tail_smooth_reg<TM>(L, tail_vec(sv, a, l, 0), xl, tail_vec(sv, a, l, 2), tail_vec(sv, a, l, 3),
+                        tail_vec(sv, a, l, 4), false, a.degree);
+  }
+  {
+    float* x0 = (float*)a.L[0].x;
+    const float* vx = tail_vec(sv, a, 0, 1);
+    for (int e = t0; e < 3 * (int)a.L[0].nn; e += nt) x0[e] = vx[e];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // setup kernels
 // ---------------------------------------------------------------------------
@@ -2712,7 +2907,17 @@ void launch_tail(vp_ctx c, int l0) {
   a.nd = C.B * (int)C.nn;
   a.Ainv = fp64 ? (const void*)C.Ainv64 : (const void*)C.Ainv32;
   hipStream_t s = c->stream;
-  if (fp64)
+  int lds_floats = 0;
+  for (int k = 0; k < a.nlev; ++k) lds_floats += 15 * (int)a.L[k].nn;
+  const bool lds = !fp64 && a.degree >= 2 && lds_floats <= kTailLdsFloats && a.L[0].nn <= (unsigned)kTailLdsThreads;
+  if (lds) {
+    if (prec == VP_PREC_FP32 || prec == VP_PREC_FP16_FP32COARSE)
+      hipLaunchKernelGGL((k_vcycle_tail_lds<float, float>), dim3(1), dim3(kTailLdsThreads), 0, s, a);
+    else if (prec == VP_PREC_FP16)
+      hipLaunchKernelGGL((k_vcycle_tail_lds<_Float16, float>), dim3(1), dim3(kTailLdsThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_vcycle_tail_lds<__hip_bfloat16, float>), dim3(1), dim3(kTailLdsThreads), 0, s, a);
+  } else if (fp64)
     hipLaunchKernelGGL((k_vcycle_tail<double, double, double>), dim3(1), dim3(kTailThreads), 0, s, a);
   else if (prec == VP_PREC_FP32 || prec == VP_PREC_FP16_FP32COARSE)
     hipLaunchKernelGGL((k_vcycle_tail<float, float, float>), dim3(1), dim3(kTailThreads), 0, s, a);
