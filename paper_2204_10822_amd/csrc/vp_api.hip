@@ -60,6 +60,13 @@ void finish(vp_ctx c, int nblocks, int K, int off) {
   launch_finish_sum(c->stream, c->partials, nblocks, K, c->dscal + off);
 }
 
+// finish into dscal[off..off+K) and hand dscal[0..mn) to the host (pinned scalars
+// written by the finishing kernel itself), then wait for the stream
+void finish_fetch(vp_ctx c, int nblocks, int K, int off, int mn) {
+  launch_finish_sum(c->stream, c->partials, nblocks, K, c->dscal + off, c->dscal, c->hscal, mn);
+  VP_HIP(hipStreamSynchronize(c->stream));
+}
+
 void fetch(vp_ctx c, int off, int K) {
   VP_HIP(hipMemcpyAsync(c->hscal + off, c->dscal + off, K * sizeof(double), hipMemcpyDeviceToHost,
                         c->stream));
@@ -266,8 +273,7 @@ int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov
       prof_end(c, pr);
       finish(c, nbq, 1, 1);
       nb = launch_fcg_update(s, c->dscal, x, r, p, q, n, c->partials, r32, dsc);
-      finish(c, nb, 1, 4);
-      fetch(c, 0, 5);
+      finish_fetch(c, nb, 1, 4, 5);
       ++it;
       if (!std::isfinite(c->hscal[4]) || !std::isfinite(c->hscal[1]))
         throw Error(VP_ENONFINITE, "non-finite Krylov scalar");

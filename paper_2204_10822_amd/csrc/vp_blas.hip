@@ -8,8 +8,10 @@ namespace vp {
 constexpr int kMaxNV = kMaxRestart + 1;
 
 // out[k] = sum_b partials[b*K + k], fixed order
-__global__ void k_finish_sum(const double* __restrict__ partials, int nblocks, int K,
-                             double* __restrict__ out) {
+// mdst (optional, pinned host memory): copy of msrc[0..mn) once the sums are done,
+// read by the host after the stream synchronises (no separate copy).
+__global__ void k_finish_sum(const double* __restrict__ partials, int nblocks, int K, double* out,
+                             const double* msrc, double* mdst, int mn) {
   __shared__ double lds[1024];
   for (int k = 0; k < K; ++k) {
     double s = 0.0;
@@ -23,10 +25,13 @@ __global__ void k_finish_sum(const double* __restrict__ partials, int nblocks, i
     if (threadIdx.x == 0) out[k] = lds[0];
     __syncthreads();
   }
+  if (mdst && threadIdx.x == 0)
+    for (int m = 0; m < mn; ++m) mdst[m] = msrc[m];
 }
 
-void launch_finish_sum(hipStream_t s, const double* partials, int nblocks, int K, double* out) {
-  hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(512), 0, s, partials, nblocks, K, out);
+void launch_finish_sum(hipStream_t s, const double* partials, int nblocks, int K, double* out, const double* msrc,
+                       double* mdst, int mn) {
+  hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(512), 0, s, partials, nblocks, K, out, msrc, mdst, mn);
   VP_LAUNCH_CHECK();
 }
 

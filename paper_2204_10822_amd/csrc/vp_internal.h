@@ -297,7 +297,8 @@ void launch_q2_pi_init(vp_ctx c, const double* v, double* pi);
 int launch_apply_K(vp_ctx c, const double* x, double* y, double* partials);
 
 // reductions / BLAS-1 (vector length n doubles)
-void launch_finish_sum(hipStream_t s, const double* partials, int nblocks, int K, double* out);
+void launch_finish_sum(hipStream_t s, const double* partials, int nblocks, int K, double* out,
+                       const double* msrc = nullptr, double* mdst = nullptr, int mn = 0);
 void launch_dot(hipStream_t s, const double* x, const double* y, size_t n, double* partials);
 void launch_mdot(hipStream_t s, const double* V, size_t ld, int nv, const double* w, size_t n,
                  double* partials);
