@@ -2778,6 +2778,8 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   {
     const char* env = std::getenv("VP_AMG_PAIRS");   // VP_AMG_PAIRS=0: one launch per sweep
     c->pair_sweeps = !(env && env[0] == '0');
+    const char* tenv = std::getenv("VP_AMG_TAIL_LDS");   // VP_AMG_TAIL_LDS=0: the tail without LDS vectors
+    c->tail_lds = !(tenv && tenv[0] == '0');
     const char* ph = std::getenv("VP_AMG_P16");      // VP_AMG_P16=0: FP32 finest transfers in the FP16 modes
     c->ph_transfers = !(ph && ph[0] == '0') && c->lev[0].Ph != nullptr &&
                       (precision == VP_PREC_FP16_BF16COARSE || precision == VP_PREC_FP16 ||
@@ -2909,7 +2911,8 @@ void launch_tail(vp_ctx c, int l0) {
   hipStream_t s = c->stream;
   int lds_floats = 0;
   for (int k = 0; k < a.nlev; ++k) lds_floats += 15 * (int)a.L[k].nn;
-  const bool lds = !fp64 && a.degree >= 2 && lds_floats <= kTailLdsFloats && a.L[0].nn <= (unsigned)kTailLdsThreads;
+  const bool lds = c->tail_lds && !fp64 && a.degree >= 2 && lds_floats <= kTailLdsFloats &&
+                   a.L[0].nn <= (unsigned)kTailLdsThreads;
   if (lds) {
     if (prec == VP_PREC_FP32 || prec == VP_PREC_FP16_FP32COARSE)
       hipLaunchKernelGGL((k_vcycle_tail_lds<float, float>), dim3(1), dim3(kTailLdsThreads), 0, s, a);

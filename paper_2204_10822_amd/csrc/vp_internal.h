@@ -226,6 +226,7 @@ struct vp_ctx_s {
   int cheb_degree = 3;
   int tail_level = -1;             // first level run by the single-workgroup tail kernel
   bool pair_sweeps = true;         // finest-level smoother sweeps fused in pairs
+  bool tail_lds = true;            // FP32-vector tail with LDS vectors and register blocks
   double cheb_ratio = 30.0;
   int max_coarse = 140;
   int power_its_cold = 16, power_its_warm = 6;

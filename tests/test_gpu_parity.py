@@ -409,6 +409,33 @@ def test_paired_sweeps_match_single_sweeps(vp, prec, degree, monkeypatch):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("degree", [2, 4])
+@pytest.mark.parametrize("prec", [1, 2, 4, 6])
+def test_lds_tail_matches_tail(vp, prec, degree, monkeypatch):
+    """The one-workgroup tail with FP32 vectors in LDS and each node's stencil blocks
+    in registers gives bitwise the V-cycle of the tail that reloads everything from
+    global memory every sweep (VP_AMG_TAIL_LDS=0)."""
+    nx, ny, seed = 200, 150, 8
+    outs = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("VP_AMG_TAIL_LDS", env)
+        w, prob, ctx = _case(vp, nx, ny, seed)
+        v = _rand_v(prob, 3, 0.05)
+        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
+        rng = np.random.default_rng(7)
+        r = rng.standard_normal(2 * prob.mesh.nnode)
+        r[~prob.mesh.free_dof] = 0.0
+        n, a, k = vp.default_opts()
+        a.precision = prec
+        a.cheb_degree = degree
+        ctx.vp_amg_setup(a)
+        z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+        ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
+        outs.append(_host(z).ravel())
+    print(f"[lds tail] prec={prec} degree={degree} max |diff| {np.abs(outs[0] - outs[1]).max():.2e}", flush=True)
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("degree", [3, 4])
 @pytest.mark.parametrize("prec", [1, 6])
 def test_coarse_paired_sweeps_match_single_sweeps(vp, prec, degree, monkeypatch):
