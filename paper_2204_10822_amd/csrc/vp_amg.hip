@@ -650,16 +650,14 @@ k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, in
 enum { PAIR_STEP_STEP = 0, PAIR_STEP_RESID = 1, PAIR_RFIRST_STEP = 2 };
 constexpr int kPairTX = 64, kPairTY = 16, kPairThreads = 256;   // defaults; launch_pair picks per type
 
-template <int MODE, int XM, typename TM, typename TV, int TX = kPairTX, int TY = kPairTY, int NT = kPairThreads,
-          int WMAX = 8>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, WMAX)))
-k_cheb_pair(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, int tiles,
-            const TV* __restrict__ vin, const TV* __restrict__ rin, const TV* xin, TV* __restrict__ rout,
-            TV* __restrict__ dout, TV* xout, typename Acc<TV>::type c1a, typename Acc<TV>::type c1b,
-            typename Acc<TV>::type c2a, typename Acc<TV>::type c2b) {
+template <int MODE, int XM, typename TM, typename TV, int TX, int TY, int NT, int B>
+__device__ __forceinline__ void cheb_pair_body(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x,
+                                               int tiles, const TV* __restrict__ vin, const TV* __restrict__ rin,
+                                               const TV* xin, TV* __restrict__ rout, TV* __restrict__ dout,
+                                               TV* xout, typename Acc<TV>::type c1a, typename Acc<TV>::type c1b,
+                                               typename Acc<TV>::type c2a, typename Acc<TV>::type c2b) {
   constexpr int xmode1 = XM;   // xmode of the first sweep's Chebyshev step (STEP modes)
   using TA = typename Acc<TV>::type;
-  constexpr int B = 2;
   __shared__ TV s_d[(TX + 2) * (TY + 2)][B];   // first sweep's direction on the ringed tile
   __shared__ TV s_r[(TX + 2) * (TY + 2)][B];   // first sweep's residual
   const int tb = (int)xcd_block();
@@ -769,6 +767,32 @@ k_cheb_pair(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, 
       store_node<B>(xout, n, x2);
     }
   }
+}
+
+template <int MODE, int XM, typename TM, typename TV, int TX = kPairTX, int TY = kPairTY, int NT = kPairThreads,
+          int WMAX = 8>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, WMAX)))
+k_cheb_pair(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, int tiles,
+            const TV* __restrict__ vin, const TV* __restrict__ rin, const TV* xin, TV* __restrict__ rout,
+            TV* __restrict__ dout, TV* xout, typename Acc<TV>::type c1a, typename Acc<TV>::type c1b,
+            typename Acc<TV>::type c2a, typename Acc<TV>::type c2b) {
+  cheb_pair_body<MODE, XM, TM, TV, TX, TY, NT, 2>(A, nn, nxn, nyn, tiles_x, tiles, vin, rin, xin, rout, dout, xout,
+                                                  c1a, c1b, c2a, c2b);
+}
+
+// The same paired sweeps on a small structured coarse level (3 x 3 blocks, any
+// storage): 14 x 14 tiles, the ringed tile one node per thread of 256.  On levels of
+// a few ten thousand nodes or fewer each launch is mostly latency, and one launch
+// for two sweeps replaces two.
+constexpr int kPair3Tile = 14;
+template <int MODE, int XM, typename TM, typename TV>
+__global__ void __launch_bounds__(256)
+k_cheb_pair3(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, int tiles,
+             const TV* __restrict__ vin, const TV* __restrict__ rin, const TV* xin, TV* __restrict__ rout,
+             TV* __restrict__ dout, TV* xout, typename Acc<TV>::type c1a, typename Acc<TV>::type c1b,
+             typename Acc<TV>::type c2a, typename Acc<TV>::type c2b) {
+  cheb_pair_body<MODE, XM, TM, TV, kPair3Tile, kPair3Tile, 256, 3>(A, nn, nxn, nyn, tiles_x, tiles, vin, rin, xin,
+                                                                   rout, dout, xout, c1a, c1b, c2a, c2b);
 }
 
 // The same two sweeps by column walks, for operators stored in the vector type
@@ -2998,11 +3022,22 @@ void launch_walk3(vp_ctx c, const Level& L, const float* A, const float* vin, co
 template <int B, int MODE, int XM, typename TM, typename TV>
 void launch_pairb(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV* rin, const TV* xin, TV* rout,
                   TV* dout, TV* xout, double c1a, double c1b, double c2a, double c2b) {
+  using TA = typename Acc<TV>::type;
   if constexpr (B == 2) {
     launch_pair<MODE, XM>(c, L, A, vin, rin, xin, rout, dout, xout, c1a, c1b, c2a, c2b);
   } else {
-    static_assert(std::is_same<TM, float>::value && std::is_same<TV, float>::value, "coarse pairs are FP32");
-    launch_walk3<MODE, XM>(c, L, A, vin, rin, xin, rout, dout, xout, c1a, c1b, c2a, c2b);
+    if constexpr (std::is_same<TM, float>::value && std::is_same<TV, float>::value) {
+      if (L.nn >= kCoarsePairNodes) {
+        launch_walk3<MODE, XM>(c, L, A, vin, rin, xin, rout, dout, xout, c1a, c1b, c2a, c2b);
+        return;
+      }
+    }
+    const int tx = (L.nxn + kPair3Tile - 1) / kPair3Tile, ty = (L.nyn + kPair3Tile - 1) / kPair3Tile;
+    const int tiles = tx * ty;
+    const unsigned g = (unsigned)((tiles + 7) / 8 * 8);   // xcd_block() needs a multiple of 8
+    hipLaunchKernelGGL((k_cheb_pair3<MODE, XM, TM, TV>), dim3(g), dim3(256), 0, c->stream, A, L.nn, L.nxn, L.nyn, tx,
+                       tiles, vin, rin, xin, rout, dout, xout, (TA)c1a, (TA)c1b, (TA)c2a, (TA)c2b);
+    VP_LAUNCH_CHECK();
   }
 }
 
@@ -3208,13 +3243,12 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     using TP = decltype(tp_tag);
     const TM* A = (const TM*)Av;
     const TP* P = (const TP*)Pv;
-    // paired sweeps: the finest level, and the large structured coarse levels in FP32
-    // (on levels of a few ten thousand nodes a walk's strips are a few rows long and
-    // load latency makes a pair slower than two single sweeps: 15 us against 10 us at
-    // 227^2 nodes, 36 us against 50 us at 683^2)
-    constexpr bool pairable = B == 2 || (std::is_same<TM, float>::value && std::is_same<TV, float>::value);
-    const bool pairs = pairable && (B == 2 ? l == 0 : (l > 0 && L.nn >= kCoarsePairNodes)) && c->pair_sweeps &&
-                       c->cheb_degree >= 2 && c->cheb_degree <= 32;
+    // paired sweeps on every level above the tail: column walks on the finest level and
+    // on large FP32 coarse levels, tiles elsewhere (on levels of a few ten thousand
+    // nodes a walk's strips are a few rows long and load latency makes it slower than
+    // two single sweeps: 15 us against 10 us at 227^2 nodes, 36 us against 50 us at 683^2)
+    constexpr bool pairable = true;
+    const bool pairs = (B == 2 ? l == 0 : l > 0) && c->pair_sweeps && c->cheb_degree >= 2 && c->cheb_degree <= 32;
     const TV* rres = (const TV*)L.r;
     if constexpr (pairable) {
       if (pairs) rres = smooth_pre_pairs<B, TM, TV>(c, L, A, b, x);
