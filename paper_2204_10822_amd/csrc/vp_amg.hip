@@ -2355,10 +2355,23 @@ __global__ void k_dense_apply(const TM* __restrict__ M, int nd, const TV* __rest
   if (r < nd) row_dense_apply(M, nd, b, x, r);
 }
 
+// d = (TD)s, four entries per step with one aligned vector load and store each (the
+// buffers are allocation bases, so 4-entry groups are aligned), the last n % 4 singly
+template <typename T>
+struct alignas(4 * sizeof(T)) Vec4 {
+  T v[4];
+};
 template <typename TS, typename TD>
 __global__ void k_convert(const TS* __restrict__ s, TD* __restrict__ d, size_t n) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-    d[e] = (TD)s[e];
+  const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += stride) {
+    const Vec4<TS> a = reinterpret_cast<const Vec4<TS>*>(s)[e];
+    Vec4<TD> b;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b.v[k] = (TD)a.v[k];
+    reinterpret_cast<Vec4<TD>*>(d)[e] = b;
+  }
+  for (size_t e = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) d[e] = (TD)s[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -2389,7 +2402,9 @@ void free_vectors(Level& L) {
 
 template <typename TS, typename TD>
 void convert(hipStream_t s, const TS* src, TD* dst, size_t n) {
-  hipLaunchKernelGGL((k_convert<TS, TD>), dim3(std::min<size_t>((n + 255) / 256, 4096) + 1), dim3(256), 0, s,
+  if ((reinterpret_cast<uintptr_t>(src) % (4 * sizeof(TS))) || (reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(TD))))
+    throw Error(VP_EINVAL, "convert: buffers not aligned to 4 entries");
+  hipLaunchKernelGGL((k_convert<TS, TD>), dim3(std::min<size_t>((n / 4 + 255) / 256, 4096) + 1), dim3(256), 0, s,
                      src, dst, n);
   VP_LAUNCH_CHECK();
 }
