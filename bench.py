@@ -177,8 +177,9 @@ def main():
                     help="kernels: a short fixed sequence (for profiler counter passes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the domain-decomposition design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(a single-GPU implementation; the mesh would shard by row strips with halo exchange).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
