@@ -423,13 +423,13 @@ __device__ __forceinline__ void group_restrict(const TP* __restrict__ P, size_t 
 
 // x += P xc at fine node n
 template <int B, typename TP, typename TV>
-__device__ __forceinline__ void node_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx,
-                                                 int ncy, const TV* __restrict__ xc, const TV* xi, TV* x, size_t n) {
+__device__ __forceinline__ void prolong_value(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx,
+                                              int ncy, const TV* __restrict__ xc, const TV* xi, size_t n,
+                                              typename Acc<TV>::type (&acc)[B]) {
   using TA = typename Acc<TV>::type;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   const int ax[2] = {agg_of(i, ncx), agg_other(i, nxn, ncx)};
   const int ay[2] = {agg_of(j, ncy), agg_other(j, nyn, ncy)};
-  TA acc[B];
 #pragma unroll
   for (int rr = 0; rr < B; ++rr) acc[rr] = (TA)xi[n * B + rr];
 #pragma unroll
@@ -445,6 +445,14 @@ __device__ __forceinline__ void node_prolong_add(const TP* __restrict__ P, size_
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[rr] += (TA)ld(P + pidx(B, nn, s, n, rr, c)) * xj[c];
   }
+}
+
+// x = xi + P xc at fine node n
+template <int B, typename TP, typename TV>
+__device__ __forceinline__ void node_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx,
+                                                 int ncy, const TV* __restrict__ xc, const TV* xi, TV* x, size_t n) {
+  typename Acc<TV>::type acc[B];
+  prolong_value<B>(P, nn, nxn, nyn, ncx, ncy, xc, xi, n, acc);
 #pragma unroll
   for (int rr = 0; rr < B; ++rr) x[n * B + rr] = (TV)acc[rr];
 }
@@ -648,6 +656,18 @@ k_prolong_add(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, in
 // rin and rout, and vin and dout, must not alias (ring nodes of one tile are
 // interior nodes of another).
 enum { PAIR_STEP_STEP = 0, PAIR_STEP_RESID = 1, PAIR_RFIRST_STEP = 2 };
+// On the tiled coarse-level pairs two more passes come first, formed on the tile and
+// two rings in LDS: PAIR_FIRST_STEP starts a pre-smoothing from x = 0 (the first
+// step d0 = D^-1 b / theta, then the sweeps of PAIR_STEP_STEP with xmode 2), and
+// PAIR_PROLONG_RFIRST starts a post-smoothing from the coarse-grid correction
+// (x + P xc, then the sweeps of PAIR_RFIRST_STEP).
+enum { PAIR_FIRST_STEP = 3, PAIR_PROLONG_RFIRST = 4 };
+struct PairExtra {
+  const void* P;      // prolongator (PAIR_PROLONG_RFIRST; stored in the vector type on coarse levels)
+  const void* xc;     // coarse correction (TV)
+  int ncx, ncy;
+  double c0;          // 1/theta (PAIR_FIRST_STEP)
+};
 constexpr int kPairTX = 64, kPairTY = 16, kPairThreads = 256;   // defaults; launch_pair picks per type
 
 template <int MODE, int XM, typename TM, typename TV, int TX, int TY, int NT, int B>
@@ -655,14 +675,60 @@ __device__ __forceinline__ void cheb_pair_body(const TM* __restrict__ A, size_t 
                                                int tiles, const TV* __restrict__ vin, const TV* __restrict__ rin,
                                                const TV* xin, TV* __restrict__ rout, TV* __restrict__ dout,
                                                TV* xout, typename Acc<TV>::type c1a, typename Acc<TV>::type c1b,
-                                               typename Acc<TV>::type c2a, typename Acc<TV>::type c2b) {
-  constexpr int xmode1 = XM;   // xmode of the first sweep's Chebyshev step (STEP modes)
+                                               typename Acc<TV>::type c2a, typename Acc<TV>::type c2b,
+                                               const PairExtra& ex) {
   using TA = typename Acc<TV>::type;
+  constexpr bool pre0 = MODE == PAIR_FIRST_STEP || MODE == PAIR_PROLONG_RFIRST;   // input formed in LDS
+  constexpr bool rfirst = MODE == PAIR_RFIRST_STEP || MODE == PAIR_PROLONG_RFIRST;
+  constexpr int xmode1 = MODE == PAIR_FIRST_STEP ? 2 : XM;   // xmode of the first sweep's step (STEP modes)
+  constexpr int W2 = TX + 4;                                   // row length of the twice-ringed tile
   __shared__ TV s_d[(TX + 2) * (TY + 2)][B];   // first sweep's direction on the ringed tile
   __shared__ TV s_r[(TX + 2) * (TY + 2)][B];   // first sweep's residual
+  __shared__ TV s_v[pre0 ? (TX + 4) * (TY + 4) : 1][B];   // the first sweep's input on the twice-ringed tile
   const int tb = (int)xcd_block();
   if (tb >= tiles) return;                   // whole workgroup
   const int i0 = (tb % tiles_x) * TX, j0 = (tb / tiles_x) * TY;
+  if constexpr (pre0) {
+#pragma unroll 1
+    for (int k = threadIdx.x; k < (TX + 4) * (TY + 4); k += NT) {
+      const int i = i0 - 2 + k % W2, j = j0 - 2 + k / W2;
+      if (i < 0 || j < 0 || i >= nxn || j >= nyn) continue;
+      const size_t n = (size_t)j * nxn + i;
+      TA v[B];
+      if constexpr (MODE == PAIR_FIRST_STEP) {   // d0 = D^-1 b / theta (node_cheb_first)
+        TA raw[B * B], D[B][B], Di[B][B], sv[B];
+        load_raw<B>(A + aidx(B, nn, 0, n, 0, 0), raw);
+#pragma unroll
+        for (int rr = 0; rr < B; ++rr)
+#pragma unroll
+          for (int c = 0; c < B; ++c) D[rr][c] = raw[rr * B + c];
+        invert_block<B>(D, Di);
+        load_node<B>(rin, n, sv);
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          TA t = TA(0);
+#pragma unroll
+          for (int c = 0; c < B; ++c) t += Di[q][c] * sv[c];
+          v[q] = t * (TA)ex.c0;
+        }
+      } else {                                   // x + P xc (node_prolong_add)
+        prolong_value<B>((const TV*)ex.P, nn, nxn, nyn, ex.ncx, ex.ncy, (const TV*)ex.xc, xin, n, v);
+      }
+#pragma unroll
+      for (int q = 0; q < B; ++q) s_v[k][q] = (TV)v[q];
+    }
+    __syncthreads();
+  }
+  // the first sweep's input and the node's own value of it
+  auto vget = [&](size_t m, int ii, int jj, TA (&xm)[B]) {
+    if constexpr (pre0) {
+      const int l = (jj - j0 + 2) * W2 + (ii - i0 + 2);
+#pragma unroll
+      for (int q = 0; q < B; ++q) xm[q] = (TA)s_v[l][q];
+    } else {
+      load_node<B>(vin, m, xm);
+    }
+  };
   // first sweep on the tile and its ring (loops kept rolled: the unrolled body
   // would not fit the instruction cache)
 #pragma unroll 1
@@ -671,12 +737,12 @@ __device__ __forceinline__ void cheb_pair_body(const TM* __restrict__ A, size_t 
     if (i < 0 || j < 0 || i >= nxn || j >= nyn) continue;
     const size_t n = (size_t)j * nxn + i;
     TA y[B], D[B][B], Di[B][B], rn[B], dk[B];
-    stencil_row<B>(A, nn, nxn, nyn, i, j, vin, y, D);
+    stencil_row_f<B>(A, nn, nxn, nyn, i, j, vget, y, D);
     invert_block<B>(D, Di);
     load_node<B>(rin, n, rn);
 #pragma unroll
     for (int q = 0; q < B; ++q) rn[q] -= y[q];
-    if constexpr (MODE == PAIR_RFIRST_STEP) {
+    if constexpr (rfirst) {
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         TA t = TA(0);
@@ -686,7 +752,7 @@ __device__ __forceinline__ void cheb_pair_body(const TM* __restrict__ A, size_t 
       }
     } else {
       TA dpn[B];
-      load_node<B>(vin, n, dpn);
+      vget(n, i, j, dpn);
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         TA t = TA(0);
@@ -717,11 +783,12 @@ __device__ __forceinline__ void cheb_pair_body(const TM* __restrict__ A, size_t 
       r1[q] = (TA)s_r[lk][q];
     }
     // iterate after the first sweep (as the single-sweep kernels store it)
-    if constexpr (MODE == PAIR_RFIRST_STEP) {
-      load_node<B>(xin, n, x1);                        // the first sweep leaves x unchanged
+    if constexpr (rfirst) {
+      if constexpr (pre0) vget(n, i, j, x1);           // the corrected x
+      else load_node<B>(xin, n, x1);                   // the first sweep leaves x unchanged
     } else {
       TA dpn[B];
-      load_node<B>(vin, n, dpn);
+      vget(n, i, j, dpn);
       if constexpr (xmode1 == 2) {
 #pragma unroll
         for (int q = 0; q < B; ++q) x1[q] = dpn[q];
@@ -751,7 +818,7 @@ __device__ __forceinline__ void cheb_pair_body(const TM* __restrict__ A, size_t 
     } else {
       TA Di[B][B], d2[B], x2[B];
       invert_block<B>(D, Di);
-      if constexpr (MODE == PAIR_RFIRST_STEP) {
+      if constexpr (rfirst) {
 #pragma unroll
         for (int q = 0; q < B; ++q) x1[q] += d1[q];     // step 1 in xmode 1: (x + d0) + d1
       }
@@ -777,7 +844,7 @@ k_cheb_pair(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, 
             TV* __restrict__ dout, TV* xout, typename Acc<TV>::type c1a, typename Acc<TV>::type c1b,
             typename Acc<TV>::type c2a, typename Acc<TV>::type c2b) {
   cheb_pair_body<MODE, XM, TM, TV, TX, TY, NT, 2>(A, nn, nxn, nyn, tiles_x, tiles, vin, rin, xin, rout, dout, xout,
-                                                  c1a, c1b, c2a, c2b);
+                                                  c1a, c1b, c2a, c2b, PairExtra{});
 }
 
 // The same paired sweeps on a small structured coarse level (3 x 3 blocks, any
@@ -790,9 +857,9 @@ __global__ void __launch_bounds__(256)
 k_cheb_pair3(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int tiles_x, int tiles,
              const TV* __restrict__ vin, const TV* __restrict__ rin, const TV* xin, TV* __restrict__ rout,
              TV* __restrict__ dout, TV* xout, typename Acc<TV>::type c1a, typename Acc<TV>::type c1b,
-             typename Acc<TV>::type c2a, typename Acc<TV>::type c2b) {
+             typename Acc<TV>::type c2a, typename Acc<TV>::type c2b, PairExtra ex) {
   cheb_pair_body<MODE, XM, TM, TV, kPair3Tile, kPair3Tile, 256, 3>(A, nn, nxn, nyn, tiles_x, tiles, vin, rin, xin,
-                                                                   rout, dout, xout, c1a, c1b, c2a, c2b);
+                                                                   rout, dout, xout, c1a, c1b, c2a, c2b, ex);
 }
 
 // The same two sweeps by column walks, for operators stored in the vector type
@@ -3012,6 +3079,12 @@ void launch_pair(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV*
 // height is the smallest with every workgroup resident at once.  Used on levels of
 // at least kCoarsePairNodes nodes.
 constexpr size_t kCoarsePairNodes = 100000;
+// whether a 3 x 3-block level's pairs run as tiles (k_cheb_pair3), which also take the
+// first step of a pre-smoothing and the prolongation before a post-smoothing
+template <typename TM, typename TV>
+bool coarse_tiles(const Level& L) {
+  return !(std::is_same<TM, float>::value && std::is_same<TV, float>::value && L.nn >= kCoarsePairNodes);
+}
 template <int MODE, int XM>
 void launch_walk3(vp_ctx c, const Level& L, const float* A, const float* vin, const float* rin, const float* xin,
                   float* rout, float* dout, float* xout, double c1a, double c1b, double c2a, double c2b) {
@@ -3036,7 +3109,8 @@ void launch_walk3(vp_ctx c, const Level& L, const float* A, const float* vin, co
 // structured coarse level (B = 3, FP32 operator and vectors only).
 template <int B, int MODE, int XM, typename TM, typename TV>
 void launch_pairb(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV* rin, const TV* xin, TV* rout,
-                  TV* dout, TV* xout, double c1a, double c1b, double c2a, double c2b) {
+                  TV* dout, TV* xout, double c1a, double c1b, double c2a, double c2b,
+                  const PairExtra& ex = PairExtra{}) {
   using TA = typename Acc<TV>::type;
   if constexpr (B == 2) {
     launch_pair<MODE, XM>(c, L, A, vin, rin, xin, rout, dout, xout, c1a, c1b, c2a, c2b);
@@ -3051,7 +3125,7 @@ void launch_pairb(vp_ctx c, const Level& L, const TM* A, const TV* vin, const TV
     const int tiles = tx * ty;
     const unsigned g = (unsigned)((tiles + 7) / 8 * 8);   // xcd_block() needs a multiple of 8
     hipLaunchKernelGGL((k_cheb_pair3<MODE, XM, TM, TV>), dim3(g), dim3(256), 0, c->stream, A, L.nn, L.nxn, L.nyn, tx,
-                       tiles, vin, rin, xin, rout, dout, xout, (TA)c1a, (TA)c1b, (TA)c2a, (TA)c2b);
+                       tiles, vin, rin, xin, rout, dout, xout, (TA)c1a, (TA)c1b, (TA)c2a, (TA)c2b, ex);
     VP_LAUNCH_CHECK();
   }
 }
@@ -3116,14 +3190,22 @@ const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, T
   }
   TV* d[2] = {(TV*)L.d0, (TV*)L.d1};
   TV* rb[2] = {(TV*)L.r, (TV*)L.r2};
-  hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, b,
-                     (TV*)nullptr, d[0], (TV*)nullptr, (TA)k.inv_theta, 0);
-  VP_LAUNCH_CHECK();
+  bool fused_first = false;   // the tiles form d0 themselves
+  if constexpr (B == 3) fused_first = m >= 2 && coarse_tiles<TM, TV>(L);
+  if (!fused_first) {
+    hipLaunchKernelGGL((k_cheb_first<B, TM, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, c->stream, A, L.nn, b,
+                       (TV*)nullptr, d[0], (TV*)nullptr, (TA)k.inv_theta, 0);
+    VP_LAUNCH_CHECK();
+  }
   const TV* rcur = b;
   int di = 0, ri = 0;
   for (int s = 1; s <= m;) {
     if (s + 1 <= m) {
-      if (s == 1)
+      if (s == 1 && fused_first)
+        launch_pairb<B, PAIR_FIRST_STEP, 2>(c, L, A, (const TV*)nullptr, rcur, (const TV*)x, rb[ri], d[di ^ 1], x,
+                                            k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1],
+                                            PairExtra{nullptr, nullptr, 0, 0, k.inv_theta});
+      else if (s == 1)
         launch_pairb<B, PAIR_STEP_STEP, 2>(c, L, A, (const TV*)d[di], rcur, (const TV*)x, rb[ri], d[di ^ 1], x,
                                            k.cdd[s], k.cdr[s], k.cdd[s + 1], k.cdr[s + 1]);
       else {
@@ -3157,7 +3239,7 @@ const TV* smooth_pre_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, T
 // xin (nullable): the corrected x in another buffer, for the four-sweep walk.
 template <int B, typename TM, typename TV>
 void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x, const float* Ares = nullptr,
-                       const TV* xin = nullptr) {
+                       const TV* xin = nullptr, const PairExtra* pro = nullptr) {
   using TA = typename Acc<TV>::type;
   const bool fine = &L == &c->lev[0];
   const int m = c->cheb_degree - 1;
@@ -3181,7 +3263,10 @@ void smooth_post_pairs(vp_ctx c, const Level& L, const TM* A, const TV* b, TV* x
       done = true;
     }
   }
-  if (!done)
+  if (!done && pro)   // x + P xc formed by the tiles themselves (x is the uncorrected iterate)
+    launch_pairb<B, PAIR_PROLONG_RFIRST, 1>(c, L, A, (const TV*)nullptr, b, (const TV*)x, rb[0], d[1], x2,
+                                            k.inv_theta, 0.0, k.cdd[1], k.cdr[1], *pro);
+  else if (!done)
     launch_pairb<B, PAIR_RFIRST_STEP, 1>(c, L, A, (const TV*)x, b, (const TV*)x, rb[0], d[1], x2, k.inv_theta, 0.0,
                                          k.cdd[1], k.cdr[1]);
   const TV* xcur = x2;
@@ -3280,16 +3365,21 @@ void vcycle_level(vp_ctx c, int l, const TV* b, TV* x) {
     // the four-sweep walk reads the corrected x around its strips, so the correction
     // goes to a second buffer and the walk writes x
     const bool walk4 = B == 2 && pairs && std::is_same<TM, TV>::value && c->cheb_degree == 4 && !Ares;
+    // tiled coarse pairs take the correction x + P xc into their first pass
+    const bool fused_pro = B == 3 && pairs && std::is_same<TP, TV>::value && coarse_tiles<TM, TV>(L);
     TV* xcor = walk4 ? (TV*)L.x2 : x;
-    hipLaunchKernelGGL((k_prolong_add<B, TP, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
-                       L.nyn, L.ncx, L.ncy, (const TV*)N.x, (const TV*)x, xcor);
-    VP_LAUNCH_CHECK();
+    if (!fused_pro) {
+      hipLaunchKernelGGL((k_prolong_add<B, TP, TV>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, P, L.nn, L.nxn,
+                         L.nyn, L.ncx, L.ncy, (const TV*)N.x, (const TV*)x, xcor);
+      VP_LAUNCH_CHECK();
+    }
+    const PairExtra pro{(const void*)P, (const void*)N.x, L.ncx, L.ncy, 0.0};
     if constexpr (B == 2) {
       if (walk4) smooth_post_pairs<B, TM, TV>(c, L, A, b, x, nullptr, (const TV*)xcor);
       else if (pairs) smooth_post_pairs<B, TM, TV>(c, L, A, b, x, Ares);
       else smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio, 0.0, Ares);
     } else if constexpr (pairable) {
-      if (pairs) smooth_post_pairs<B, TM, TV>(c, L, A, b, x);
+      if (pairs) smooth_post_pairs<B, TM, TV>(c, L, A, b, x, nullptr, nullptr, fused_pro ? &pro : nullptr);
       else smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
     } else {
       smooth<B, TM, TV>(c, l, L, A, b, x, false, c->cheb_degree, c->cheb_ratio);
