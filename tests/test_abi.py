@@ -48,3 +48,28 @@ def test_create_rejects_bad_descriptions_without_touching_the_device():
     assert b"nx" in vp.LIB.vp_last_error(None)
     d.nx, d.dt = 8, -1.0
     assert vp.LIB.vp_create(ctypes.byref(d), None, ctypes.byref(h)) == vp.VP_EINVAL
+
+
+def header_constants():
+    """NAME = value pairs of the enums in include/vp.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HDRS[0]).read(), flags=re.S)
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(VP_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvp.so not built")
+def test_binding_constants_match_the_header():
+    """Every enum value the binding defines equals the header's, and the profiling
+    kernel ids cover the header's list (VP_KID_COUNT entries)."""
+    from paper_2204_10822_amd import vp
+    consts = header_constants()
+    checked = 0
+    for name, value in consts.items():
+        if name.startswith("VP_KID_") or not hasattr(vp, name):
+            continue
+        assert getattr(vp, name) == value, name
+        checked += 1
+    assert checked >= 20
+    kids = {k: v for k, v in consts.items() if k.startswith("VP_KID_") and k != "VP_KID_COUNT"}
+    assert sorted(vp.VP_KID.values()) == sorted(kids.values()) == list(range(consts["VP_KID_COUNT"]))
+    for name, value in vp.VP_KID.items():
+        assert kids["VP_KID_" + name.upper()] == value, name
