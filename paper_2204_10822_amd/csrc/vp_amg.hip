@@ -1117,8 +1117,9 @@ __device__ __forceinline__ WVec<T> wsolve(const WBlk<T>& Di, const T (&r)[2]) {
   return WVec<T>{t0, t1};
 }
 
+constexpr int kWalk4Waves = 2;   // waves (strips) per workgroup: finer packing of the resident slots
 template <int KIND, typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kWalk4Waves)
 k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const T* __restrict__ b,
              const T* __restrict__ xin, T* __restrict__ rout, T* __restrict__ xout, T c0, T a1, T b1, T a2, T b2,
              T a3, T b3) {
@@ -1127,7 +1128,7 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
   using Rw = WRow<T>;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 56 - 4 + lane;
-  const int j0 = (blockIdx.y * 4 + (int)(threadIdx.x >> 6)) * TR;
+  const int j0 = (blockIdx.y * kWalk4Waves + (int)(threadIdx.x >> 6)) * TR;
   const bool in = i >= 0 && i < nxn;
   const int ic = in ? i : -(1 << 29);   // idle lanes load nothing
   const int lm = (lane + 63) & 63, lp = (lane + 1) & 63;
@@ -3161,16 +3162,16 @@ void launch_walk4(vp_ctx c, const Level& L, const T* A, const T* b, const T* xin
     int ncu = 0, per_cu = 0;
     VP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
     VP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_cheb_walk4<KIND, T>), 256, 0));
+        &per_cu, reinterpret_cast<const void*>(&k_cheb_walk4<KIND, T>), 64 * kWalk4Waves, 0));
     resident = std::max(1, ncu * per_cu);
   }
   const int gx = (L.nxn + 55) / 56;
-  const int gy_fit = std::max(1, resident / gx);   // workgroup rows (4 strips each) that fit
-  const int tr = std::max(8, (L.nyn + 4 * gy_fit - 1) / (4 * gy_fit));
-  const int gy = (L.nyn + 4 * tr - 1) / (4 * tr);
-  hipLaunchKernelGGL((k_cheb_walk4<KIND, T>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, c->stream, tr, A, L.nn,
-                     L.nxn, L.nyn, b, xin, rout, xout, (T)k.inv_theta, (T)k.cdd[1], (T)k.cdr[1], (T)k.cdd[2],
-                     (T)k.cdr[2], (T)k.cdd[3], (T)k.cdr[3]);
+  const int gy_fit = std::max(1, resident / gx);   // workgroup rows (kWalk4Waves strips each) that fit
+  const int tr = std::max(8, (L.nyn + kWalk4Waves * gy_fit - 1) / (kWalk4Waves * gy_fit));
+  const int gy = (L.nyn + kWalk4Waves * tr - 1) / (kWalk4Waves * tr);
+  hipLaunchKernelGGL((k_cheb_walk4<KIND, T>), dim3((unsigned)gx, (unsigned)gy), dim3(64 * kWalk4Waves), 0,
+                     c->stream, tr, A, L.nn, L.nxn, L.nyn, b, xin, rout, xout, (T)k.inv_theta, (T)k.cdd[1],
+                     (T)k.cdr[1], (T)k.cdd[2], (T)k.cdr[2], (T)k.cdd[3], (T)k.cdr[3]);
   VP_LAUNCH_CHECK();
 }
 
