@@ -18,6 +18,9 @@ With bf16=True the rounding points of the BF16 path are emulated: the network
 input, conv/down weights, every stored activation, the up-sampling product before
 its bias, and every per-layer gradient fed to the weight/input products are
 rounded to BF16 (round to nearest even); accumulation stays FP64.
+
+The optimiser (adam_step) is plain Adam with the library's constants
+(beta 0.9 / 0.999, eps 1e-8), FP64.
 """
 from __future__ import annotations
 
@@ -249,3 +252,16 @@ def loss_and_grad(theta, x, t, bf16=False):
             agrad[i2] += dX[..., cin:]
     flat = np.concatenate([np.concatenate([dW.ravel(), db.ravel()]) for dW, db in grads])
     return loss, flat, out
+
+
+# --- optimiser ------------------------------------------------------------------------
+def adam_step(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba, Algorithm 1) in FP64: first and second moment
+    running averages, their bias corrections by 1 - beta^step (step counts from 1),
+    and the update lr * m_hat / (sqrt(v_hat) + eps).  Returns (theta, m, v)."""
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    return np.asarray(theta, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -170,6 +170,57 @@ def test_drag_only_balance():
     np.testing.assert_allclose(V[30:35, 28:37], np.broadcast_to(u * dirn, (5, 9, 2)), rtol=1e-10)
 
 
+def test_coriolis_and_air_load_closed_form():
+    """eq. F with uniform fields: every interior node's test function integrates to
+    hx*hy, so F_i = hx hy (rho H v^n - dt rho H f_c e_r x (v^n - v_o) + dt C_a rho_a |v_a| v_a)
+    with e_r x u = (-u_y, u_x) (Sec. 3, explicit Coriolis; eq. force)."""
+    n = 8
+    w = inputs.synthetic(n, 13)
+    d = w.desc
+    H = np.full_like(w.H, 0.7)
+    vn = np.zeros_like(w.v_air)
+    vn[..., 0], vn[..., 1] = 0.12, -0.05
+    vo = np.zeros_like(vn)
+    vo[..., 0], vo[..., 1] = -0.03, 0.08
+    va = np.zeros_like(vn)
+    va[..., 0], va[..., 1] = 6.0, 8.0
+    p = O.VPProblem(d, H, np.ones_like(H), va, vo, vn)
+    F = p.load().reshape(n + 1, n + 1, 2)
+    rhoH = d.rho_ice * 0.7
+    u = np.array([0.12 + 0.03, -0.05 - 0.08])                  # v^n - v_o
+    cor = np.array([-u[1], u[0]])                               # e_r x u
+    ta = d.C_air * d.rho_air * 10.0 * np.array([6.0, 8.0])
+    per_area = rhoH * np.array([0.12, -0.05]) - d.dt * rhoH * d.f_coriolis * cor + d.dt * ta
+    hx, hy = d.Lx / n, d.Ly / n
+    np.testing.assert_allclose(F[1:-1, 1:-1], np.broadcast_to(hx * hy * per_area, (n - 1, n - 1, 2)), rtol=1e-13)
+    # a corner node sees one cell: a quarter of the area
+    np.testing.assert_allclose(F[0, 0], 0.25 * hx * hy * per_area, rtol=1e-13)
+
+
+def test_coriolis_step_closed_form():
+    """No ice strength, no ocean drag, no wind, uniform H, v^n and v_o: the step is
+    the mass balance rho H v = rho H (v^n - dt f_c e_r x (v^n - v_o)) (eq. Av=F with
+    eq. F), so away from the boundary v = v^n - dt f_c e_r x (v^n - v_o).  The
+    consistent-mass coupling to the v = 0 boundary decays by ~0.27 per node."""
+    n = 64
+    w = inputs.synthetic(n, 14)
+    d = w.desc.replace(P_star=0.0, C_ocean=0.0)
+    assert d.f_coriolis > 0.0
+    H = np.full_like(w.H, 1.3)
+    vn = np.zeros_like(w.v_air)
+    vn[..., 0], vn[..., 1] = 0.21, 0.07
+    vo = np.zeros_like(vn)
+    vo[..., 0], vo[..., 1] = 0.02, -0.04
+    z = np.zeros_like(vn)
+    p = O.VPProblem(d, H, np.ones_like(H), z, vo, vn)
+    res = O.newton_solve(p, variant="std", tol=1e-13, maxit=20)
+    assert res.converged
+    V = res.v.reshape(n + 1, n + 1, 2)
+    u = np.array([0.21 - 0.02, 0.07 + 0.04])
+    expect = np.array([0.21, 0.07]) - d.dt * d.f_coriolis * np.array([-u[1], u[0]])
+    np.testing.assert_allclose(V[25:40, 25:40], np.broadcast_to(expect, (15, 15, 2)), rtol=1e-12, atol=0)
+
+
 # --- Newton finds the unique minimiser of the convex energy ------------------------
 def test_newton_matches_bruteforce_minimisation():
     p = _prob(3, delta_min=3e-7)
