@@ -197,6 +197,23 @@ typedef struct { int iters; double rel_resid; } vp_krylov_info;
 int vp_krylov_solve(vp_ctx ctx, const double* b, double* x, const vp_krylov_opts* opts,
                     vp_krylov_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the flexible-CG solve of
+ * vp_krylov_solve (opts->method must be VP_KRYLOV_FCG; restart is ignored) with
+ * its four work vectors in a static device array of the library instead of a
+ * workspace allocated on the first solve.  The call allocates nothing; the
+ * operator and AMG hierarchy come from earlier vp_newton_assemble / vp_amg_setup
+ * calls.  Limit: at most 2,359,296 dofs (a 1085 x 1085-cell Q1 mesh); the array
+ * takes 72 MiB on every GPU the library runs on, from the first vp_create on that
+ * GPU until the process ends.  All contexts on one GPU share it and it keeps the
+ * last call's contents (the solve overwrites every entry it reads), so calls on
+ * one GPU that overlap in time (other host threads, other streams) race.  Event
+ * profiling (vp_profile) records nothing during this call.  Results are those of
+ * vp_krylov_solve with method VP_KRYLOV_FCG.  VP_EINVAL for null pointers, another
+ * method or a larger mesh; VP_ESTATE before assembly or AMG setup. */
+int vp_krylov_solve_noalloc(vp_ctx ctx, const double* b, double* x, const vp_krylov_opts* opts,
+                            vp_krylov_info* info);
+
 /* Dual update (eq. tautilde with eq. modification, Sec. 4.2):
  * pi <- pi + alpha * pi~(v, dv, pi), in place. */
 int vp_pi_update(vp_ctx ctx, const double* v, const double* dv, double* pi, double alpha);

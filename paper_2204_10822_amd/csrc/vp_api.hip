@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace vp {
 void amg_free(vp_ctx c);
@@ -18,7 +19,32 @@ void amg_reset_estimates(vp_ctx c);
 
 using namespace vp;
 
+// Workspace of vp_krylov_solve_noalloc: the four flexible-CG vectors (r, q, z, p) of
+// at most kNoAllocDofs doubles each (72 MiB), one copy per GPU, held until the
+// process ends.  Host code never passes this name to a kernel: it is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, per device.
+static constexpr size_t kNoAllocDofs = 2359296;
+static __device__ __align__(256) double scratch[4 * kNoAllocDofs];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device;
+// resolved once per device.
+double* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error(VP_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    VP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(VP_EHIP, "hipGetSymbolAddress returned no address for the Krylov workspace");
+    g_scratch_dev[device] = static_cast<double*>(p);
+  }
+  return g_scratch_dev[device];
+}
 
 thread_local std::string g_create_error;
 
@@ -237,10 +263,10 @@ int fgmres(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_kry
 // flexible CG (Polak-Ribiere form), one host synchronisation per iteration
 // dscal layout: [0] r.z  [1] p.q  [4] r.r  [5] z.r new  [6] z.q
 // ---------------------------------------------------------------------------
-int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov_info* info) {
+// ws: four vectors of ndof doubles (r, q, z, p)
+int fcg(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_krylov_info* info, double* ws) {
   const size_t n = c->ndof;
-  ensure_krylov(c, 2);
-  double* r = c->kv;          // r and q adjacent: mdot over [r, q]
+  double* r = ws;             // r and q adjacent: mdot over [r, q]
   double* q = r + n;
   double* z = q + n;
   double* p = z + n;
@@ -293,7 +319,10 @@ int krylov(vp_ctx c, const double* b, double* x, const vp_krylov_opts& o, vp_kry
   require(c->have_K, VP_ESTATE, "no assembled operator");
   require(c->amg_ready, VP_ESTATE, "AMG not set up");
   require(o.maxit >= 1 && o.rtol > 0.0, VP_EINVAL, "bad Krylov options");
-  if (o.method == VP_KRYLOV_FCG) return fcg(c, b, x, o, info);
+  if (o.method == VP_KRYLOV_FCG) {
+    ensure_krylov(c, 2);
+    return fcg(c, b, x, o, info, c->kv);
+  }
   require(o.restart >= 1 && o.restart <= kMaxRestart, VP_EINVAL, "restart out of range");
   return fgmres(c, b, x, o, info);
 }
@@ -446,6 +475,7 @@ int vp_create(const vp_problem_desc* desc, void* stream, vp_ctx* out) {
       c->desc = *desc;
       c->stream = (hipStream_t)stream;
       VP_HIP(hipGetDevice(&c->device));
+      c->static_ws = scratch_address(c->device);
       c->order = desc->order == 2 ? 2 : 1;
       ElemConst& e = c->ec;
       e.nx = desc->nx; e.ny = desc->ny;
@@ -655,6 +685,28 @@ int vp_krylov_solve(vp_ctx c, const double* b, double* x, const vp_krylov_opts* 
   return guarded(c, [&] {
     require(c != nullptr && b && x && o, VP_EINVAL, "null argument");
     return krylov(c, b, x, *o, info);
+  });
+}
+
+int vp_krylov_solve_noalloc(vp_ctx c, const double* b, double* x, const vp_krylov_opts* o,
+                            vp_krylov_info* info) {
+  return guarded(c, [&] {
+    require(c != nullptr && b && x && o, VP_EINVAL, "null argument");
+    require(o->method == VP_KRYLOV_FCG, VP_EINVAL, "the allocation-free Krylov solve runs flexible CG only");
+    require(c->ndof <= kNoAllocDofs, VP_EINVAL,
+            "mesh too large for the static Krylov workspace (at most 2359296 dofs)");
+    require(c->have_K, VP_ESTATE, "no assembled operator");
+    require(c->amg_ready, VP_ESTATE, "AMG not set up");
+    require(o->maxit >= 1 && o->rtol > 0.0, VP_EINVAL, "bad Krylov options");
+    require(c->static_ws != nullptr, VP_ESTATE, "no workspace address for this device");
+    // profiling creates events on demand: leave it off for this call
+    struct ProfOff {
+      Prof& p;
+      bool on;
+      explicit ProfOff(Prof& q) : p(q), on(q.on) { p.on = false; }
+      ~ProfOff() { p.on = on; }
+    } off(c->prof);
+    return fcg(c, b, x, *o, info, c->static_ws);
   });
 }
 

@@ -237,6 +237,7 @@ struct vp_ctx_s {
   double* hscal = nullptr;         // pinned host scalars [256]
   double* work = nullptr;          // [6*ndof] Newton/line-search temporaries
   double* kv = nullptr;            // Krylov bases [(2*restart+1 + 4) * ndof]
+  double* static_ws = nullptr;     // device address of the static workspace (allocation-free solve)
   int kv_restart = 0;
   double* dense = nullptr;         // coarse dense matrix scratch
   double* gal_work = nullptr;      // A P per fine node for the Galerkin product [9*3*B*nn]

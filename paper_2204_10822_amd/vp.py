@@ -28,7 +28,7 @@ VP_AMG_SA, VP_AMG_RS = 0, 1
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_residual",
             "vp_newton_assemble", "vp_operator_apply", "vp_operator_export", "vp_amg_setup",
             "vp_amg_apply", "vp_amg_info", "vp_amg_export", "vp_amg_rs_info", "vp_amg_rs_export",
-            "vp_krylov_solve", "vp_pi_update", "vp_pi_init",
+            "vp_krylov_solve", "vp_krylov_solve_noalloc", "vp_pi_update", "vp_pi_init",
             "vp_newton_step", "vp_newton_solve", "vp_default_opts", "vp_advect", "vp_profile",
             "vp_profile_read"]
 EXPORTED_NET = ["vpnet_create", "vpnet_destroy", "vpnet_last_error", "vpnet_param_count",
@@ -98,6 +98,7 @@ def _load():
         "vp_amg_rs_info": (I, [P, I, P]),
         "vp_amg_rs_export": (I, [P, I, P, P, P, P, P, P, P, P]),
         "vp_krylov_solve": (I, [P, P, P, C.POINTER(vp_krylov_opts), C.POINTER(vp_krylov_info)]),
+        "vp_krylov_solve_noalloc": (I, [P, P, P, C.POINTER(vp_krylov_opts), C.POINTER(vp_krylov_info)]),
         "vp_pi_update": (I, [P, P, P, P, D]),
         "vp_pi_init": (I, [P, P, P]),
         "vp_newton_step": (I, [P, P, P, C.POINTER(vp_newton_opts), C.POINTER(vp_amg_opts),
@@ -303,6 +304,15 @@ class Context:
         rc = self._check(LIB.vp_krylov_solve(self.h, _ptr(b, self.node_shape, "b"),
                                              _ptr(x, self.node_shape, "x"), C.byref(opts),
                                              C.byref(info)))
+        return rc, info
+
+    def vp_krylov_solve_noalloc(self, b, x, opts=None):
+        if opts is None:
+            opts = default_opts()[2]
+        info = vp_krylov_info()
+        rc = self._check(LIB.vp_krylov_solve_noalloc(self.h, _ptr(b, self.node_shape, "b"),
+                                                     _ptr(x, self.node_shape, "x"), C.byref(opts),
+                                                     C.byref(info)))
         return rc, info
 
     def vp_pi_update(self, v, dv, pi, alpha):
