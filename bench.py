@@ -5,9 +5,13 @@ One "step" is a whole stress-velocity Newton solve (residual, assembly, AMG
 setup, AMG-preconditioned Krylov, energy backtracking, dual update; Sec. 4.2,
 5.1, 5.4) from v = 0, pi = 0 on the 2048 x 2048 Q1 workload (8,396,802
 unknowns; wind to 25 m/s, H in [0.05, 1.5] m, Delta_min = 2e-10).  Inputs are
-resident in HBM before the timed region.  The plain FP64 path and the mixed
-path (FP32 V-cycle and preconditioner SpMV, FP64 residual, tau/Delta,
-orthogonalisation and update) are both timed; `value` is the faster one.
+resident in HBM before the timed region.  Paths: plain FP64; FP32 V-cycle and
+preconditioner SpMV; FP32 V-cycle with BF16 coarse-level storage (the mixed
+mode); each mixed mode also from the learned start (U-Net inference and the
+energy choice inside the timed region).  Residual, tau/Delta, Krylov
+orthogonalisation and update are FP64 in every path.  `value` is the mixed +
+learned path's time, reported beside plain FP64; every path's final velocity is
+compared with the FP64 path's and put through the CPU oracle's residual.
 
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
@@ -26,6 +30,7 @@ sys.path.insert(0, ROOT)
 PREC = {"fp64": 0, "fp32": 1, "fp32+learned": 1, "bf16": 2, "bf16+learned": 2, "bf16all": 3, "bf16all+learned": 3,
         "fp16": 4, "fp16+learned": 4, "fp16all": 5, "fp16all+learned": 5, "fp16c32": 6, "fp16c32+learned": 6}
 METRIC = "time-to-1e-8 residual, 2048^2 mesh: plain FP64 vs mixed+learned; SpMV GB/s"
+HEADLINE = "bf16+learned"   # FP32 V-cycle, BF16 coarse storage, learned start
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak
 
@@ -34,29 +39,67 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample: int, gpu_newton_its: int, n_full: int):
-    """The CPU oracle on a bounded sample: a full Newton solve of the same recipe
-    on an n_sample^2 mesh, one thread; scaled to the full mesh by unknowns and by
-    the ratio of Newton iterations."""
+def cpu_baseline(samples, gpu_newton_its: int, n_full: int):
+    """The CPU oracle on a bounded sample: full Newton solves (direct inner solves,
+    one thread) of the same recipe on the meshes in `samples`.  The time per Newton
+    iteration is fitted as a * unknowns^p through the measured meshes and
+    extrapolated to the full mesh, times the GPU's Newton iteration count there."""
+    import math
+
     from threadpoolctl import threadpool_limits
 
     from oracle import vp_oracle as O
     from paper_2204_10822_amd import inputs
 
-    w = inputs.sharp_step(n_sample)
-    prob = O.problem_from_workload(w)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        res = O.newton_solve(prob, tol=1e-8, maxit=200)
-        t = time.perf_counter() - t0
-    dofs_s, dofs_f = 2 * (n_sample + 1) ** 2, 2 * (n_full + 1) ** 2
-    scaled = t * (dofs_f / dofs_s) * (gpu_newton_its / max(res.iterations, 1))
-    return dict(value=scaled, unit="s", cores=1, kind="oracle",
-                sample=(f"oracle Newton solve (direct inner solves) of the same recipe on a "
-                        f"{n_sample}x{n_sample} mesh: {t:.2f} s, {res.iterations} Newton its, "
-                        f"converged={res.converged}; scaled by unknowns x{dofs_f / dofs_s:.0f} and "
-                        f"by Newton its {gpu_newton_its}/{res.iterations}"),
-                sample_seconds=t)
+    meas = []
+    for ns in samples:
+        w = inputs.sharp_step(ns)
+        prob = O.problem_from_workload(w)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            res = O.newton_solve(prob, tol=1e-8, maxit=200)
+            t = time.perf_counter() - t0
+        meas.append(dict(n=ns, dofs=2 * (ns + 1) ** 2, seconds=t, newton_its=res.iterations,
+                         converged=res.converged, s_per_it=t / max(res.iterations, 1)))
+        log(f"cpu baseline: oracle {ns}^2: {t:.2f} s, {res.iterations} Newton its")
+    a, b = meas[0], meas[-1]
+    p = math.log(b["s_per_it"] / a["s_per_it"]) / math.log(b["dofs"] / a["dofs"]) if len(meas) > 1 else 1.0
+    dofs_f = 2 * (n_full + 1) ** 2
+    per_it = b["s_per_it"] * (dofs_f / b["dofs"]) ** p
+    return dict(value=per_it * gpu_newton_its, unit="s", cores=1, kind="oracle",
+                sample=("oracle Newton solves (direct sparse inner solves, 1 thread) of the same recipe on "
+                        + ", ".join(f"{m['n']}^2 ({m['seconds']:.1f} s, {m['newton_its']} its)" for m in meas)
+                        + f"; time per Newton iteration ~ unknowns^{p:.2f} fitted through them, "
+                        f"extrapolated to {n_full}^2 and multiplied by the GPU's {gpu_newton_its} Newton its"),
+                measured=meas, exponent=p, sample_seconds=sum(m["seconds"] for m in meas))
+
+
+def _oracle_rel_residual(args):
+    """||R(v)|| / ||R(0)|| of the oracle's residual (eq. A - eq. F) at a GPU
+    solution v of the n^2 benchmark recipe (runs in a worker process)."""
+    import numpy as np
+
+    from oracle import vp_oracle as O
+    from paper_2204_10822_amd import inputs
+
+    n, v = args
+    prob = O.problem_from_workload(inputs.sharp_step(n))
+    r = np.linalg.norm(prob.residual(v))
+    r0 = np.linalg.norm(prob.residual(np.zeros_like(v)))
+    return float(r / r0)
+
+
+def oracle_residuals(n, vs):
+    """The oracle's relative residual at each path's final velocity, in parallel
+    worker processes (fresh interpreters: they never touch the GPU)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    names = list(vs)
+    workers = min(len(names), 6)
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        out = list(ex.map(_oracle_rel_residual, [(n, vs[k]) for k in names]))
+    return dict(zip(names, out))
 
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -168,11 +211,14 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--paths", default="fp64,fp32,fp16,fp16all+learned,fp16c32",
+    ap.add_argument("--paths", default="fp64,fp32,fp32+learned,bf16,bf16+learned",
                     help="comma list of fp64, fp32, fp32+learned, bf16, bf16+learned, bf16all, bf16all+learned, fp16, fp16+learned, fp16all, "
                          "fp16all+learned, fp16c32 (FP16 finest, FP32 coarse), fp16c32+learned")
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-samples", default="128,192",
+                    help="meshes of the oracle's bounded CPU sample (comma list)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the oracle's residual at each path's final velocity")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels"],
                     help="kernels: a short fixed sequence (for profiler counter passes)")
     args = ap.parse_args()
@@ -205,30 +251,30 @@ def main():
         return no, ao, ko
 
     ws = None
-    fields = None
     if any(p.endswith("learned") for p in args.paths.split(",")):
         from paper_2204_10822_amd import warmstart
         if os.path.exists(warmstart.WEIGHTS):
             ws = warmstart.WarmStart()
-            fields = ctx._state
         else:
             log("no trained warm-start weights: skipping the learned path")
             args.paths = ",".join(p for p in args.paths.split(",") if not p.endswith("learned"))
     starts = {}
 
     def solve(path):
-        if path.endswith("learned"):
-            # learned start (U-Net on the pooled 256-cell grid) with the energy
-            # fallback to the zero start; inside the timed region
-            starts[path] = warmstart.start_with_fallback(ctx, ws, fields, n, n, v, pi, ("learned", "zero"))
-        else:
-            v.zero_()
-            pi.zero_()
         no, ao, ko = opts(path)
+        if path.endswith("learned"):
+            # learned start (U-Net on the pooled 256-cell grid) chosen against the
+            # zero start by energy, and a rerun from zero if Newton fails from it;
+            # all inside the timed region
+            rc, info, starts[path] = warmstart.solve_with_fallback(ctx, ws, v, pi, ("learned", "zero"), no, ao, ko)
+            return rc, info
+        v.zero_()
+        pi.zero_()
         rc, info, _ = ctx.vp_newton_solve(v, pi, 200, no, ao, ko, history=False)
         return rc, info
 
     results = {}
+    finals = {}
     for path in [p for p in args.paths.split(",") if p]:
         for k in range(args.warmup):
             rc, info = solve(path)
@@ -261,9 +307,29 @@ def main():
                                   gbs=(b / (ms / cnt * 1e-3) / 1e9) if b > 0 and ms > 0 else None)
         results[path] = dict(total=total, times=times, median=statistics.median(times),
                              newton=[i.iterations for i in infos],
-                             krylov=[i.krylov_iters for i in infos], kernels=kern)
+                             krylov=[i.krylov_iters for i in infos], kernels=kern,
+                             rel_resid=infos[-1].rel_resid)
+        finals[path] = v.detach().cpu().numpy().ravel().copy()
 
-    best = min(results, key=lambda p: results[p]["median"])
+    # every path's final velocity against the plain FP64 path's, and the oracle's
+    # own residual at it (host, after the timed regions)
+    import numpy as np
+    if "fp64" in finals:
+        ref = finals["fp64"]
+        for p_, vv in finals.items():
+            results[p_]["rel_l2_vs_fp64"] = float(np.linalg.norm(vv - ref) / np.linalg.norm(ref))
+    if not args.no_oracle_check:
+        t_or = time.time()
+        orr = oracle_residuals(n, finals)
+        for p_, r_ in orr.items():
+            results[p_]["oracle_rel_resid"] = r_
+        log("oracle residual at each path's velocity: "
+            + ", ".join(f"{k} {v_:.2e}" for k, v_ in orr.items()) + f" ({time.time() - t_or:.0f}s)")
+
+    # headline: the mixed-precision + learned-start path the metric names, beside
+    # plain FP64 (both reported); otherwise the fastest path
+    best = HEADLINE if HEADLINE in results else min(results, key=lambda p: results[p]["median"])
+    fastest = min(results, key=lambda p: results[p]["median"])
     R = results[best]
     # dominant single kernel (by summed time) of the headline path
     single = {k: d for k, d in R["kernels"].items() if k != "vcycle" and d["bytes_per_launch"] > 0}
@@ -289,9 +355,14 @@ def main():
         "dtype": dtype_of(best),
         "data": "synthetic",
         "config": {"workload": w.name, "mesh": f"{n}x{n} Q1", "unknowns": 2 * nn,
-                   "tol": 1e-8, "path": best, "newton_its": R["newton"], "krylov_its": R["krylov"]},
+                   "tol": 1e-8, "path": best, "newton_its": R["newton"], "krylov_its": R["krylov"],
+                   "fp64_s": results["fp64"]["median"] if "fp64" in results else None,
+                   "speedup_vs_fp64": (results["fp64"]["median"] / R["median"]) if "fp64" in results else None,
+                   "fastest_path": fastest},
         "paths": {p: dict(median_s=d["median"], times_s=d["times"], newton_its=d["newton"],
-                          krylov_its=d["krylov"], start=starts.get(p, "zero")) for p, d in results.items()},
+                          krylov_its=d["krylov"], start=starts.get(p, "zero"), rel_resid=d["rel_resid"],
+                          rel_l2_vs_fp64=d.get("rel_l2_vs_fp64"), oracle_rel_resid=d.get("oracle_rel_resid"))
+                  for p, d in results.items()},
         "spmv_gbs": spmv["gbs"] if spmv else None,
         "kernels": R["kernels"],
         "roofline": roof,
@@ -333,8 +404,10 @@ def main():
     except Exception as e:  # the solver metric stands on its own
         out["unet"] = dict(error=str(e))
     if not args.no_cpu:
-        log(f"cpu baseline: oracle on a {args.cpu_sample}^2 sample")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, R["newton"][0], n)
+        samples = [int(x) for x in args.cpu_samples.split(",") if x]
+        ref_path = "fp64" if "fp64" in results else best
+        log(f"cpu baseline: oracle on {samples} samples")
+        out["cpu_baseline"] = cpu_baseline(samples, results[ref_path]["newton"][0], n)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

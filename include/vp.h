@@ -95,7 +95,10 @@ const char* vp_last_error(vp_ctx ctx);
  * node vectors.  Computes P = P* H exp(-C(1-A)) (eq. ice-strength), rho_ice*H and
  * the load vector F(phi_i) of eq. F (explicit Coriolis on v_prev - v_ocean,
  * air stress C_a rho_a |v_a| v_a of eq. force at quadrature points).
- * H must be >= 0 and A in [0,1]; values are not checked on the device. */
+ * The data are checked first (one device pass, synchronises): VP_EINVAL if any H
+ * is negative or not finite, any A lies outside [0, 1] or is not finite, or any
+ * velocity component is not finite; the context then keeps its previous state.
+ * A copy of H, A, v_air and v_prev is kept for vpnet_infer (vpnet.h). */
 int vp_set_state(vp_ctx ctx, const double* H, const double* A, const double* v_air,
                  const double* v_ocean, const double* v_prev);
 

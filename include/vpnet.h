@@ -19,6 +19,8 @@
 
 #include <stdint.h>
 
+#include "vp.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -51,15 +53,34 @@ int vpnet_train_step(vpnet net, const float* input, const float* target, float l
  * features: the 8 normalised input channels on the (nx/f) x (ny/f) grid of f x f
  *   cell blocks (node fields averaged to cells first): H/2, (A-0.85)/0.15,
  *   v_air/25, v_ocean/0.1, v_prev/0.3.  f must divide nx and ny.
- * targets:  training targets on the cell grid: cell mean of v / 0.3 and the mean
- *   of pi over the cell's 4 Gauss points.
- * guess:    v0 at the nodes (0 on the boundary) and pi0 at the Gauss points
- *   (nullable) by bilinear sampling of a (wc x hc) cell-centred network output. */
+ * targets:  training targets on the cell grid: cell mean of (v - v_prev) / 0.3 (the
+ *   velocity change over the step; v_prev nullable = 0) and the mean of pi over the
+ *   cell's 4 Gauss points.
+ * guess:    v0 = v_prev + 0.3 * (sampled change) at the nodes (0 on the boundary;
+ *   v_prev nullable = 0) and pi0 at the Gauss points (nullable), by bilinear
+ *   sampling of a (wc x hc) cell-centred network output. */
 int vpnet_features(int nx, int ny, int f, const double* H, const double* A, const double* v_air,
                    const double* v_ocean, const double* v_prev, float* out, void* hip_stream);
-int vpnet_targets(int nx, int ny, const double* v, const double* pi, float* out, void* hip_stream);
-int vpnet_guess(int nx, int ny, const float* net_out, int wc, int hc, double* v0, double* pi0,
-                void* hip_stream);
+int vpnet_targets(int nx, int ny, const double* v, const double* pi, const double* v_prev, float* out,
+                  void* hip_stream);
+int vpnet_guess(int nx, int ny, const float* net_out, int wc, int hc, const double* v_prev, double* v0,
+                double* pi0, void* hip_stream);
+
+/* The learned start of the Newton solve (Sec. 4.2) for the step data of the last
+ * vp_set_state on ctx: its features box-averaged onto the network's grid
+ * (f = nx / width = ny / height cells per grid cell, an integer), one forward pass,
+ * and the output sampled back onto the mesh as (v0, pi0) like vpnet_guess (v0 =
+ * v_prev + change).  Then, of the starts in `candidates` (VPNET_START_* flags), the
+ * one with the lowest energy Phi (eq. energy, the merit function of the Newton
+ * line search) is written to v0 [(ny+1)(nx+1)][2] and pi0 [4][3][ny][nx] (device):
+ * the learned start; the previous-step velocity v_prev with pi = tau/Delta (eq. pi);
+ * or zero.  Ties go to the earlier of learned, previous, zero.  chosen (host,
+ * nullable) receives the chosen flag.  Newton always finishes the solve.
+ * Needs a batch-1 network, a Q1 context and one stream for both.  Synchronises.
+ * VP_EINVAL for null pointers, an empty candidate set or mismatched sizes;
+ * VP_ESTATE before vp_set_state; VP_ENONFINITE if an energy is not finite. */
+enum { VPNET_START_LEARNED = 1, VPNET_START_PREVIOUS = 2, VPNET_START_ZERO = 4 };
+int vpnet_infer(vpnet net, vp_ctx ctx, int candidates, double* v0, double* pi0, int* chosen);
 
 /* The network's matrix-core GEMM, exposed for verification: C[M][N] (FP32) =
  * op(A) op(B) with BF16 A ([M][K], or [K][M] if a_trans) and B ([K][N], or [N][K]

@@ -116,6 +116,15 @@ ResidOut residual_eval(vp_ctx c, const double* v, const double* dv, double alpha
   return o;
 }
 
+}  // namespace
+
+double vp::energy_at(vp_ctx c, const double* v) {
+  if (!c->have_state) throw Error(VP_ESTATE, "vp_set_state not called");
+  return residual_eval(c, v, nullptr, 0.0, nullptr).energy;
+}
+
+namespace {
+
 double norm2(vp_ctx c, const double* x, size_t n) {
   launch_dot(c->stream, x, x, n, c->partials);
   finish(c, kRedBlocks, 1, 0);
@@ -493,6 +502,10 @@ int vp_create(const vp_problem_desc* desc, void* stream, vp_ctx* out) {
       c->rhoH = dalloc<double>(c->ncell);
       c->F = dalloc<double>(c->ndof);
       c->vo = dalloc<double>(c->ndof);
+      c->Hs = dalloc<double>(c->ncell);
+      c->As = dalloc<double>(c->ncell);
+      c->vas = dalloc<double>(c->ndof);
+      c->vps = dalloc<double>(c->ndof);
       c->partials = dalloc<double>(partial_slots(c->nn));
       c->dscal = dalloc<double>(256);
       VP_HIP(hipHostMalloc((void**)&c->hscal, 512 * sizeof(double), hipHostMallocDefault));
@@ -520,7 +533,7 @@ void vp_destroy(vp_ctx c) {
   rs_free(c);
   amg_free(c);
   if (K) (void)hipFree(K);
-  void* bufs[] = {c->P, c->rhoH, c->F, c->vo, c->partials, c->dscal, c->work, c->kv, c->dense,
+  void* bufs[] = {c->P, c->rhoH, c->F, c->vo, c->Hs, c->As, c->vas, c->vps, c->partials, c->dscal, c->work, c->kv, c->dense,
                   c->K2, c->K2_32, c->lmax_q2, c->pq0, c->pq1, c->pqn};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -534,6 +547,10 @@ int vp_set_state(vp_ctx c, const double* H, const double* A, const double* va, c
   return guarded(c, [&] {
     require(c != nullptr, VP_EINVAL, "null context");
     require(H && A && va && vo && vp_, VP_EINVAL, "null state array");
+    const int nb = launch_state_check(c, H, A, va, vo, vp_);
+    finish_fetch(c, nb, 1, 0, 1);
+    require(c->hscal[0] == 0.0, VP_EINVAL,
+            "invalid step data: H must be finite and >= 0, A finite in [0, 1], velocities finite");
     launch_precompute(c, H, A, va, vo, vp_);
     c->have_state = true;
     c->rnorm_zero = -1.0;

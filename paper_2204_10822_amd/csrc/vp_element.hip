@@ -141,6 +141,34 @@ __global__ void k_load_vector(ElemConst c, const double* __restrict__ rhoH,
   reinterpret_cast<double2*>(F)[n] = make_double2(fx, fy);
 }
 
+// Count of invalid step data per workgroup: H negative or not finite, A outside
+// [0, 1] or not finite, a velocity component not finite.  partials[b] (K = 1).
+__global__ void __launch_bounds__(kBlock)
+k_state_check(const double* __restrict__ H, const double* __restrict__ A, const double* __restrict__ va,
+              const double* __restrict__ vo, const double* __restrict__ vprev, size_t ncell, size_t ndof,
+              double* __restrict__ partials) {
+  __shared__ double lds[16];
+  double bad[1] = {0.0};
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ncell; e += stride) {
+    const double h = H[e], a = A[e];
+    if (!(isfinite(h) && h >= 0.0)) bad[0] += 1.0;
+    if (!(isfinite(a) && a >= 0.0 && a <= 1.0)) bad[0] += 1.0;
+  }
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ndof; e += stride)
+    if (!(isfinite(va[e]) && isfinite(vo[e]) && isfinite(vprev[e]))) bad[0] += 1.0;
+  block_sum<1>(bad, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bad[0];
+}
+
+int launch_state_check(vp_ctx c, const double* H, const double* A, const double* va, const double* vo,
+                       const double* vprev) {
+  hipLaunchKernelGGL(k_state_check, dim3(kRedBlocks), dim3(kBlock), 0, c->stream, H, A, va, vo, vprev,
+                     c->ncell, c->ndof, c->partials);
+  VP_LAUNCH_CHECK();
+  return kRedBlocks;
+}
+
 void launch_precompute(vp_ctx c, const double* H, const double* A, const double* va,
                        const double* vo, const double* vprev) {
   const size_t nc = c->ncell;
@@ -155,6 +183,11 @@ void launch_precompute(vp_ctx c, const double* H, const double* A, const double*
     VP_LAUNCH_CHECK();
   }
   VP_HIP(hipMemcpyAsync(c->vo, vo, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  // the step's data, kept for the learned start's input features
+  VP_HIP(hipMemcpyAsync(c->Hs, H, c->ncell * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  VP_HIP(hipMemcpyAsync(c->As, A, c->ncell * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  VP_HIP(hipMemcpyAsync(c->vas, va, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  VP_HIP(hipMemcpyAsync(c->vps, vprev, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
 }
 
 // ---------------------------------------------------------------------------

@@ -209,6 +209,8 @@ struct vp_ctx_s {
   double* rhoH = nullptr;   // [ncell]
   double* F = nullptr;      // [ndof]
   double* vo = nullptr;     // [ndof]
+  double *Hs = nullptr, *As = nullptr;    // copies of the step's H, A [ncell]
+  double *vas = nullptr, *vps = nullptr;  // copies of v_air, v_prev [ndof]
   bool have_state = false;
   double rnorm_zero = -1.0;
   // operator
@@ -278,6 +280,11 @@ void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, 
 void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, double* K);
 void launch_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
 void launch_pi_init(vp_ctx c, const double* v, double* pi);
+// per-workgroup counts of invalid step data into c->partials (K = 1); returns the workgroups
+int launch_state_check(vp_ctx c, const double* H, const double* A, const double* va, const double* vo,
+                       const double* vprev);
+// Phi(v) of eq. energy on the context's state (synchronises); VP_ENONFINITE if not finite
+double energy_at(vp_ctx c, const double* v);
 void launch_advect(vp_ctx c, const double* v, const double* A, const double* H, double* Ao, double* Ho);
 // Q2 velocity elements
 void launch_q2_precompute(vp_ctx c, const double* va, const double* vo, const double* vprev);

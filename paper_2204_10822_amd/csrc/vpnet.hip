@@ -402,9 +402,10 @@ __global__ void k_features(int nx, int ny, int f, const double* __restrict__ H, 
   }
 }
 
-// training targets on the cell grid: v (mean of the 4 corners)/0.3, pi (mean of the 4 points)
+// training targets on the cell grid: the velocity change v - v_prev (mean of the 4
+// corners)/0.3 (v_prev nullable: 0), pi (mean of the 4 points)
 __global__ void k_targets(int nx, int ny, const double* __restrict__ v, const double* __restrict__ pi,
-                          float* __restrict__ out) {
+                          const double* __restrict__ vprev, float* __restrict__ out) {
   const size_t ncell = (size_t)nx * ny;
   const int nxn = nx + 1;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ncell; e += (size_t)gridDim.x * blockDim.x) {
@@ -412,7 +413,11 @@ __global__ void k_targets(int nx, int ny, const double* __restrict__ v, const do
     const size_t sw = (size_t)cj * nxn + ci;
     const size_t id[4] = {sw, sw + 1, sw + nxn, sw + nxn + 1};
     double vx = 0, vy = 0;
-    for (int a = 0; a < 4; ++a) { vx += 0.25 * v[2 * id[a]]; vy += 0.25 * v[2 * id[a] + 1]; }
+    for (int a = 0; a < 4; ++a) {
+      const double px = vprev ? vprev[2 * id[a]] : 0.0, py = vprev ? vprev[2 * id[a] + 1] : 0.0;
+      vx += 0.25 * (v[2 * id[a]] - px);
+      vy += 0.25 * (v[2 * id[a] + 1] - py);
+    }
     float* o = out + e * 5;
     o[0] = (float)(vx / 0.3);
     o[1] = (float)(vy / 0.3);
@@ -438,10 +443,11 @@ __device__ __forceinline__ float sample(const float* __restrict__ F, int Wc, int
   return (float)((1 - ty) * ((1 - tx) * a + tx * b) + ty * ((1 - tx) * c + tx * d));
 }
 
-// network output (Wc x Hc x 5) -> v0 at the mesh nodes (zero on the boundary), pi0 at
-// the Gauss points, both by bilinear sampling; v de-normalised by 0.3 m/s
-__global__ void k_guess(int nx, int ny, const float* __restrict__ outp, int Wc, int Hc, double* __restrict__ v0,
-                        double* __restrict__ pi0) {
+// network output (Wc x Hc x 5) -> v0 = v_prev + the sampled change (de-normalised by
+// 0.3 m/s) at the mesh nodes (zero on the boundary; v_prev nullable: 0), pi0 at the
+// Gauss points, both by bilinear sampling
+__global__ void k_guess(int nx, int ny, const float* __restrict__ outp, int Wc, int Hc,
+                        const double* __restrict__ vprev, double* __restrict__ v0, double* __restrict__ pi0) {
   const size_t nn = (size_t)(nx + 1) * (ny + 1), ncell = (size_t)nx * ny;
   const double g0 = 0.21132486540518711775, g1 = 0.78867513459481288225;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn + ncell; e += (size_t)gridDim.x * blockDim.x) {
@@ -449,8 +455,9 @@ __global__ void k_guess(int nx, int ny, const float* __restrict__ outp, int Wc, 
       const int i = (int)(e % (nx + 1)), j = (int)(e / (nx + 1));
       const bool bnd = i == 0 || j == 0 || i == nx || j == ny;
       const double x = (double)i / nx, y = (double)j / ny;
-      v0[2 * e] = bnd ? 0.0 : 0.3 * sample(outp, Wc, Hc, 5, 0, x, y);
-      v0[2 * e + 1] = bnd ? 0.0 : 0.3 * sample(outp, Wc, Hc, 5, 1, x, y);
+      const double px = vprev ? vprev[2 * e] : 0.0, py = vprev ? vprev[2 * e + 1] : 0.0;
+      v0[2 * e] = bnd ? 0.0 : px + 0.3 * sample(outp, Wc, Hc, 5, 0, x, y);
+      v0[2 * e + 1] = bnd ? 0.0 : py + 0.3 * sample(outp, Wc, Hc, 5, 1, x, y);
     } else if (pi0) {
       const size_t cell = e - nn;
       const int ci = (int)(cell % nx), cj = (int)(cell / nx);
@@ -517,6 +524,7 @@ struct vpnet_s {
   float* gout = nullptr;
   double* red = nullptr;     // reduction partials
   double* hred = nullptr;    // pinned
+  float* feat = nullptr;     // [H][W][8] input features of vpnet_infer
   bf16* xin = nullptr;  // BF16 input
 };
 
@@ -819,7 +827,8 @@ void vpnet_destroy(vpnet_s* n) {
     if (a.y) (void)hipFree(a.y);
     if (a.g) (void)hipFree(a.g);
   }
-  void* bufs[] = {n->w, n->wb, n->g, n->m, n->v, n->col, n->fcol, n->part, n->gb, n->tmp, n->out, n->gout, n->red};
+  void* bufs[] = {n->w, n->wb, n->g, n->m, n->v, n->col, n->fcol, n->part, n->gb, n->tmp, n->out, n->gout, n->red,
+                  n->feat};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (n->hred) (void)hipHostFree(n->hred);
@@ -919,17 +928,78 @@ int vpnet_features(int nx, int ny, int f, const double* H, const double* A, cons
   return hipGetLastError() == hipSuccess ? VP_OK : VP_EHIP;
 }
 
-int vpnet_targets(int nx, int ny, const double* v, const double* pi, float* out, void* stream) {
+int vpnet_targets(int nx, int ny, const double* v, const double* pi, const double* v_prev, float* out,
+                  void* stream) {
   if (nx < 1 || ny < 1 || !v || !pi || !out) return VP_EINVAL;
-  hipLaunchKernelGGL(k_targets, dim3(gs((size_t)nx * ny)), dim3(256), 0, (hipStream_t)stream, nx, ny, v, pi, out);
+  hipLaunchKernelGGL(k_targets, dim3(gs((size_t)nx * ny)), dim3(256), 0, (hipStream_t)stream, nx, ny, v, pi, v_prev,
+                     out);
   return hipGetLastError() == hipSuccess ? VP_OK : VP_EHIP;
 }
 
-int vpnet_guess(int nx, int ny, const float* outp, int wc, int hc, double* v0, double* pi0, void* stream) {
+int vpnet_guess(int nx, int ny, const float* outp, int wc, int hc, const double* v_prev, double* v0, double* pi0,
+                void* stream) {
   if (nx < 1 || ny < 1 || wc < 1 || hc < 1 || !outp || !v0) return VP_EINVAL;
   const size_t n = (size_t)(nx + 1) * (ny + 1) + (size_t)nx * ny;
-  hipLaunchKernelGGL(k_guess, dim3(gs(n)), dim3(256), 0, (hipStream_t)stream, nx, ny, outp, wc, hc, v0, pi0);
+  hipLaunchKernelGGL(k_guess, dim3(gs(n)), dim3(256), 0, (hipStream_t)stream, nx, ny, outp, wc, hc, v_prev, v0,
+                     pi0);
   return hipGetLastError() == hipSuccess ? VP_OK : VP_EHIP;
+}
+
+int vpnet_infer(vpnet_s* n, vp_ctx c, int candidates, double* v0, double* pi0, int* chosen) {
+  return nguard(n, [&] {
+    nreq(n && c && v0 && pi0, "null argument");
+    nreq(candidates > 0 && candidates <= (VPNET_START_LEARNED | VPNET_START_PREVIOUS | VPNET_START_ZERO),
+         "candidates must be a non-empty set of VPNET_START_* flags");
+    nreq(n->Bn == 1, "vpnet_infer needs a network of batch 1");
+    nreq(c->order == 1, "the learned start takes Q1 velocity elements");
+    nreq(c->stream == n->stream, "the network and the context must share a stream");
+    const int nx = c->ec.nx, ny = c->ec.ny;
+    nreq(nx % n->W == 0 && ny % n->H == 0 && nx / n->W == ny / n->H,
+         "the mesh must be f times the network's grid on both sides (integer f)");
+    if (!c->have_state) throw Error(VP_ESTATE, "vp_set_state not called");
+    const int f = nx / n->W;
+    const size_t P = (size_t)n->H * n->W;
+    if (!n->feat) n->feat = dalloc<float>(P * kCin);
+    hipStream_t s = n->stream;
+    if (candidates & VPNET_START_LEARNED) {
+      hipLaunchKernelGGL(k_features, dim3(gs(P)), dim3(256), 0, s, nx, ny, f, c->Hs, c->As, c->vas, c->vo, c->vps,
+                         n->feat);
+      VP_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_to_bf16, dim3(gs(P * kCin)), dim3(256), 0, s, n->feat, n->acts[0].y, P * kCin);
+      VP_LAUNCH_CHECK();
+      forward(n);
+      const size_t m = (size_t)(nx + 1) * (ny + 1) + (size_t)nx * ny;
+      hipLaunchKernelGGL(k_guess, dim3(gs(m)), dim3(256), 0, s, nx, ny, n->out, n->W, n->H, c->vps, v0, pi0);
+      VP_LAUNCH_CHECK();
+    }
+    // the start with the lowest energy Phi (eq. energy), first in the order
+    // learned, previous, zero on ties
+    int best = 0;
+    double be = 0.0;
+    auto consider = [&](int flag, const double* v) {
+      const double e = energy_at(c, v);
+      if (!best || e < be) {
+        best = flag;
+        be = e;
+      }
+    };
+    if (candidates & VPNET_START_LEARNED) consider(VPNET_START_LEARNED, v0);
+    if (candidates & VPNET_START_PREVIOUS) consider(VPNET_START_PREVIOUS, c->vps);
+    if (candidates & VPNET_START_ZERO) {
+      double* z = c->work + 4 * c->ndof;
+      launch_fill(s, z, 0.0, c->ndof);
+      consider(VPNET_START_ZERO, z);
+    }
+    if (best == VPNET_START_PREVIOUS) {
+      VP_HIP(hipMemcpyAsync(v0, c->vps, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_pi_init(c, v0, pi0);
+    } else if (best == VPNET_START_ZERO) {
+      launch_fill(s, v0, 0.0, c->ndof);
+      launch_fill(s, pi0, 0.0, 4 * 3 * c->ncell);
+    }
+    if (chosen) *chosen = best;
+    return VP_OK;
+  });
 }
 
 int vpnet_gemm(const void* A, const void* B, float* C, int M, int N, int K, int a_trans, int b_trans, void* stream) {

@@ -24,6 +24,8 @@ VP_PREC_FP16_FP32COARSE = 6
 VP_KRYLOV_FGMRES, VP_KRYLOV_FCG = 0, 1
 VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
 VP_AMG_SA, VP_AMG_RS = 0, 1
+VPNET_START_LEARNED, VPNET_START_PREVIOUS, VPNET_START_ZERO = 1, 2, 4
+START = {"learned": VPNET_START_LEARNED, "previous": VPNET_START_PREVIOUS, "zero": VPNET_START_ZERO}
 
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_residual",
             "vp_newton_assemble", "vp_operator_apply", "vp_operator_export", "vp_amg_setup",
@@ -34,7 +36,7 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_resi
 EXPORTED_NET = ["vpnet_create", "vpnet_destroy", "vpnet_last_error", "vpnet_param_count",
                 "vpnet_set_params", "vpnet_get_params", "vpnet_get_grads", "vpnet_forward",
                 "vpnet_backward", "vpnet_adam", "vpnet_train_step", "vpnet_features",
-                "vpnet_targets", "vpnet_guess", "vpnet_gemm"]
+                "vpnet_targets", "vpnet_guess", "vpnet_infer", "vpnet_gemm"]
 VP_KID = dict(apply_fine=0, cheb_step0=1, sten_resid0=2, residual=3, assemble=4, vcycle=5, cheb_pair0=6,
               cheb_walk4=7)
 
@@ -122,8 +124,9 @@ def _load():
         "vpnet_adam": (I, [P, C.c_float]),
         "vpnet_train_step": (I, [P, P, P, C.c_float, C.POINTER(C.c_float)]),
         "vpnet_features": (I, [I, I, I, P, P, P, P, P, P, P]),
-        "vpnet_targets": (I, [I, I, P, P, P, P]),
-        "vpnet_guess": (I, [I, I, P, I, I, P, P, P]),
+        "vpnet_targets": (I, [I, I, P, P, P, P, P]),
+        "vpnet_guess": (I, [I, I, P, I, I, P, P, P, P]),
+        "vpnet_infer": (I, [P, P, I, P, P, C.POINTER(I)]),
         "vpnet_gemm": (I, [P, P, P, I, I, I, I, I, P]),
     }
     for name, (res, args) in sig.items():
@@ -441,6 +444,17 @@ class Net:
     def vpnet_adam(self, lr):
         return self._check(LIB.vpnet_adam(self.h, C.c_float(lr)))
 
+    def vpnet_infer(self, ctx, candidates, v0, pi0):
+        """Learned start for ctx's current state, chosen by energy among `candidates`
+        (names from START); returns the chosen name."""
+        mask = 0
+        for c in candidates:
+            mask |= START[c]
+        chosen = C.c_int()
+        self._check(LIB.vpnet_infer(self.h, ctx.h, mask, _ptr(v0, ctx.node_shape, "v0"),
+                                    _ptr(pi0, ctx.pi_shape, "pi0"), C.byref(chosen)))
+        return {v: k for k, v in START.items()}[chosen.value]
+
     def vpnet_train_step(self, x, target, lr, want_loss=True):
         P = self.B * self.H * self.W
         loss = C.c_float()
@@ -463,16 +477,18 @@ def vpnet_features(nx, ny, f, H, A, v_air, v_ocean, v_prev, out):
         raise VPError(rc, "vpnet_features")
 
 
-def vpnet_targets(nx, ny, v, pi, out):
+def vpnet_targets(nx, ny, v, pi, out, v_prev=None):
     rc = LIB.vpnet_targets(nx, ny, _fptr(v, 2 * (nx + 1) * (ny + 1), "v", torch.float64),
                            _fptr(pi, 12 * nx * ny, "pi", torch.float64),
+                           _fptr(v_prev, 2 * (nx + 1) * (ny + 1), "v_prev", torch.float64),
                            _fptr(out, nx * ny * 5, "out"), _stream())
     if rc != 0:
         raise VPError(rc, "vpnet_targets")
 
 
-def vpnet_guess(nx, ny, net_out, wc, hc, v0, pi0):
+def vpnet_guess(nx, ny, net_out, wc, hc, v0, pi0, v_prev=None):
     rc = LIB.vpnet_guess(nx, ny, _fptr(net_out, wc * hc * 5, "net_out"), wc, hc,
+                         _fptr(v_prev, 2 * (nx + 1) * (ny + 1), "v_prev", torch.float64),
                          _fptr(v0, 2 * (nx + 1) * (ny + 1), "v0", torch.float64),
                          _fptr(pi0, 12 * nx * ny, "pi0", torch.float64) if pi0 is not None else None,
                          _stream())
