@@ -156,7 +156,19 @@ typedef struct {
   double strong_threshold; /* RS: strength threshold theta in (0, 1)              */
   double max_row_sum;    /* RS: rows with |row sum| > max_row_sum |a_ii| have no
                             strong couplings (1 switches the rule off)             */
+  int variant;           /* SA, for verification: 0 = the fastest kernels; a set of
+                            VP_AMG_VAR_* flags selects reference kernels that
+                            compute the same V-cycle bit for bit                  */
+  int walk4_rows;        /* SA, for verification: 0 = automatic strip height of
+                            the four-sweep walk (degree-4 FP32/FP64 smoothing on the
+                            finest level); 1..4096 = that height                   */
 } vp_amg_opts;
+enum {
+  VP_AMG_VAR_NO_TAIL = 1,      /* one launch per sweep on the smallest levels too      */
+  VP_AMG_VAR_NO_PAIRS = 2,     /* one launch per Chebyshev sweep (no fused sweeps)     */
+  VP_AMG_VAR_NO_TAIL_LDS = 4,  /* the single-workgroup tail reloads its vectors        */
+  VP_AMG_VAR_NO_P16 = 8        /* FP16 modes: FP32 finest restriction/prolongation     */
+};
 int vp_amg_setup(vp_ctx ctx, const vp_amg_opts* opts);
 /* z = M^{-1} r, one V-cycle.  VP_ESTATE before vp_amg_setup. */
 int vp_amg_apply(vp_ctx ctx, const double* r, double* z);

@@ -2672,11 +2672,10 @@ void amg_reset_estimates(vp_ctx c) {
 }
 
 // Numeric setup on the current finest operator.
-// First level handled by the single-workgroup tail kernel, or -1 (also when the
-// environment sets VP_AMG_TAIL=0, which keeps one launch per sweep everywhere).
+// First level handled by the single-workgroup tail kernel, or -1 (also with
+// VP_AMG_VAR_NO_TAIL, which keeps one launch per sweep everywhere).
 int tail_start(vp_ctx c) {
-  const char* env = std::getenv("VP_AMG_TAIL");
-  if (env && env[0] == '0') return -1;
+  if (c->amg_variant & VP_AMG_VAR_NO_TAIL) return -1;
   if (c->cheb_degree > kTailDegree) return -1;
   for (int l = 1; l + 1 < c->nlev; ++l)
     if (c->lev[l].B == 3 && c->lev[l].nn <= (size_t)kTailNodes && c->nlev - l <= kTailLevels) return l;
@@ -2883,12 +2882,9 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   if (c->order == 2) c->lmax_q2_h = c->hscal[c->nlev];
   c->tail_level = tail_start(c);
   {
-    const char* env = std::getenv("VP_AMG_PAIRS");   // VP_AMG_PAIRS=0: one launch per sweep
-    c->pair_sweeps = !(env && env[0] == '0');
-    const char* tenv = std::getenv("VP_AMG_TAIL_LDS");   // VP_AMG_TAIL_LDS=0: the tail without LDS vectors
-    c->tail_lds = !(tenv && tenv[0] == '0');
-    const char* ph = std::getenv("VP_AMG_P16");      // VP_AMG_P16=0: FP32 finest transfers in the FP16 modes
-    c->ph_transfers = !(ph && ph[0] == '0') && c->lev[0].Ph != nullptr &&
+    c->pair_sweeps = !(c->amg_variant & VP_AMG_VAR_NO_PAIRS);
+    c->tail_lds = !(c->amg_variant & VP_AMG_VAR_NO_TAIL_LDS);
+    c->ph_transfers = !(c->amg_variant & VP_AMG_VAR_NO_P16) && c->lev[0].Ph != nullptr &&
                       (precision == VP_PREC_FP16_BF16COARSE || precision == VP_PREC_FP16 ||
                        precision == VP_PREC_FP16_FP32COARSE);
   }
@@ -3167,7 +3163,8 @@ void launch_walk4(vp_ctx c, const Level& L, const T* A, const T* b, const T* xin
   }
   const int gx = (L.nxn + 55) / 56;
   const int gy_fit = std::max(1, resident / gx);   // workgroup rows (kWalk4Waves strips each) that fit
-  const int tr = std::max(8, (L.nyn + kWalk4Waves * gy_fit - 1) / (kWalk4Waves * gy_fit));
+  const int tr = c->walk4_rows > 0 ? c->walk4_rows
+                                   : std::max(8, (L.nyn + kWalk4Waves * gy_fit - 1) / (kWalk4Waves * gy_fit));
   const int gy = (L.nyn + kWalk4Waves * tr - 1) / (kWalk4Waves * tr);
   hipLaunchKernelGGL((k_cheb_walk4<KIND, T>), dim3((unsigned)gx, (unsigned)gy), dim3(64 * kWalk4Waves), 0,
                      c->stream, tr, A, L.nn, L.nxn, L.nyn, b, xin, rout, xout, (T)k.inv_theta, (T)k.cdd[1],

@@ -359,6 +359,10 @@ void amg_setup(vp_ctx c, const vp_amg_opts& a) {
   require(c->order == 1 || a.precision <= VP_PREC_FP32_BF16COARSE, VP_EINVAL,
           "Q2 elements take the FP64, FP32 or FP32 + BF16-coarse V-cycle");
   require(a.cheb_ratio > 1.0 && a.omega_scale > 0.0, VP_EINVAL, "bad smoother options");
+  require(a.variant >= 0 && a.variant <= 15, VP_EINVAL, "unknown AMG variant flags");
+  require(a.walk4_rows >= 0 && a.walk4_rows <= 4096, VP_EINVAL, "walk4_rows out of range");
+  c->amg_variant = a.variant;
+  c->walk4_rows = a.walk4_rows;
   if (!c->amg_struct || c->max_coarse != a.max_coarse) amg_build_structure(c, c->lev[0].A64, a.max_coarse);
   c->cheb_degree = a.cheb_degree;
   c->cheb_ratio = a.cheb_ratio;
@@ -468,7 +472,7 @@ extern "C" {
 
 void vp_default_opts(vp_newton_opts* n, vp_amg_opts* a, vp_krylov_opts* k) {
   if (n) *n = vp_newton_opts{VP_SVN, 1e-8, 0.1, 30, VP_LS_ENERGY};
-  if (a) *a = vp_amg_opts{4, 140, VP_PREC_FP64, 30.0, 1.0, VP_AMG_SA, 3, 0.5, 0.9};
+  if (a) *a = vp_amg_opts{4, 140, VP_PREC_FP64, 30.0, 1.0, VP_AMG_SA, 3, 0.5, 0.9, 0, 0};
   if (k) *k = vp_krylov_opts{VP_KRYLOV_FCG, 30, 500, 1e-2};
 }
 

@@ -229,6 +229,8 @@ struct vp_ctx_s {
   int tail_level = -1;             // first level run by the single-workgroup tail kernel
   bool pair_sweeps = true;         // finest-level smoother sweeps fused in pairs
   bool tail_lds = true;            // FP32-vector tail with LDS vectors and register blocks
+  int amg_variant = 0;             // VP_AMG_VAR_* flags of the last setup (verification)
+  int walk4_rows = 0;              // fixed strip height of the four-sweep walk (0 = automatic)
   double cheb_ratio = 30.0;
   int max_coarse = 140;
   int power_its_cold = 16, power_its_warm = 6;

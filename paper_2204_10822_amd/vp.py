@@ -24,6 +24,7 @@ VP_PREC_FP16_FP32COARSE = 6
 VP_KRYLOV_FGMRES, VP_KRYLOV_FCG = 0, 1
 VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
 VP_AMG_SA, VP_AMG_RS = 0, 1
+VP_AMG_VAR_NO_TAIL, VP_AMG_VAR_NO_PAIRS, VP_AMG_VAR_NO_TAIL_LDS, VP_AMG_VAR_NO_P16 = 1, 2, 4, 8
 VPNET_START_LEARNED, VPNET_START_PREVIOUS, VPNET_START_ZERO = 1, 2, 4
 START = {"learned": VPNET_START_LEARNED, "previous": VPNET_START_PREVIOUS, "zero": VPNET_START_ZERO}
 
@@ -52,7 +53,8 @@ class vp_problem_desc(C.Structure):
 class vp_amg_opts(C.Structure):
     _fields_ = [("cheb_degree", C.c_int), ("max_coarse", C.c_int), ("precision", C.c_int),
                 ("cheb_ratio", C.c_double), ("omega_scale", C.c_double), ("kind", C.c_int), ("sweeps", C.c_int),
-                ("strong_threshold", C.c_double), ("max_row_sum", C.c_double)]
+                ("strong_threshold", C.c_double), ("max_row_sum", C.c_double), ("variant", C.c_int),
+                ("walk4_rows", C.c_int)]
 
 
 class vp_krylov_opts(C.Structure):

@@ -355,112 +355,127 @@ def test_galerkin_coarse_operators(vp, nx, ny, seed):
         assert err < 1e-12
 
 
+_VC_CASES = {}
+
+
+def _vcycle(vp, nx, ny, seed, prec, degree, rseed, variant=0, walk4_rows=0):
+    """One V-cycle of a fresh context (so the spectral estimates are identical) on a
+    random residual, with the given kernel variant flags and walk strip height."""
+    key = (nx, ny, seed)
+    if key not in _VC_CASES:
+        w = inputs.synthetic(nx, seed, ny=ny, Ly=512e3 * ny / nx)
+        w.v_prev = 0.05 * np.random.default_rng(seed).standard_normal(w.v_prev.shape)
+        prob = O.problem_from_workload(w)
+        v = _rand_v(prob, 3, 0.05)
+        _VC_CASES[key] = (w, prob, v, prob.pi_consistent(v))
+    w, prob, v, pi = _VC_CASES[key]
+    print(f"[case] nx={nx} ny={ny} seed={seed} prec={prec} degree={degree} variant={variant} rows={walk4_rows}",
+          flush=True)
+    ctx = vp.context_for(w)
+    ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(pi), vp.VP_SVN)
+    rng = np.random.default_rng(rseed)
+    r = rng.standard_normal(2 * prob.mesh.nnode)
+    r[~prob.mesh.free_dof] = 0.0
+    n, a, k = vp.default_opts()
+    a.precision, a.cheb_degree, a.variant, a.walk4_rows = prec, degree, variant, walk4_rows
+    ctx.vp_amg_setup(a)
+    z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
+    ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
+    return _host(z).ravel(), ctx
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2, 5, 6])
-def test_vcycle_tail_kernel_matches_per_sweep_launches(vp, prec, monkeypatch):
+def test_vcycle_tail_kernel_matches_per_sweep_launches(vp, prec):
     """The single-workgroup kernel for the smallest levels runs the same per-node
     arithmetic as the one-launch-per-sweep path: the V-cycle outputs are bitwise
-    equal (VP_AMG_TAIL=0 switches the single-workgroup kernel off at setup)."""
-    nx, ny, seed = 200, 150, 8
-    outs = []
-    for env in ("0", "1"):   # fresh contexts: identical spectral estimates
-        monkeypatch.setenv("VP_AMG_TAIL", env)
-        w, prob, ctx = _case(vp, nx, ny, seed)
-        v = _rand_v(prob, 3, 0.05)
-        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
-        rng = np.random.default_rng(4)
-        r = rng.standard_normal(2 * prob.mesh.nnode)
-        r[~prob.mesh.free_dof] = 0.0
-        n, a, k = vp.default_opts()
-        a.precision = prec
-        ctx.vp_amg_setup(a)
-        z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
-        ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
-        outs.append(_host(z).ravel())
-    print(f"[tail] prec={prec} levels {ctx.vp_amg_info()} max |diff| {np.abs(outs[0] - outs[1]).max():.2e}",
-          flush=True)
-    assert np.array_equal(outs[0], outs[1])
+    equal (VP_AMG_VAR_NO_TAIL switches the single-workgroup kernel off at setup)."""
+    ref, _ = _vcycle(vp, 200, 150, 8, prec, 4, 4, variant=vp.VP_AMG_VAR_NO_TAIL)
+    out, ctx = _vcycle(vp, 200, 150, 8, prec, 4, 4)
+    print(f"[tail] prec={prec} levels {ctx.vp_amg_info()} max |diff| {np.abs(ref - out).max():.2e}", flush=True)
+    assert np.array_equal(ref, out)
 
 
 @pytest.mark.parametrize("degree", [2, 3, 4, 5])
-@pytest.mark.parametrize("prec", [0, 1, 5, 6])
-def test_paired_sweeps_match_single_sweeps(vp, prec, degree, monkeypatch):
+@pytest.mark.parametrize("prec", [0, 1, 2, 4, 5, 6])
+def test_paired_sweeps_match_single_sweeps(vp, prec, degree):
     """The finest-level smoother with its sweeps fused (two Chebyshev steps per
     pass, or all four of a degree-4 smoothing in one column walk) gives bitwise the
-    V-cycle of one launch per sweep (VP_AMG_PAIRS=0), for even and odd step counts."""
-    nx, ny, seed = 200, 150, 8
+    V-cycle of one launch per sweep (VP_AMG_VAR_NO_PAIRS), for even and odd step
+    counts, in every storage mode with fused sweeps (BF16 coarse levels included)."""
+    ref, _ = _vcycle(vp, 200, 150, 8, prec, degree, 5, variant=vp.VP_AMG_VAR_NO_PAIRS)
+    out, _ = _vcycle(vp, 200, 150, 8, prec, degree, 5)
+    print(f"[pairs] prec={prec} degree={degree} max |diff| {np.abs(ref - out).max():.2e} "
+          f"|z| {np.abs(out).max():.2e}", flush=True)
+    assert np.array_equal(ref, out)
+
+
+@pytest.mark.parametrize("rows", [1, 5, 13, 38, 151])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_walk4_strip_heights(vp, prec, rows):
+    """The four-sweep column walk gives bitwise the single sweeps' V-cycle for any
+    strip height: short strips, the 38 rows the launcher picks at 2049^2, and one
+    strip over the whole mesh (the halo rows each strip recomputes are the same)."""
+    ref, _ = _vcycle(vp, 200, 150, 8, prec, 4, 9, variant=vp.VP_AMG_VAR_NO_PAIRS)
+    out, _ = _vcycle(vp, 200, 150, 8, prec, 4, 9, walk4_rows=rows)
+    print(f"[walk4 rows] prec={prec} rows={rows} max |diff| {np.abs(ref - out).max():.2e}", flush=True)
+    assert np.array_equal(ref, out)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_walk4_production_geometry_2048(vp, prec):
+    """At the benchmark's 2048^2 cells the launcher runs the walk in its production
+    geometry (tall strips sized to the resident workgroups); the V-cycle is bitwise
+    the one of single sweeps.  (v random, pi = tau/Delta of it, both set on the GPU.)"""
+    n = 2048
     outs = []
-    for env in ("0", "1"):   # fresh contexts: identical spectral estimates
-        monkeypatch.setenv("VP_AMG_PAIRS", env)
-        w, prob, ctx = _case(vp, nx, ny, seed)
-        v = _rand_v(prob, 3, 0.05)
-        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
-        rng = np.random.default_rng(5)
-        r = rng.standard_normal(2 * prob.mesh.nnode)
-        r[~prob.mesh.free_dof] = 0.0
-        n, a, k = vp.default_opts()
-        a.precision = prec
-        a.cheb_degree = degree
+    for variant in (vp.VP_AMG_VAR_NO_PAIRS, 0):
+        w = inputs.synthetic(n, 10)
+        print(f"[walk4 2048] prec={prec} variant={variant}", flush=True)
+        ctx = vp.context_for(w)
+        g = torch.Generator(device="cuda").manual_seed(3)
+        v = 0.05 * torch.randn(ctx.node_shape, dtype=torch.float64, device="cuda", generator=g)
+        vv = v.view(n + 1, n + 1, 2)
+        vv[0].zero_(); vv[-1].zero_(); vv[:, 0].zero_(); vv[:, -1].zero_()
+        pi = torch.zeros(ctx.pi_shape, dtype=torch.float64, device="cuda")
+        ctx.vp_pi_init(v, pi)
+        ctx.vp_newton_assemble(v, pi, vp.VP_SVN)
+        _, a, _ = vp.default_opts()
+        a.precision, a.variant = prec, variant
         ctx.vp_amg_setup(a)
-        z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
-        ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
+        r = torch.randn(ctx.node_shape, dtype=torch.float64, device="cuda", generator=g)
+        z = torch.zeros_like(r)
+        ctx.vp_amg_apply(r, z)
         outs.append(_host(z).ravel())
-    print(f"[pairs] prec={prec} degree={degree} max |diff| {np.abs(outs[0] - outs[1]).max():.2e} "
-          f"|z| {np.abs(outs[1]).max():.2e}", flush=True)
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    print(f"[walk4 2048] prec={prec} max |diff| {np.abs(outs[0] - outs[1]).max():.2e}", flush=True)
+    assert np.isfinite(outs[1]).all() and np.abs(outs[1]).max() > 0
     assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("degree", [2, 4])
 @pytest.mark.parametrize("prec", [1, 2, 4, 6])
-def test_lds_tail_matches_tail(vp, prec, degree, monkeypatch):
+def test_lds_tail_matches_tail(vp, prec, degree):
     """The one-workgroup tail with FP32 vectors in LDS and each node's stencil blocks
     in registers gives bitwise the V-cycle of the tail that reloads everything from
-    global memory every sweep (VP_AMG_TAIL_LDS=0)."""
-    nx, ny, seed = 200, 150, 8
-    outs = []
-    for env in ("0", "1"):
-        monkeypatch.setenv("VP_AMG_TAIL_LDS", env)
-        w, prob, ctx = _case(vp, nx, ny, seed)
-        v = _rand_v(prob, 3, 0.05)
-        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
-        rng = np.random.default_rng(7)
-        r = rng.standard_normal(2 * prob.mesh.nnode)
-        r[~prob.mesh.free_dof] = 0.0
-        n, a, k = vp.default_opts()
-        a.precision = prec
-        a.cheb_degree = degree
-        ctx.vp_amg_setup(a)
-        z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
-        ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
-        outs.append(_host(z).ravel())
-    print(f"[lds tail] prec={prec} degree={degree} max |diff| {np.abs(outs[0] - outs[1]).max():.2e}", flush=True)
-    assert np.array_equal(outs[0], outs[1])
+    global memory every sweep (VP_AMG_VAR_NO_TAIL_LDS)."""
+    ref, _ = _vcycle(vp, 200, 150, 8, prec, degree, 7, variant=vp.VP_AMG_VAR_NO_TAIL_LDS)
+    out, _ = _vcycle(vp, 200, 150, 8, prec, degree, 7)
+    print(f"[lds tail] prec={prec} degree={degree} max |diff| {np.abs(ref - out).max():.2e}", flush=True)
+    assert np.array_equal(ref, out)
 
 
 @pytest.mark.parametrize("degree", [3, 4])
-@pytest.mark.parametrize("prec", [1, 6])
-def test_coarse_paired_sweeps_match_single_sweeps(vp, prec, degree, monkeypatch):
+@pytest.mark.parametrize("prec", [1, 2, 4, 6])
+def test_coarse_paired_sweeps_match_single_sweeps(vp, prec, degree):
     """On a mesh whose first coarse level has over 10^5 nodes (961^2 -> 321^2) the
-    FP32 coarse levels smooth with paired column walks (3 x 3 blocks) too; the
-    V-cycle is bitwise the one of single sweeps on every level."""
-    nx = ny = 960
-    outs = []
-    for env in ("0", "1"):
-        monkeypatch.setenv("VP_AMG_PAIRS", env)
-        w, prob, ctx = _case(vp, nx, ny, 9)
-        v = _rand_v(prob, 3, 0.05)
-        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
-        rng = np.random.default_rng(6)
-        r = rng.standard_normal(2 * prob.mesh.nnode)
-        r[~prob.mesh.free_dof] = 0.0
-        n, a, k = vp.default_opts()
-        a.precision = prec
-        a.cheb_degree = degree
-        ctx.vp_amg_setup(a)
-        levels = ctx.vp_amg_info()
-        assert levels[1][0] * levels[1][1] >= 100000
-        z = torch.zeros(prob.mesh.nnode, 2, dtype=torch.float64, device="cuda")
-        ctx.vp_amg_apply(_dev(r.reshape(-1, 2)), z)
-        outs.append(_host(z).ravel())
-    print(f"[coarse pairs] prec={prec} degree={degree} max |diff| {np.abs(outs[0] - outs[1]).max():.2e}",
-          flush=True)
-    assert np.array_equal(outs[0], outs[1])
+    coarse levels smooth with paired sweeps too (column walks for FP32 3 x 3 blocks,
+    tiles for BF16 storage); the V-cycle is bitwise the one of single sweeps on every
+    level."""
+    ref, _ = _vcycle(vp, 960, 960, 9, prec, degree, 6, variant=vp.VP_AMG_VAR_NO_PAIRS)
+    out, ctx = _vcycle(vp, 960, 960, 9, prec, degree, 6)
+    levels = ctx.vp_amg_info()
+    assert levels[1][0] * levels[1][1] >= 100000
+    print(f"[coarse pairs] prec={prec} degree={degree} max |diff| {np.abs(ref - out).max():.2e}", flush=True)
+    assert np.array_equal(ref, out)
