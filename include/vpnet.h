@@ -82,6 +82,16 @@ int vpnet_guess(int nx, int ny, const float* net_out, int wc, int hc, const doub
 enum { VPNET_START_LEARNED = 1, VPNET_START_PREVIOUS = 2, VPNET_START_ZERO = 4 };
 int vpnet_infer(vpnet net, vp_ctx ctx, int candidates, double* v0, double* pi0, int* chosen);
 
+/* Activations of the last forward pass and their gradients from the last
+ * vpnet_backward, exposed for verification.  act 0 is the network input, act
+ * k >= 1 the (post-ReLU) output of the k-th layer in execution order (20 layers
+ * before the output head): [B][H_l][W_l][C] with H_l, W_l the layer's level size.
+ * y (device FP32, nullable) receives the stored BF16 values, g (device FP32,
+ * nullable) the gradient of the loss with respect to them; count (host, nullable)
+ * the number of entries.  VP_EINVAL for act out of range, VP_ESTATE for g before
+ * any vpnet_backward. */
+int vpnet_inspect(vpnet net, int act, float* y, float* g, int64_t* count);
+
 /* The network's matrix-core GEMM, exposed for verification: C[M][N] (FP32) =
  * op(A) op(B) with BF16 A ([M][K], or [K][M] if a_trans) and B ([K][N], or [N][K]
  * if b_trans). */

@@ -77,8 +77,9 @@ T* dalloc(size_t n) {
   return static_cast<T*>(p);
 }
 
-size_t partial_slots(size_t nn) {
-  return std::max<size_t>((size_t)kRedBlocks * (kMaxRestart + 4), 3 * (size_t)grid_for(nn) + 64);
+size_t partial_slots(vp_ctx c) {
+  const size_t red = std::max<size_t>((size_t)kRedBlocks * (kMaxRestart + 4), 3 * (size_t)grid_for(c->nn) + 64);
+  return std::max<size_t>(red, 3 * (size_t)residual_blocks(c->ec) + 64);
 }
 
 // sum the first K partial columns of nblocks workgroups into dscal[off..off+K)
@@ -510,7 +511,7 @@ int vp_create(const vp_problem_desc* desc, void* stream, vp_ctx* out) {
       c->As = dalloc<double>(c->ncell);
       c->vas = dalloc<double>(c->ndof);
       c->vps = dalloc<double>(c->ndof);
-      c->partials = dalloc<double>(partial_slots(c->nn));
+      c->partials = dalloc<double>(partial_slots(c));
       c->dscal = dalloc<double>(256);
       VP_HIP(hipHostMalloc((void**)&c->hscal, 512 * sizeof(double), hipHostMallocDefault));
       c->work = dalloc<double>(5 * c->ndof);

@@ -8,9 +8,10 @@
 //   c1 = (1 + 1/e)/2, c2 = (1 - 1/e)/2, s2e = 1/(sqrt2 e),
 // and Delta = sqrt(Delta_min^2 + 2 m(tau).m(tau)).
 //
-// Node-centred kernels gather the contributions of the (up to) four cells around
-// their node, so no two threads write the same output and results are
-// deterministic without atomics.
+// The residual and the assembly run on element patches staged in LDS (each cell's
+// Gauss points evaluated once per tile, then gathered by the nodes of the tile in
+// a fixed order), the dual update per cell; no two threads write the same output
+// and results are deterministic without atomics.
 #include "vp_internal.h"
 
 namespace vp {
@@ -191,55 +192,88 @@ void launch_precompute(vp_ctx c, const double* H, const double* A, const double*
 }
 
 // ---------------------------------------------------------------------------
+// Element patches.  A workgroup owns a tile of kTN x kTN nodes and the
+// (kTN+1) x (kTN+1) = 256 cells around them (one cell per thread).  Phase 1:
+// every thread evaluates its cell's four Gauss points once and leaves the
+// cell's element contributions in LDS (plane per value: lds[k * 256 + cell]).
+// Phase 2: every node thread sums, in a fixed order, what the (up to) four cells
+// around it hold for it and writes its outputs.  Each cell is evaluated by at
+// most four tiles at their seams (~1.14x on average) instead of by its four
+// corner nodes (4x), and the sums are deterministic without atomics.
+// Tile-local cell (cx, cy), cx, cy in [0, 16): global cell (i0 - 1 + cx, j0 - 1 + cy);
+// tile-local node (x, y), x, y in [0, kTN): global node (i0 + x, j0 + y), whose
+// cells are NE = (x+1, y+1) (node = its SW corner a=0), NW = (x, y+1) (a=1),
+// SE = (x+1, y) (a=2), SW = (x, y) (a=3).
+// ---------------------------------------------------------------------------
+constexpr int kTC = 16;            // cells per tile side
+constexpr int kTN = kTC - 1;       // nodes per tile side
+constexpr int kTCells = kTC * kTC; // = threads per workgroup
+
+inline dim3 tile_grid(const ElemConst& c) {
+  return dim3((unsigned)((c.nxn + kTN - 1) / kTN), (unsigned)((c.nyn + kTN - 1) / kTN));
+}
+
+// ---------------------------------------------------------------------------
 // residual R(v) = A(v, phi) - F(phi) (eq. A with eq. sigma) and energy Phi (eq. energy)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock)
+// Cell values in LDS: 0..7 the element vector (corner a: x at 2a, y at 2a+1) of
+// the integral terms, 8 the cell's integrated energy density.
+__global__ void __launch_bounds__(kTCells)
 k_residual(ElemConst c, const double* __restrict__ v, const double* __restrict__ dv, double alpha,
            const double* __restrict__ vo, const double* __restrict__ F,
            const double* __restrict__ P, const double* __restrict__ rhoH,
            double* __restrict__ r, double* __restrict__ partials) {
+  __shared__ double cv[9 * kTCells];
   __shared__ double lds[16 * 3];
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  double acc[3] = {0.0, 0.0, 0.0};
-  if (n < (size_t)c.nxn * c.nyn) {
-    const int i = (int)(n % c.nxn), j = (int)(n / c.nxn);
-    const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
-    double rx = 0.0, ry = 0.0, ecell = 0.0, eabs = 0.0;
-    for (int dyc = 0; dyc < 2; ++dyc)
-      for (int dxc = 0; dxc < 2; ++dxc) {
-        const int ci = i - 1 + dxc, cj = j - 1 + dyc;
-        if (ci < 0 || cj < 0 || ci >= c.nx || cj >= c.ny) continue;
-        const int a = (dxc ? 0 : 1) + (dyc ? 0 : 2);
-        const bool owner = dxc && dyc;  // this node is the cell's SW corner
-        CellVel V, O;
-        load_cell(c, v, dv, alpha, ci, cj, V);
-        load_cell(c, vo, nullptr, 0.0, ci, cj, O);
-        const size_t e = (size_t)cj * c.nx + ci;
-        const double Pc = P[e], rh = rhoH[e];
-        double en = 0.0;
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * kTN, j0 = blockIdx.y * kTN;
+  {
+    const int ci = i0 - 1 + (t % kTC), cj = j0 - 1 + (t / kTC);
+    double ev[8] = {0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
+    if (ci >= 0 && cj >= 0 && ci < c.nx && cj < c.ny) {
+      const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+      CellVel V, O;
+      load_cell(c, v, dv, alpha, ci, cj, V);
+      load_cell(c, vo, nullptr, 0.0, ci, cj, O);
+      const size_t e = (size_t)cj * c.nx + ci;
+      const double Pc = P[e], rh = rhoH[e];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const Shape s = shape_at(q, ihx, ihy);
-          const Kin k = kinematics(c, s, V);
-          // (P/Delta) tau(v):tau(phi) - (P/2) tr eps(phi), times dt
-          const double kd = c.dt * Pc / k.delta, hp = 0.5 * c.dt * Pc;
-          const double Sx = kd * (c.c1 * k.t1 + c.c2 * k.t2) - hp;
-          const double Sy = kd * (c.c2 * k.t1 + c.c1 * k.t2) - hp;
-          const double Sxy = kd * c.s2e * k.t3;
-          // mass and ocean drag: rhoH v - dt tau_ocean(v)
-          const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
-          const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
-          const double fx = rh * k.u - c.dt * c.cdo * wn * wx_;
-          const double fy = rh * k.w - c.dt * c.cdo * wn * wy_;
-          rx += c.wq * (Sx * s.gx[a] + Sxy * s.gy[a] + fx * s.N[a]);
-          ry += c.wq * (Sy * s.gy[a] + Sxy * s.gx[a] + fy * s.N[a]);
-          if (owner) {
-            en += c.wq * (0.5 * rh * (k.u * k.u + k.w * k.w) +
-                          c.dt * (0.5 * Pc * (k.delta - (k.ux + k.wy)) + c.cdo * wn * wn * wn / 3.0));
-          }
+      for (int q = 0; q < 4; ++q) {
+        const Shape s = shape_at(q, ihx, ihy);
+        const Kin k = kinematics(c, s, V);
+        // (P/Delta) tau(v):tau(phi) - (P/2) tr eps(phi), times dt
+        const double kd = c.dt * Pc / k.delta, hp = 0.5 * c.dt * Pc;
+        const double Sx = kd * (c.c1 * k.t1 + c.c2 * k.t2) - hp;
+        const double Sy = kd * (c.c2 * k.t1 + c.c1 * k.t2) - hp;
+        const double Sxy = kd * c.s2e * k.t3;
+        // mass and ocean drag: rhoH v - dt tau_ocean(v)
+        const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
+        const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
+        const double fx = rh * k.u - c.dt * c.cdo * wn * wx_;
+        const double fy = rh * k.w - c.dt * c.cdo * wn * wy_;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ev[2 * a] += c.wq * (Sx * s.gx[a] + Sxy * s.gy[a] + fx * s.N[a]);
+          ev[2 * a + 1] += c.wq * (Sy * s.gy[a] + Sxy * s.gx[a] + fy * s.N[a]);
         }
-        if (owner) { ecell += en; eabs += fabs(en); }
+        en += c.wq * (0.5 * rh * (k.u * k.u + k.w * k.w) +
+                      c.dt * (0.5 * Pc * (k.delta - (k.ux + k.wy)) + c.cdo * wn * wn * wn / 3.0));
       }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cv[k * kTCells + t] = ev[k];
+    cv[8 * kTCells + t] = en;
+  }
+  __syncthreads();
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int x = t % kTN, y = t / kTN;
+  const int i = i0 + x, j = j0 + y;
+  if (t < kTN * kTN && i < c.nxn && j < c.nyn) {
+    const int cNE = (y + 1) * kTC + x + 1, cNW = (y + 1) * kTC + x, cSE = y * kTC + x + 1, cSW = y * kTC + x;
+    // corner a of the cells NE, NW, SE, SW is 0, 1, 2, 3 (cells outside the mesh hold 0)
+    double rx = cv[0 * kTCells + cNE] + cv[2 * kTCells + cNW] + cv[4 * kTCells + cSE] + cv[6 * kTCells + cSW];
+    double ry = cv[1 * kTCells + cNE] + cv[3 * kTCells + cNW] + cv[5 * kTCells + cSE] + cv[7 * kTCells + cSW];
+    const size_t n = (size_t)j * c.nxn + i;
     const double2 Fn = reinterpret_cast<const double2*>(F)[n];
     double2 vn = reinterpret_cast<const double2*>(v)[n];
     if (dv) {
@@ -251,17 +285,25 @@ k_residual(ElemConst c, const double* __restrict__ v, const double* __restrict__
     ry -= Fn.y;
     if (is_boundary(c, i, j)) rx = ry = 0.0;
     if (r) reinterpret_cast<double2*>(r)[n] = make_double2(rx, ry);
+    // the cell whose SW corner is this node is counted here (each cell once)
+    const double ecell = cv[8 * kTCells + cNE];
     const double fv = Fn.x * vn.x + Fn.y * vn.y;
     acc[0] = rx * rx + ry * ry;
     acc[1] = ecell - fv;
-    acc[2] = eabs + fabs(fv);
+    acc[2] = fabs(ecell) + fabs(fv);
   }
   block_sum<3>(acc, lds);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x * 3 + 0] = acc[0];
-    partials[blockIdx.x * 3 + 1] = acc[1];
-    partials[blockIdx.x * 3 + 2] = acc[2];
+  if (t == 0) {
+    const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    partials[b * 3 + 0] = acc[0];
+    partials[b * 3 + 1] = acc[1];
+    partials[b * 3 + 2] = acc[2];
   }
+}
+
+unsigned residual_blocks(const ElemConst& c) {
+  const dim3 g = tile_grid(c);
+  return g.x * g.y;
 }
 
 void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, double* r,
@@ -270,11 +312,11 @@ void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, 
     launch_q2_residual(c, v, dv, alpha, r, partials, nblocks);
     return;
   }
-  const unsigned g = grid_for(c->nn);
-  hipLaunchKernelGGL(k_residual, dim3(g), dim3(kBlock), 0, c->stream, c->ec, v, dv, alpha, c->vo,
+  const dim3 g = tile_grid(c->ec);
+  hipLaunchKernelGGL(k_residual, g, dim3(kTCells), 0, c->stream, c->ec, v, dv, alpha, c->vo,
                      c->F, c->P, c->rhoH, r, partials);
   VP_LAUNCH_CHECK();
-  *nblocks = g;
+  *nblocks = g.x * g.y;
 }
 
 // ---------------------------------------------------------------------------
@@ -286,34 +328,58 @@ void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, 
 //   stdN: C = dt P/Delta [I - 2 a a^T / Delta^2]
 // and the mass/drag part is the symmetric 2x2 matrix
 //   M = rhoH I + dt C_o rho_o (|w| I + w w^T / |w|),  w = v_o - v_l.
-// The element block of nodes (a, b) is sum_q wq [B_a^T C B_b + N_a N_b M], where
-// B_a maps the two nodal dofs of node a to m(tau(N_a e_d)).
-__global__ void __launch_bounds__(kBlock)
+// The element block of corners (a, b) is sum_q wq [B_a^T C B_b + N_a N_b M], where
+// B_a maps the two nodal dofs of corner a to m(tau(N_a e_d)).  A cell keeps its
+// ten blocks with a <= b in LDS: the diagonal blocks as (xx, xy, yy) (symmetric),
+// the others as [r][c] with the rows of corner a:
+//   values  0.. 11: D0, D1, D2, D3          (diagonal blocks, 3 each)
+//   values 12.. 35: B01, B23, B02, B13, B03, B12 (4 each)
+// and the node sums self = D0(NE)+D1(NW)+D2(SE)+D3(SW), east = B01(NE)+B23(SE),
+// north = B02(NE)+B13(NW), north-east = B03(NE), north-west = B12(NW).
+namespace {
+constexpr int kB01 = 12, kB23 = 16, kB02 = 20, kB13 = 24, kB03 = 28, kB12 = 32;
+
+// acc[0..3] += wq * (B_a^T C B_b + N_a N_b M) for corner b given X = B_a^T C
+__device__ __forceinline__ void add_block(const ElemConst& c, const Shape& s, int a, int b, const double X[6],
+                                          double Mxx, double Mxy, double Myy, double* acc) {
+  const double gxb = s.gx[b], gyb = s.gy[b];
+  const double cx0 = c.c1 * gxb, cx1 = c.c2 * gxb, cx2 = c.s2e * gyb;
+  const double cy0 = c.c2 * gyb, cy1 = c.c1 * gyb, cy2 = c.s2e * gxb;
+  const double nn_ = s.N[a] * s.N[b];
+  acc[0] += c.wq * (X[0] * cx0 + X[1] * cx1 + X[2] * cx2 + nn_ * Mxx);
+  acc[1] += c.wq * (X[0] * cy0 + X[1] * cy1 + X[2] * cy2 + nn_ * Mxy);
+  acc[2] += c.wq * (X[3] * cx0 + X[4] * cx1 + X[5] * cx2 + nn_ * Mxy);
+  acc[3] += c.wq * (X[3] * cy0 + X[4] * cy1 + X[5] * cy2 + nn_ * Myy);
+}
+
+__device__ __forceinline__ void add_diag(const ElemConst& c, const Shape& s, int a, const double X[6],
+                                         double Mxx, double Mxy, double Myy, double* acc) {
+  const double gxb = s.gx[a], gyb = s.gy[a];
+  const double cx0 = c.c1 * gxb, cx1 = c.c2 * gxb, cx2 = c.s2e * gyb;
+  const double cy0 = c.c2 * gyb, cy1 = c.c1 * gyb, cy2 = c.s2e * gxb;
+  const double nn_ = s.N[a] * s.N[a];
+  acc[0] += c.wq * (X[0] * cx0 + X[1] * cx1 + X[2] * cx2 + nn_ * Mxx);
+  acc[1] += c.wq * (X[0] * cy0 + X[1] * cy1 + X[2] * cy2 + nn_ * Mxy);
+  acc[2] += c.wq * (X[3] * cy0 + X[4] * cy1 + X[5] * cy2 + nn_ * Myy);
+}
+}  // namespace
+
+__global__ void __launch_bounds__(kTCells)
 k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__ pi, int variant,
            const double* __restrict__ vo, const double* __restrict__ P,
            const double* __restrict__ rhoH, double* __restrict__ K) {
+  __shared__ double cv[36 * kTCells];
   const size_t nn = (size_t)c.nxn * c.nyn;
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
-  const int i = (int)(n % c.nxn), j = (int)(n / c.nxn);
   const size_t ncell = (size_t)c.nx * c.ny;
-  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
-  double blk[5][4];
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * kTN, j0 = blockIdx.y * kTN;
+  {
+    const int ci = i0 - 1 + (t % kTC), cj = j0 - 1 + (t / kTC);
+    double acc[36];
 #pragma unroll
-  for (int b = 0; b < 5; ++b)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) blk[b][k] = 0.0;
-
-  // the cell loops are unrolled so that every block index below is a
-  // compile-time constant and the accumulators stay in registers
-#pragma unroll
-  for (int dyc = 0; dyc < 2; ++dyc)
-#pragma unroll
-    for (int dxc = 0; dxc < 2; ++dxc) {
-      const int ci = i - 1 + dxc, cj = j - 1 + dyc;
-      if (ci < 0 || cj < 0 || ci >= c.nx || cj >= c.ny) continue;
-      const int a = (dxc ? 0 : 1) + (dyc ? 0 : 2);
-      const int ax = a & 1, ay = a >> 1;
+    for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+    if (ci >= 0 && cj >= 0 && ci < c.nx && cj < c.ny) {
+      const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
       CellVel V, O;
       load_cell(c, v, nullptr, 0.0, ci, cj, V);
       load_cell(c, vo, nullptr, 0.0, ci, cj, O);
@@ -356,38 +422,54 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
           Myy += dr * wy_ * wy_ / wn;
           Mxy = dr * wx_ * wy_ / wn;
         }
-        // X = B_a^T C (2x3), B_a columns: dof x (c1 gx, c2 gx, s2e gy), dof y (c2 gy, c1 gy, s2e gx)
-        const double gxa = s.gx[a], gya = s.gy[a];
-        const double bx0 = c.c1 * gxa, bx1 = c.c2 * gxa, bx2 = c.s2e * gya;
-        const double by0 = c.c2 * gya, by1 = c.c1 * gya, by2 = c.s2e * gxa;
-        const double X00 = bx0 * C11 + bx1 * C12 + bx2 * C13;
-        const double X01 = bx0 * C12 + bx1 * C22 + bx2 * C23;
-        const double X02 = bx0 * C13 + bx1 * C23 + bx2 * C33;
-        const double X10 = by0 * C11 + by1 * C12 + by2 * C13;
-        const double X11 = by0 * C12 + by1 * C22 + by2 * C23;
-        const double X12 = by0 * C13 + by1 * C23 + by2 * C33;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int ox = (b & 1) - ax, oy = (b >> 1) - ay;
-          int dir;
-          if (ox == 0 && oy == 0) dir = 0;
-          else if (ox == 1 && oy == 0) dir = 1;
-          else if (ox == 0 && oy == 1) dir = 2;
-          else if (ox == 1 && oy == 1) dir = 3;
-          else if (ox == -1 && oy == 1) dir = 4;
-          else continue;
-          const double gxb = s.gx[b], gyb = s.gy[b];
-          const double cx0 = c.c1 * gxb, cx1 = c.c2 * gxb, cx2 = c.s2e * gyb;
-          const double cy0 = c.c2 * gyb, cy1 = c.c1 * gyb, cy2 = c.s2e * gxb;
-          const double nn_ = s.N[a] * s.N[b];
-          blk[dir][0] += c.wq * (X00 * cx0 + X01 * cx1 + X02 * cx2 + nn_ * Mxx);
-          blk[dir][1] += c.wq * (X00 * cy0 + X01 * cy1 + X02 * cy2 + nn_ * Mxy);
-          blk[dir][2] += c.wq * (X10 * cx0 + X11 * cx1 + X12 * cx2 + nn_ * Mxy);
-          blk[dir][3] += c.wq * (X10 * cy0 + X11 * cy1 + X12 * cy2 + nn_ * Myy);
+        for (int a = 0; a < 4; ++a) {
+          // X = B_a^T C (2x3), B_a columns: dof x (c1 gx, c2 gx, s2e gy), dof y (c2 gy, c1 gy, s2e gx)
+          const double gxa = s.gx[a], gya = s.gy[a];
+          const double bx0 = c.c1 * gxa, bx1 = c.c2 * gxa, bx2 = c.s2e * gya;
+          const double by0 = c.c2 * gya, by1 = c.c1 * gya, by2 = c.s2e * gxa;
+          const double X[6] = {bx0 * C11 + bx1 * C12 + bx2 * C13, bx0 * C12 + bx1 * C22 + bx2 * C23,
+                               bx0 * C13 + bx1 * C23 + bx2 * C33, by0 * C11 + by1 * C12 + by2 * C13,
+                               by0 * C12 + by1 * C22 + by2 * C23, by0 * C13 + by1 * C23 + by2 * C33};
+          add_diag(c, s, a, X, Mxx, Mxy, Myy, acc + 3 * a);
+          if (a == 0) {
+            add_block(c, s, 0, 1, X, Mxx, Mxy, Myy, acc + kB01);
+            add_block(c, s, 0, 2, X, Mxx, Mxy, Myy, acc + kB02);
+            add_block(c, s, 0, 3, X, Mxx, Mxy, Myy, acc + kB03);
+          } else if (a == 1) {
+            add_block(c, s, 1, 3, X, Mxx, Mxy, Myy, acc + kB13);
+            add_block(c, s, 1, 2, X, Mxx, Mxy, Myy, acc + kB12);
+          } else if (a == 2) {
+            add_block(c, s, 2, 3, X, Mxx, Mxy, Myy, acc + kB23);
+          }
         }
       }
     }
+#pragma unroll
+    for (int k = 0; k < 36; ++k) cv[k * kTCells + t] = acc[k];
+  }
+  __syncthreads();
+  const int x = t % kTN, y = t / kTN;
+  const int i = i0 + x, j = j0 + y;
+  if (t >= kTN * kTN || i >= c.nxn || j >= c.nyn) return;
+  const int cNE = (y + 1) * kTC + x + 1, cNW = (y + 1) * kTC + x, cSE = y * kTC + x + 1, cSW = y * kTC + x;
+  auto at = [&](int k, int cell) { return cv[k * kTCells + cell]; };
+  double blk[5][4];
+  {
+    const double sxx = ((at(0, cNE) + at(3, cNW)) + at(6, cSE)) + at(9, cSW);
+    const double sxy = ((at(1, cNE) + at(4, cNW)) + at(7, cSE)) + at(10, cSW);
+    const double syy = ((at(2, cNE) + at(5, cNW)) + at(8, cSE)) + at(11, cSW);
+    blk[0][0] = sxx; blk[0][1] = sxy; blk[0][2] = sxy; blk[0][3] = syy;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    blk[1][k] = at(kB01 + k, cNE) + at(kB23 + k, cSE);
+    blk[2][k] = at(kB02 + k, cNE) + at(kB13 + k, cNW);
+    blk[3][k] = at(kB03 + k, cNE);
+    blk[4][k] = at(kB12 + k, cNW);
+  }
   // Dirichlet rows and columns: identity at boundary nodes, no coupling to them.
+  const size_t n = (size_t)j * c.nxn + i;
   const bool bn = is_boundary(c, i, j);
   const int nbi[5] = {i, i + 1, i, i + 1, i - 1};
   const int nbj[5] = {j, j, j + 1, j + 1, j + 1};
@@ -416,7 +498,7 @@ void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, d
     launch_q2_assemble(c, v, pi, variant);
     return;
   }
-  hipLaunchKernelGGL(k_assemble, dim3(grid_for(c->nn)), dim3(kBlock), 0, c->stream, c->ec, v, pi,
+  hipLaunchKernelGGL(k_assemble, tile_grid(c->ec), dim3(kTCells), 0, c->stream, c->ec, v, pi,
                      variant, c->vo, c->P, c->rhoH, K);
   VP_LAUNCH_CHECK();
 }

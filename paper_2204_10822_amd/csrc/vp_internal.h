@@ -282,6 +282,8 @@ void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, 
 void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, double* K);
 void launch_pi_update(vp_ctx c, const double* v, const double* dv, double* pi, double alpha);
 void launch_pi_init(vp_ctx c, const double* v, double* pi);
+// workgroups of the Q1 residual kernel (one per element-patch tile)
+unsigned residual_blocks(const ElemConst& c);
 // per-workgroup counts of invalid step data into c->partials (K = 1); returns the workgroups
 int launch_state_check(vp_ctx c, const double* H, const double* A, const double* va, const double* vo,
                        const double* vprev);

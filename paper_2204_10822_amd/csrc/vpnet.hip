@@ -237,6 +237,11 @@ __global__ void k_relu_grad(const float* __restrict__ dY, const bf16* __restrict
   }
 }
 
+__global__ void k_bf16_to_f32(const bf16* __restrict__ x, size_t n, float* __restrict__ y) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = (float)x[e];
+}
+
 // sum of two FP32 gradients (skip connection receives from two consumers)
 __global__ void k_add_into(float* __restrict__ a, const float* __restrict__ b, size_t n) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
@@ -998,6 +1003,25 @@ int vpnet_infer(vpnet_s* n, vp_ctx c, int candidates, double* v0, double* pi0, i
       launch_fill(s, pi0, 0.0, 4 * 3 * c->ncell);
     }
     if (chosen) *chosen = best;
+    return VP_OK;
+  });
+}
+
+int vpnet_inspect(vpnet_s* n, int act, float* y, float* g, int64_t* count) {
+  return nguard(n, [&] {
+    nreq(n != nullptr, "null network");
+    nreq(act >= 0 && act < (int)n->acts.size(), "activation index out of range");
+    const Act& a = n->acts[act];
+    const size_t m = (size_t)n->Bn * a.H * a.W * a.C;
+    if (count) *count = (int64_t)m;
+    if (y) {
+      hipLaunchKernelGGL(k_bf16_to_f32, dim3(gs(m)), dim3(256), 0, n->stream, a.y, m, y);
+      VP_LAUNCH_CHECK();
+    }
+    if (g) {
+      if (!a.g) throw Error(VP_ESTATE, "no gradients before vpnet_backward");
+      VP_HIP(hipMemcpyAsync(g, a.g, m * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
+    }
     return VP_OK;
   });
 }

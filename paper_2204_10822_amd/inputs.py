@@ -209,6 +209,25 @@ def advance_wind(w: Workload, t: float) -> np.ndarray:
     return vortex_wind(w.vortices, d.nx, d.ny, d.Lx, d.Ly, w.wind_max, t)
 
 
+def sequence_wind(w: Workload, k: int) -> np.ndarray:
+    """Wind of step k >= 1 of a workload's sequence: the vortices drifted for (k - 1) dt."""
+    return w.v_air if k == 1 else advance_wind(w, (k - 1) * w.desc.dt)
+
+
+def sequence_step(w: Workload, k: int, v_prev: np.ndarray) -> Workload:
+    """Step k >= 1 of a workload's sequence of implicit steps: the same thickness,
+    concentration and ocean, the vortices drifted for (k - 1) dt (so step 1 is the
+    workload itself), and the previous step's velocity as v_prev."""
+    va = sequence_wind(w, k)
+    return dataclasses.replace(w, name=f"{w.name}_step{k}", v_air=va,
+                               v_prev=np.asarray(v_prev, float).reshape(w.v_prev.shape))
+
+
+def long_run(n: int = 1024) -> Workload:
+    """1024x1024 mesh, seed 5: the 48-step (one day) workload, wind to 25 m/s."""
+    return synthetic(n, 5, (0.1, 2.0), (0.7, 1.0), 25.0, 2e-9, name=f"vp_day_{n}")
+
+
 def problem_one(n: int = 512, order: int = 1) -> Workload:
     """The paper's Problem I (Sec. 5.2): analytic A, H = 2A, constant wind
     (5, 5) m/s, no ocean current, zero Coriolis, delta_min = 2e-9.

@@ -37,7 +37,7 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_resi
 EXPORTED_NET = ["vpnet_create", "vpnet_destroy", "vpnet_last_error", "vpnet_param_count",
                 "vpnet_set_params", "vpnet_get_params", "vpnet_get_grads", "vpnet_forward",
                 "vpnet_backward", "vpnet_adam", "vpnet_train_step", "vpnet_features",
-                "vpnet_targets", "vpnet_guess", "vpnet_infer", "vpnet_gemm"]
+                "vpnet_targets", "vpnet_guess", "vpnet_infer", "vpnet_inspect", "vpnet_gemm"]
 VP_KID = dict(apply_fine=0, cheb_step0=1, sten_resid0=2, residual=3, assemble=4, vcycle=5, cheb_pair0=6,
               cheb_walk4=7)
 
@@ -129,6 +129,7 @@ def _load():
         "vpnet_targets": (I, [I, I, P, P, P, P, P]),
         "vpnet_guess": (I, [I, I, P, I, I, P, P, P, P]),
         "vpnet_infer": (I, [P, P, I, P, P, C.POINTER(I)]),
+        "vpnet_inspect": (I, [P, I, P, P, C.POINTER(C.c_int64)]),
         "vpnet_gemm": (I, [P, P, P, I, I, I, I, I, P]),
     }
     for name, (res, args) in sig.items():
@@ -456,6 +457,16 @@ class Net:
         self._check(LIB.vpnet_infer(self.h, ctx.h, mask, _ptr(v0, ctx.node_shape, "v0"),
                                     _ptr(pi0, ctx.pi_shape, "pi0"), C.byref(chosen)))
         return {v: k for k, v in START.items()}[chosen.value]
+
+    def vpnet_inspect(self, act, want_grad=True):
+        """(values, gradient) of activation `act` as flat CUDA float32 tensors."""
+        cnt = C.c_int64()
+        self._check(LIB.vpnet_inspect(self.h, int(act), None, None, C.byref(cnt)))
+        y = torch.empty(cnt.value, dtype=torch.float32, device="cuda")
+        g = torch.empty_like(y) if want_grad else None
+        self._check(LIB.vpnet_inspect(self.h, int(act), C.c_void_p(y.data_ptr()),
+                                      C.c_void_p(g.data_ptr()) if g is not None else None, None))
+        return y, g
 
     def vpnet_train_step(self, x, target, lr, want_loss=True):
         P = self.B * self.H * self.W

@@ -10,7 +10,8 @@ below the 1e-6 the tests allow.  The discrete problem has a unique minimiser
     python tests/golden/make_goldens.py [name ...]      # default: all
 
 Output: tests/golden/<name>.npz with v [(n+1)^2 * 2] float64 and the solve's
-iteration count, final relative residual and ||R(0)||.
+iteration count, final relative residual and ||R(0)||; for a step sequence the
+last step's v and every step's iteration count and residual.
 """
 from __future__ import annotations
 
@@ -41,7 +42,36 @@ def workloads():
                                                   name="vp_sharp_512")}
 
 
+SEQUENCES = {"medium_512_steps10": (lambda: inputs.medium_steps(512), 10)}
+
+
+def make_sequence(name: str) -> None:
+    """The oracle's velocity after a sequence of implicit steps (Sec. 3): step k's
+    previous velocity is the oracle's own step k-1 solution, each solve starting
+    from it; A and H stay fixed, the wind's vortices drift."""
+    mk, steps = SEQUENCES[name]
+    w0 = mk()
+    v = np.zeros(w0.v_prev.size)
+    its, rels = [], []
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        prob = O.problem_from_workload(inputs.sequence_step(w0, k, v))
+        res = O.newton_solve(prob, v0=v, tol=TOL, maxit=200, inner="direct")
+        rel = res.history[-1]["rel"]
+        print(f"[golden] {name} step {k}: converged={res.converged} its={res.iterations} rel={rel:.3e} "
+              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+        if not res.converged:
+            raise SystemExit(f"{name} step {k}: oracle did not converge ({res.status})")
+        v = res.v
+        its.append(res.iterations)
+        rels.append(rel)
+    np.savez_compressed(os.path.join(HERE, f"{name}.npz"), v=v, iterations=np.array(its),
+                        rel_resid=np.array(rels), steps=steps, tol=TOL)
+
+
 def make(name: str) -> None:
+    if name in SEQUENCES:
+        return make_sequence(name)
     w = workloads()[name]()
     prob = O.problem_from_workload(w)
     t0 = time.perf_counter()
@@ -58,5 +88,5 @@ def make(name: str) -> None:
 
 
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or list(workloads()):
+    for nm in sys.argv[1:] or list(workloads()) + list(SEQUENCES):
         make(nm)

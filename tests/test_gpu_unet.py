@@ -80,6 +80,109 @@ def test_forward_backward_parity(vp):
     assert min(coss) > 0.99
 
 
+def test_per_layer_backward_at_gemm_tolerance(vp):
+    """Each layer's backward on the GPU's own inputs: for every layer, the reference
+    (FP64, oracle/unet_ref.py) is fed the layer's BF16 input activations, BF16
+    weights and the GPU's incoming gradient (masked by the ReLU and rounded to BF16
+    as the kernels do), so no rounding difference of an earlier layer carries over.
+    Weight and bias gradients of every layer, and the gradient reaching every
+    activation (summed over its consumers), must then agree to GEMM tolerance (FP32
+    accumulation of exact BF16 products)."""
+    rng = np.random.default_rng(15)
+    B, H, W = 2, 32, 24
+    theta = U.init_params(12) + 0.02 * rng.standard_normal(U.param_count())
+    theta[U.param_count() - 5:] = 0.1 * rng.standard_normal(5)
+    x = rng.standard_normal((B, H, W, 8))
+    t = rng.standard_normal((B, H, W, 5))
+    net = vp.Net(B, H, W)
+    net.vpnet_set_params(torch.tensor(theta, dtype=torch.float32).cuda())
+    xd = torch.tensor(x.ravel(), dtype=torch.float32).cuda()
+    td = torch.tensor(t.ravel(), dtype=torch.float32).cuda()
+    out = torch.zeros(B * H * W * 5, dtype=torch.float32, device="cuda")
+    net.vpnet_forward(xd, out)
+    net.vpnet_backward(xd, td)
+    gd = torch.zeros(net.nparam, dtype=torch.float32, device="cuda")
+    net.vpnet_get_grads(gd)
+    L = U.layers()
+    names = ["x"] + [l[7] for l in L[:-1]]
+    shapes = {"x": (B, H, W, 8)}
+    for (kind, cin, cin2, cout, lev, i, i2, o) in L[:-1]:
+        shapes[o] = (B, H >> lev, W >> lev, cout)
+    acts, grads = {}, {}
+    for k, nm in enumerate(names):
+        y, g = net.vpnet_inspect(k)
+        acts[nm] = y.cpu().numpy().astype(np.float64).reshape(shapes[nm])
+        grads[nm] = g.cpu().numpy().astype(np.float64).reshape(shapes[nm])
+    out_h = out.cpu().numpy().astype(np.float64).reshape(B, H, W, 5)
+    g_all = gd.cpu().numpy().astype(np.float64)
+    th = np.asarray(theta, np.float32).astype(np.float64)    # the GPU's FP32 master weights
+    P = U.unpack(th)
+    expect = {nm: np.zeros(shapes[nm]) for nm in names}
+    off, worst = 0, 0.0
+    for li, ((kind, cin, cin2, cout, lev, i, i2, o), (Wt, bt)) in enumerate(zip(L, P)):
+        nW, nb = Wt.size, bt.size
+        X = acts[i] if i2 is None else np.concatenate([acts[i], acts[i2]], axis=-1)
+        if kind == "head":
+            gout = 2.0 * (out_h - t) / out_h.size
+            dW = X.reshape(-1, cin).T @ gout.reshape(-1, cout)
+            db = gout.reshape(-1, cout).sum(0)
+            dX = gout @ Wt.T
+        else:
+            g = U.to_bf16(grads[o] * (acts[o] > 0))
+            db = g.reshape(-1, cout).sum(0)
+            Wr = U.to_bf16(Wt)
+            if kind == "conv":
+                dX, dW = U.conv3_back(X, Wr, g)
+            elif kind == "down":
+                dX, dW = U.down_back(X, Wr, g)
+            else:
+                dX, dW = U.up_back(X, Wr, g, cout)
+        ew = _rel(g_all[off:off + nW], dW)
+        eb = _rel(g_all[off + nW:off + nW + nb], db)
+        worst = max(worst, ew, eb)
+        print(f"[unet layer {li:2d} {kind:4s}] dW {ew:.1e} db {eb:.1e}", flush=True)
+        assert ew < 2e-5 and eb < 2e-5, (li, kind, ew, eb)
+        off += nW + nb
+        if i2 is None:
+            expect[i] += dX
+        else:
+            expect[i] += dX[..., :cin]
+            expect[i2] += dX[..., cin:]
+    for nm in names[1:]:
+        e = _rel(grads[nm], expect[nm])
+        print(f"[unet act {nm}] dX {e:.1e}", flush=True)
+        assert e < 2e-5, (nm, e)
+
+
+def test_adam_step_matches_reference(vp):
+    """Two Adam steps of the library (FP32) against the reference Adam (FP64) on the
+    same gradients: the parameters agree to FP32 rounding."""
+    rng = np.random.default_rng(16)
+    B, H, W = 1, 16, 16
+    net = vp.Net(B, H, W)
+    theta = U.init_params(3)
+    net.vpnet_set_params(torch.tensor(theta, dtype=torch.float32).cuda())
+    th = np.asarray(theta, np.float32).astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for step in (1, 2):
+        x = torch.tensor(rng.standard_normal(B * H * W * 8), dtype=torch.float32).cuda()
+        t = torch.tensor(rng.standard_normal(B * H * W * 5), dtype=torch.float32).cuda()
+        net.vpnet_backward(x, t)
+        g = torch.zeros(net.nparam, dtype=torch.float32, device="cuda")
+        net.vpnet_get_grads(g)
+        net.vpnet_adam(1e-3)
+        out = torch.zeros(net.nparam, dtype=torch.float32, device="cuda")
+        net.vpnet_get_params(out)
+        gh = g.cpu().numpy().astype(np.float64)
+        th, m, v = U.adam_step(th, gh, m, v, step, 1e-3)
+        got = out.cpu().numpy().astype(np.float64)
+        err = np.abs(got - th).max()
+        print(f"[adam] step {step}: max |theta_gpu - theta_ref| {err:.2e}", flush=True)
+        assert err < 1e-6
+        th = got                          # continue from the GPU's FP32 parameters
+
+
 def test_training_reduces_loss(vp):
     rng = np.random.default_rng(6)
     B, H, W = 4, 32, 32
