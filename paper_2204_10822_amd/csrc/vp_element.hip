@@ -213,6 +213,35 @@ inline dim3 tile_grid(const ElemConst& c) {
   return dim3((unsigned)((c.nxn + kTN - 1) / kTN), (unsigned)((c.nyn + kTN - 1) / kTN));
 }
 
+// The integral terms of one cell's residual element vector (corner a: x at ev[2a],
+// y at ev[2a+1]) and its integrated energy density, by the cell's 2x2 Gauss rule.
+__device__ __forceinline__ void cell_residual(const ElemConst& c, const CellVel& V, const CellVel& O, double Pc,
+                                              double rh, double (&ev)[8], double& en) {
+  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+#pragma unroll 1   // fewer live registers (126 instead of 162), same speed or better
+  for (int q = 0; q < 4; ++q) {
+    const Shape s = shape_at(q, ihx, ihy);
+    const Kin k = kinematics(c, s, V);
+    // (P/Delta) tau(v):tau(phi) - (P/2) tr eps(phi), times dt
+    const double kd = c.dt * Pc / k.delta, hp = 0.5 * c.dt * Pc;
+    const double Sx = kd * (c.c1 * k.t1 + c.c2 * k.t2) - hp;
+    const double Sy = kd * (c.c2 * k.t1 + c.c1 * k.t2) - hp;
+    const double Sxy = kd * c.s2e * k.t3;
+    // mass and ocean drag: rhoH v - dt tau_ocean(v)
+    const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
+    const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
+    const double fx = rh * k.u - c.dt * c.cdo * wn * wx_;
+    const double fy = rh * k.w - c.dt * c.cdo * wn * wy_;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ev[2 * a] += c.wq * (Sx * s.gx[a] + Sxy * s.gy[a] + fx * s.N[a]);
+      ev[2 * a + 1] += c.wq * (Sy * s.gy[a] + Sxy * s.gx[a] + fy * s.N[a]);
+    }
+    en += c.wq * (0.5 * rh * (k.u * k.u + k.w * k.w) +
+                  c.dt * (0.5 * Pc * (k.delta - (k.ux + k.wy)) + c.cdo * wn * wn * wn / 3.0));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // residual R(v) = A(v, phi) - F(phi) (eq. A with eq. sigma) and energy Phi (eq. energy)
 // ---------------------------------------------------------------------------
@@ -231,34 +260,11 @@ k_residual(ElemConst c, const double* __restrict__ v, const double* __restrict__
     const int ci = i0 - 1 + (t % kTC), cj = j0 - 1 + (t / kTC);
     double ev[8] = {0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
     if (ci >= 0 && cj >= 0 && ci < c.nx && cj < c.ny) {
-      const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
       CellVel V, O;
       load_cell(c, v, dv, alpha, ci, cj, V);
       load_cell(c, vo, nullptr, 0.0, ci, cj, O);
       const size_t e = (size_t)cj * c.nx + ci;
-      const double Pc = P[e], rh = rhoH[e];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const Shape s = shape_at(q, ihx, ihy);
-        const Kin k = kinematics(c, s, V);
-        // (P/Delta) tau(v):tau(phi) - (P/2) tr eps(phi), times dt
-        const double kd = c.dt * Pc / k.delta, hp = 0.5 * c.dt * Pc;
-        const double Sx = kd * (c.c1 * k.t1 + c.c2 * k.t2) - hp;
-        const double Sy = kd * (c.c2 * k.t1 + c.c1 * k.t2) - hp;
-        const double Sxy = kd * c.s2e * k.t3;
-        // mass and ocean drag: rhoH v - dt tau_ocean(v)
-        const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
-        const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
-        const double fx = rh * k.u - c.dt * c.cdo * wn * wx_;
-        const double fy = rh * k.w - c.dt * c.cdo * wn * wy_;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          ev[2 * a] += c.wq * (Sx * s.gx[a] + Sxy * s.gy[a] + fx * s.N[a]);
-          ev[2 * a + 1] += c.wq * (Sy * s.gy[a] + Sxy * s.gx[a] + fy * s.N[a]);
-        }
-        en += c.wq * (0.5 * rh * (k.u * k.u + k.w * k.w) +
-                      c.dt * (0.5 * Pc * (k.delta - (k.ux + k.wy)) + c.cdo * wn * wn * wn / 3.0));
-      }
+      cell_residual(c, V, O, P[e], rhoH[e], ev, en);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) cv[k * kTCells + t] = ev[k];
@@ -301,23 +307,8 @@ k_residual(ElemConst c, const double* __restrict__ v, const double* __restrict__
   }
 }
 
-unsigned residual_blocks(const ElemConst& c) {
-  const dim3 g = tile_grid(c);
-  return g.x * g.y;
-}
 
-void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, double* r,
-                     double* partials, unsigned* nblocks) {
-  if (c->order == 2) {
-    launch_q2_residual(c, v, dv, alpha, r, partials, nblocks);
-    return;
-  }
-  const dim3 g = tile_grid(c->ec);
-  hipLaunchKernelGGL(k_residual, g, dim3(kTCells), 0, c->stream, c->ec, v, dv, alpha, c->vo,
-                     c->F, c->P, c->rhoH, r, partials);
-  VP_LAUNCH_CHECK();
-  *nblocks = g.x * g.y;
-}
+
 
 // ---------------------------------------------------------------------------
 // operator assembly (eq. linearSVNewton + eq. modification; eq. standardNewton1/2)
@@ -364,12 +355,106 @@ __device__ __forceinline__ void add_diag(const ElemConst& c, const Shape& s, int
 }
 }  // namespace
 
+// The ten upper element blocks (a <= b) of one cell in the layout described
+// above, by the cell's 2x2 Gauss rule; pi points at the cell's value of the first
+// Mandel component at the first Gauss point (planes ncell apart), unused for stdN.
+__device__ __forceinline__ void cell_blocks(const ElemConst& c, const CellVel& V, const CellVel& O, double Pc,
+                                            double rh, int variant, const double* __restrict__ pi, size_t ncell,
+                                            double (&acc)[36]) {
+  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const Shape s = shape_at(q, ihx, ihy);
+    const Kin k = kinematics(c, s, V);
+    const double d = k.delta;
+    const double base = c.dt * Pc / d;
+    double C11, C12, C13, C22, C23, C33;
+    if (variant == VP_SVN) {
+      const double p1 = pi[(size_t)(q * 3 + 0) * ncell];
+      const double p2 = pi[(size_t)(q * 3 + 1) * ncell];
+      const double p3 = kSqrt2 * pi[(size_t)(q * 3 + 2) * ncell];
+      const double sn = fmax(1.0, sqrt(2.0 * (p1 * p1 + p2 * p2 + p3 * p3)));
+      const double f = base / (d * sn);
+      C11 = base - f * 2.0 * k.t1 * p1;
+      C22 = base - f * 2.0 * k.t2 * p2;
+      C33 = base - f * 2.0 * k.t3 * p3;
+      C12 = -f * (k.t1 * p2 + p1 * k.t2);
+      C13 = -f * (k.t1 * p3 + p1 * k.t3);
+      C23 = -f * (k.t2 * p3 + p2 * k.t3);
+    } else {
+      const double f = 2.0 * base / (d * d);
+      C11 = base - f * k.t1 * k.t1;
+      C22 = base - f * k.t2 * k.t2;
+      C33 = base - f * k.t3 * k.t3;
+      C12 = -f * k.t1 * k.t2;
+      C13 = -f * k.t1 * k.t3;
+      C23 = -f * k.t2 * k.t3;
+    }
+    const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
+    const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
+    const double dr = c.dt * c.cdo;
+    double Mxx = rh + dr * wn, Myy = Mxx, Mxy = 0.0;
+    if (wn > 0.0) {
+      Mxx += dr * wx_ * wx_ / wn;
+      Myy += dr * wy_ * wy_ / wn;
+      Mxy = dr * wx_ * wy_ / wn;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      // X = B_a^T C (2x3), B_a columns: dof x (c1 gx, c2 gx, s2e gy), dof y (c2 gy, c1 gy, s2e gx)
+      const double gxa = s.gx[a], gya = s.gy[a];
+      const double bx0 = c.c1 * gxa, bx1 = c.c2 * gxa, bx2 = c.s2e * gya;
+      const double by0 = c.c2 * gya, by1 = c.c1 * gya, by2 = c.s2e * gxa;
+      const double X[6] = {bx0 * C11 + bx1 * C12 + bx2 * C13, bx0 * C12 + bx1 * C22 + bx2 * C23,
+                           bx0 * C13 + bx1 * C23 + bx2 * C33, by0 * C11 + by1 * C12 + by2 * C13,
+                           by0 * C12 + by1 * C22 + by2 * C23, by0 * C13 + by1 * C23 + by2 * C33};
+      add_diag(c, s, a, X, Mxx, Mxy, Myy, acc + 3 * a);
+      if (a == 0) {
+        add_block(c, s, 0, 1, X, Mxx, Mxy, Myy, acc + kB01);
+        add_block(c, s, 0, 2, X, Mxx, Mxy, Myy, acc + kB02);
+        add_block(c, s, 0, 3, X, Mxx, Mxy, Myy, acc + kB03);
+      } else if (a == 1) {
+        add_block(c, s, 1, 3, X, Mxx, Mxy, Myy, acc + kB13);
+        add_block(c, s, 1, 2, X, Mxx, Mxy, Myy, acc + kB12);
+      } else if (a == 2) {
+        add_block(c, s, 2, 3, X, Mxx, Mxy, Myy, acc + kB23);
+      }
+    }
+  }
+}
+
+// Write node (i, j)'s five stored blocks (self, E, N, NE, NW) with the Dirichlet
+// rows and columns: identity at boundary nodes, no coupling to them.
+__device__ __forceinline__ void store_node_blocks(const ElemConst& c, double* __restrict__ K, int i, int j,
+                                                  const double (&blk)[5][4]) {
+  const size_t nn = (size_t)c.nxn * c.nyn;
+  const size_t n = (size_t)j * c.nxn + i;
+  const bool bn = is_boundary(c, i, j);
+  const int nbi[5] = {i, i + 1, i, i + 1, i - 1};
+  const int nbj[5] = {j, j, j + 1, j + 1, j + 1};
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    bool zero;
+    if (b == 0) zero = bn;
+    else zero = bn || nbi[b] < 0 || nbi[b] > c.nx || nbj[b] > c.ny || is_boundary(c, nbi[b], nbj[b]);
+    double val[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      val[k] = zero ? 0.0 : blk[b][k];
+      if (b == 0 && bn) val[k] = (k == 0 || k == 3) ? 1.0 : 0.0;
+    }
+    // block-interleaved storage: the block's 4 values are contiguous (32 bytes)
+    double2* dst = reinterpret_cast<double2*>(K + aidx(2, nn, b, n, 0, 0));
+    dst[0] = make_double2(val[0], val[1]);
+    dst[1] = make_double2(val[2], val[3]);
+  }
+}
+
 __global__ void __launch_bounds__(kTCells)
 k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__ pi, int variant,
            const double* __restrict__ vo, const double* __restrict__ P,
            const double* __restrict__ rhoH, double* __restrict__ K) {
   __shared__ double cv[36 * kTCells];
-  const size_t nn = (size_t)c.nxn * c.nyn;
   const size_t ncell = (size_t)c.nx * c.ny;
   const int t = threadIdx.x;
   const int i0 = blockIdx.x * kTN, j0 = blockIdx.y * kTN;
@@ -379,71 +464,11 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
 #pragma unroll
     for (int k = 0; k < 36; ++k) acc[k] = 0.0;
     if (ci >= 0 && cj >= 0 && ci < c.nx && cj < c.ny) {
-      const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
       CellVel V, O;
       load_cell(c, v, nullptr, 0.0, ci, cj, V);
       load_cell(c, vo, nullptr, 0.0, ci, cj, O);
       const size_t e = (size_t)cj * c.nx + ci;
-      const double Pc = P[e], rh = rhoH[e];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const Shape s = shape_at(q, ihx, ihy);
-        const Kin k = kinematics(c, s, V);
-        const double d = k.delta;
-        const double base = c.dt * Pc / d;
-        double C11, C12, C13, C22, C23, C33;
-        if (variant == VP_SVN) {
-          const double p1 = pi[(size_t)(q * 3 + 0) * ncell + e];
-          const double p2 = pi[(size_t)(q * 3 + 1) * ncell + e];
-          const double p3 = kSqrt2 * pi[(size_t)(q * 3 + 2) * ncell + e];
-          const double sn = fmax(1.0, sqrt(2.0 * (p1 * p1 + p2 * p2 + p3 * p3)));
-          const double f = base / (d * sn);
-          C11 = base - f * 2.0 * k.t1 * p1;
-          C22 = base - f * 2.0 * k.t2 * p2;
-          C33 = base - f * 2.0 * k.t3 * p3;
-          C12 = -f * (k.t1 * p2 + p1 * k.t2);
-          C13 = -f * (k.t1 * p3 + p1 * k.t3);
-          C23 = -f * (k.t2 * p3 + p2 * k.t3);
-        } else {
-          const double f = 2.0 * base / (d * d);
-          C11 = base - f * k.t1 * k.t1;
-          C22 = base - f * k.t2 * k.t2;
-          C33 = base - f * k.t3 * k.t3;
-          C12 = -f * k.t1 * k.t2;
-          C13 = -f * k.t1 * k.t3;
-          C23 = -f * k.t2 * k.t3;
-        }
-        const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
-        const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
-        const double dr = c.dt * c.cdo;
-        double Mxx = rh + dr * wn, Myy = Mxx, Mxy = 0.0;
-        if (wn > 0.0) {
-          Mxx += dr * wx_ * wx_ / wn;
-          Myy += dr * wy_ * wy_ / wn;
-          Mxy = dr * wx_ * wy_ / wn;
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          // X = B_a^T C (2x3), B_a columns: dof x (c1 gx, c2 gx, s2e gy), dof y (c2 gy, c1 gy, s2e gx)
-          const double gxa = s.gx[a], gya = s.gy[a];
-          const double bx0 = c.c1 * gxa, bx1 = c.c2 * gxa, bx2 = c.s2e * gya;
-          const double by0 = c.c2 * gya, by1 = c.c1 * gya, by2 = c.s2e * gxa;
-          const double X[6] = {bx0 * C11 + bx1 * C12 + bx2 * C13, bx0 * C12 + bx1 * C22 + bx2 * C23,
-                               bx0 * C13 + bx1 * C23 + bx2 * C33, by0 * C11 + by1 * C12 + by2 * C13,
-                               by0 * C12 + by1 * C22 + by2 * C23, by0 * C13 + by1 * C23 + by2 * C33};
-          add_diag(c, s, a, X, Mxx, Mxy, Myy, acc + 3 * a);
-          if (a == 0) {
-            add_block(c, s, 0, 1, X, Mxx, Mxy, Myy, acc + kB01);
-            add_block(c, s, 0, 2, X, Mxx, Mxy, Myy, acc + kB02);
-            add_block(c, s, 0, 3, X, Mxx, Mxy, Myy, acc + kB03);
-          } else if (a == 1) {
-            add_block(c, s, 1, 3, X, Mxx, Mxy, Myy, acc + kB13);
-            add_block(c, s, 1, 2, X, Mxx, Mxy, Myy, acc + kB12);
-          } else if (a == 2) {
-            add_block(c, s, 2, 3, X, Mxx, Mxy, Myy, acc + kB23);
-          }
-        }
-      }
+      cell_blocks(c, V, O, P[e], rhoH[e], variant, pi + e, ncell, acc);
     }
 #pragma unroll
     for (int k = 0; k < 36; ++k) cv[k * kTCells + t] = acc[k];
@@ -468,27 +493,26 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
     blk[3][k] = at(kB03 + k, cNE);
     blk[4][k] = at(kB12 + k, cNW);
   }
-  // Dirichlet rows and columns: identity at boundary nodes, no coupling to them.
-  const size_t n = (size_t)j * c.nxn + i;
-  const bool bn = is_boundary(c, i, j);
-  const int nbi[5] = {i, i + 1, i, i + 1, i - 1};
-  const int nbj[5] = {j, j, j + 1, j + 1, j + 1};
-#pragma unroll
-  for (int b = 0; b < 5; ++b) {
-    bool zero;
-    if (b == 0) zero = bn;
-    else zero = bn || nbi[b] < 0 || nbi[b] > c.nx || nbj[b] > c.ny || is_boundary(c, nbi[b], nbj[b]);
-    double val[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      val[k] = zero ? 0.0 : blk[b][k];
-      if (b == 0 && bn) val[k] = (k == 0 || k == 3) ? 1.0 : 0.0;
-    }
-    // block-interleaved storage: the block's 4 values are contiguous (32 bytes)
-    double2* dst = reinterpret_cast<double2*>(K + aidx(2, nn, b, n, 0, 0));
-    dst[0] = make_double2(val[0], val[1]);
-    dst[1] = make_double2(val[2], val[3]);
+  store_node_blocks(c, K, i, j, blk);
+}
+
+
+void launch_residual(vp_ctx c, const double* v, const double* dv, double alpha, double* r,
+                     double* partials, unsigned* nblocks) {
+  if (c->order == 2) {
+    launch_q2_residual(c, v, dv, alpha, r, partials, nblocks);
+    return;
   }
+  const dim3 g = tile_grid(c->ec);
+  hipLaunchKernelGGL(k_residual, g, dim3(kTCells), 0, c->stream, c->ec, v, dv, alpha, c->vo,
+                     c->F, c->P, c->rhoH, r, partials);
+  VP_LAUNCH_CHECK();
+  *nblocks = g.x * g.y;
+}
+
+unsigned residual_blocks(const ElemConst& c) {
+  const dim3 g = tile_grid(c);
+  return g.x * g.y;
 }
 
 // K receives the Q1 operator; with Q2 elements the operator goes to c->K2 (the AMG
