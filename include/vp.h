@@ -143,7 +143,8 @@ typedef struct {
   int max_coarse;        /* coarsest level dof bound (<= 1024)                     */
   int precision;         /* VP_PREC_*: V-cycle arithmetic and operator storage:
                             FP64; FP32; FP32 finest + BF16 Jacobi-scaled coarse levels;
-                            BF16 Jacobi-scaled on every level (FP32 arithmetic);
+                            BF16 Jacobi-scaled on every level (FP32 arithmetic;
+                            experimental: ~4x the Krylov iterations of FP32);
                             FP16 Jacobi-scaled finest + BF16 Jacobi-scaled coarse;
                             FP16 Jacobi-scaled on every level;
                             FP16 Jacobi-scaled finest smoothing with the residual

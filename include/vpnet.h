@@ -76,10 +76,16 @@ int vpnet_guess(int nx, int ny, const float* net_out, int wc, int hc, const doub
  * the learned start; the previous-step velocity v_prev with pi = tau/Delta (eq. pi);
  * or zero.  Ties go to the earlier of learned, previous, zero.  chosen (host,
  * nullable) receives the chosen flag.  Newton always finishes the solve.
- * Needs a batch-1 network, a Q1 context and one stream for both.  Synchronises.
- * VP_EINVAL for null pointers, an empty candidate set or mismatched sizes;
- * VP_ESTATE before vp_set_state; VP_ENONFINITE if an energy is not finite. */
+ * Needs a batch-1 network, a Q1 context and one stream for both.  On meshes more
+ * than VPNET_MAX_POOL times the network's grid per side the learned start is not
+ * a candidate (box-averaged this far, its proposal misses the fine-scale
+ * deformation and costs Newton iterations; measured: 36 -> 50 iterations at
+ * 2048^2 with a 256^2 network); the network is then not run.  Synchronises.
+ * VP_EINVAL for null pointers, an empty candidate set, mismatched sizes or the
+ * learned start alone on too fine a mesh; VP_ESTATE before vp_set_state;
+ * VP_ENONFINITE if an energy is not finite. */
 enum { VPNET_START_LEARNED = 1, VPNET_START_PREVIOUS = 2, VPNET_START_ZERO = 4 };
+enum { VPNET_MAX_POOL = 4 };
 int vpnet_infer(vpnet net, vp_ctx ctx, int candidates, double* v0, double* pi0, int* chosen);
 
 /* Activations of the last forward pass and their gradients from the last

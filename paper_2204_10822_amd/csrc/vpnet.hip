@@ -950,6 +950,8 @@ int vpnet_guess(int nx, int ny, const float* outp, int wc, int hc, const double*
   return hipGetLastError() == hipSuccess ? VP_OK : VP_EHIP;
 }
 
+constexpr int kMaxPool = VPNET_MAX_POOL;
+
 int vpnet_infer(vpnet_s* n, vp_ctx c, int candidates, double* v0, double* pi0, int* chosen) {
   return nguard(n, [&] {
     nreq(n && c && v0 && pi0, "null argument");
@@ -963,6 +965,12 @@ int vpnet_infer(vpnet_s* n, vp_ctx c, int candidates, double* v0, double* pi0, i
          "the mesh must be f times the network's grid on both sides (integer f)");
     if (!c->have_state) throw Error(VP_ESTATE, "vp_set_state not called");
     const int f = nx / n->W;
+    if (f > kMaxPool) {
+      // pooled this far the proposal misses the fine-scale deformation and slows
+      // Newton down: the learned start is not a candidate on such meshes
+      nreq(candidates != VPNET_START_LEARNED, "mesh finer than the network's grid times VPNET_MAX_POOL");
+      candidates &= ~VPNET_START_LEARNED;
+    }
     const size_t P = (size_t)n->H * n->W;
     if (!n->feat) n->feat = dalloc<float>(P * kCin);
     hipStream_t s = n->stream;

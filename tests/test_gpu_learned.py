@@ -85,6 +85,15 @@ def test_infer_pools_larger_meshes_and_rejects_others(vp, ws):
     p0 = torch.empty(ctx.pi_shape, dtype=torch.float64, device="cuda")
     assert ws.start(ctx, v0, p0, ("learned",)) == "learned"
     assert bool(torch.isfinite(v0).all()) and bool(torch.isfinite(p0).all())
+    # more than 4x the network's grid per side: the learned start is no candidate
+    fine = vp.context_for(W.sample_workload(90102, 1280))
+    vf = torch.full(fine.node_shape, 7.0, dtype=torch.float64, device="cuda")
+    pf = torch.full(fine.pi_shape, 7.0, dtype=torch.float64, device="cuda")
+    assert ws.start(fine, vf, pf, ("learned", "zero")) == "zero"
+    assert torch.count_nonzero(vf) == 0 and torch.count_nonzero(pf) == 0
+    with pytest.raises(vp.VPError) as e:
+        ws.start(fine, vf, pf, ("learned",))
+    assert e.value.code == vp.VP_EINVAL
     bad = vp.context_for(inputs.synthetic(300, 5))
     vb = torch.empty(bad.node_shape, dtype=torch.float64, device="cuda")
     pb = torch.empty(bad.pi_shape, dtype=torch.float64, device="cuda")
