@@ -495,6 +495,7 @@ int vp_create(const vp_problem_desc* desc, void* stream, vp_ctx* out) {
       e.nx = desc->nx; e.ny = desc->ny;
       e.nxn = c->order * desc->nx + 1; e.nyn = c->order * desc->ny + 1;
       e.hx = desc->Lx / desc->nx; e.hy = desc->Ly / desc->ny; e.wq = 0.25 * e.hx * e.hy;
+      e.ihx = 1.0 / e.hx; e.ihy = 1.0 / e.hy;
       e.dt = desc->dt; e.dmin2 = desc->delta_min * desc->delta_min;
       e.c1 = 0.5 * (1.0 + 1.0 / desc->e_ratio); e.c2 = 0.5 * (1.0 - 1.0 / desc->e_ratio);
       e.s2e = 1.0 / (std::sqrt(2.0) * desc->e_ratio);

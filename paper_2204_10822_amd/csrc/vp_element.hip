@@ -59,11 +59,24 @@ __device__ __forceinline__ void load_cell(const ElemConst& c, const double* __re
   }
 }
 
+// 1/sqrt(x) for a positive, normal x: the hardware estimate refined by two steps of
+// Newton's method for f(y) = 1/y^2 - x (y <- y (3 - x y^2) / 2, each step squaring
+// the relative error), so the result is within a few ulp.  Replaces a square root
+// and a division (each a multi-instruction sequence in FP64) where both are needed.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
 struct Kin {
   double u, w;       // velocity at the point
   double ux, uy, wx, wy;
   double t1, t2, t3; // m(tau(v))
-  double delta;
+  double delta;      // Delta = sqrt(Delta_min^2 + 2 m(tau).m(tau))
+  double idelta;     // 1 / Delta
 };
 
 __device__ __forceinline__ Kin kinematics(const ElemConst& c, const Shape& s, const CellVel& v) {
@@ -81,8 +94,17 @@ __device__ __forceinline__ Kin kinematics(const ElemConst& c, const Shape& s, co
   k.t1 = c.c1 * k.ux + c.c2 * k.wy;
   k.t2 = c.c2 * k.ux + c.c1 * k.wy;
   k.t3 = c.s2e * (k.uy + k.wx);
-  k.delta = sqrt(c.dmin2 + 2.0 * (k.t1 * k.t1 + k.t2 * k.t2 + k.t3 * k.t3));
+  const double d2 = c.dmin2 + 2.0 * (k.t1 * k.t1 + k.t2 * k.t2 + k.t3 * k.t3);
+  k.idelta = rsqrt_nr(d2);   // d2 >= Delta_min^2 > 0
+  k.delta = d2 * k.idelta;
   return k;
+}
+
+// |w| and 1/|w| (0 and 0 for w = 0)
+__device__ __forceinline__ void norm_inv(double wx, double wy, double& n, double& in) {
+  const double n2 = wx * wx + wy * wy;
+  in = n2 > 0.0 ? rsqrt_nr(n2) : 0.0;
+  n = n2 * in;
 }
 
 __device__ __forceinline__ double interp(const Shape& s, const double f[4]) {
@@ -113,7 +135,7 @@ __global__ void k_load_vector(ElemConst c, const double* __restrict__ rhoH,
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
   if (n >= (size_t)c.nxn * c.nyn) return;
   const int i = (int)(n % c.nxn), j = (int)(n / c.nxn);
-  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  const double ihx = c.ihx, ihy = c.ihy;
   double fx = 0.0, fy = 0.0;
   for (int dyc = 0; dyc < 2; ++dyc)
     for (int dxc = 0; dxc < 2; ++dxc) {
@@ -217,19 +239,20 @@ inline dim3 tile_grid(const ElemConst& c) {
 // y at ev[2a+1]) and its integrated energy density, by the cell's 2x2 Gauss rule.
 __device__ __forceinline__ void cell_residual(const ElemConst& c, const CellVel& V, const CellVel& O, double Pc,
                                               double rh, double (&ev)[8], double& en) {
-  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  const double ihx = c.ihx, ihy = c.ihy;
 #pragma unroll 1   // fewer live registers (126 instead of 162), same speed or better
   for (int q = 0; q < 4; ++q) {
     const Shape s = shape_at(q, ihx, ihy);
     const Kin k = kinematics(c, s, V);
     // (P/Delta) tau(v):tau(phi) - (P/2) tr eps(phi), times dt
-    const double kd = c.dt * Pc / k.delta, hp = 0.5 * c.dt * Pc;
+    const double kd = c.dt * Pc * k.idelta, hp = 0.5 * c.dt * Pc;
     const double Sx = kd * (c.c1 * k.t1 + c.c2 * k.t2) - hp;
     const double Sy = kd * (c.c2 * k.t1 + c.c1 * k.t2) - hp;
     const double Sxy = kd * c.s2e * k.t3;
     // mass and ocean drag: rhoH v - dt tau_ocean(v)
     const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
-    const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
+    double wn, iwn;
+    norm_inv(wx_, wy_, wn, iwn);
     const double fx = rh * k.u - c.dt * c.cdo * wn * wx_;
     const double fy = rh * k.w - c.dt * c.cdo * wn * wy_;
 #pragma unroll
@@ -238,7 +261,7 @@ __device__ __forceinline__ void cell_residual(const ElemConst& c, const CellVel&
       ev[2 * a + 1] += c.wq * (Sy * s.gy[a] + Sxy * s.gx[a] + fy * s.N[a]);
     }
     en += c.wq * (0.5 * rh * (k.u * k.u + k.w * k.w) +
-                  c.dt * (0.5 * Pc * (k.delta - (k.ux + k.wy)) + c.cdo * wn * wn * wn / 3.0));
+                  c.dt * (0.5 * Pc * (k.delta - (k.ux + k.wy)) + c.cdo * wn * wn * wn * (1.0 / 3.0)));
   }
 }
 
@@ -330,17 +353,18 @@ k_residual(ElemConst c, const double* __restrict__ v, const double* __restrict__
 namespace {
 constexpr int kB01 = 12, kB23 = 16, kB02 = 20, kB13 = 24, kB03 = 28, kB12 = 32;
 
-// acc[0..3] += wq * (B_a^T C B_b + N_a N_b M) for corner b given X = B_a^T C
+// acc[0..3] += B_a^T C B_b + N_a N_b M for corner b given X = B_a^T C (C and M
+// already carry the Gauss weight)
 __device__ __forceinline__ void add_block(const ElemConst& c, const Shape& s, int a, int b, const double X[6],
                                           double Mxx, double Mxy, double Myy, double* acc) {
   const double gxb = s.gx[b], gyb = s.gy[b];
   const double cx0 = c.c1 * gxb, cx1 = c.c2 * gxb, cx2 = c.s2e * gyb;
   const double cy0 = c.c2 * gyb, cy1 = c.c1 * gyb, cy2 = c.s2e * gxb;
   const double nn_ = s.N[a] * s.N[b];
-  acc[0] += c.wq * (X[0] * cx0 + X[1] * cx1 + X[2] * cx2 + nn_ * Mxx);
-  acc[1] += c.wq * (X[0] * cy0 + X[1] * cy1 + X[2] * cy2 + nn_ * Mxy);
-  acc[2] += c.wq * (X[3] * cx0 + X[4] * cx1 + X[5] * cx2 + nn_ * Mxy);
-  acc[3] += c.wq * (X[3] * cy0 + X[4] * cy1 + X[5] * cy2 + nn_ * Myy);
+  acc[0] += X[0] * cx0 + X[1] * cx1 + X[2] * cx2 + nn_ * Mxx;
+  acc[1] += X[0] * cy0 + X[1] * cy1 + X[2] * cy2 + nn_ * Mxy;
+  acc[2] += X[3] * cx0 + X[4] * cx1 + X[5] * cx2 + nn_ * Mxy;
+  acc[3] += X[3] * cy0 + X[4] * cy1 + X[5] * cy2 + nn_ * Myy;
 }
 
 __device__ __forceinline__ void add_diag(const ElemConst& c, const Shape& s, int a, const double X[6],
@@ -349,9 +373,9 @@ __device__ __forceinline__ void add_diag(const ElemConst& c, const Shape& s, int
   const double cx0 = c.c1 * gxb, cx1 = c.c2 * gxb, cx2 = c.s2e * gyb;
   const double cy0 = c.c2 * gyb, cy1 = c.c1 * gyb, cy2 = c.s2e * gxb;
   const double nn_ = s.N[a] * s.N[a];
-  acc[0] += c.wq * (X[0] * cx0 + X[1] * cx1 + X[2] * cx2 + nn_ * Mxx);
-  acc[1] += c.wq * (X[0] * cy0 + X[1] * cy1 + X[2] * cy2 + nn_ * Mxy);
-  acc[2] += c.wq * (X[3] * cy0 + X[4] * cy1 + X[5] * cy2 + nn_ * Myy);
+  acc[0] += X[0] * cx0 + X[1] * cx1 + X[2] * cx2 + nn_ * Mxx;
+  acc[1] += X[0] * cy0 + X[1] * cy1 + X[2] * cy2 + nn_ * Mxy;
+  acc[2] += X[3] * cy0 + X[4] * cy1 + X[5] * cy2 + nn_ * Myy;
 }
 }  // namespace
 
@@ -361,20 +385,21 @@ __device__ __forceinline__ void add_diag(const ElemConst& c, const Shape& s, int
 __device__ __forceinline__ void cell_blocks(const ElemConst& c, const CellVel& V, const CellVel& O, double Pc,
                                             double rh, int variant, const double* __restrict__ pi, size_t ncell,
                                             double (&acc)[36]) {
-  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  const double ihx = c.ihx, ihy = c.ihy;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const Shape s = shape_at(q, ihx, ihy);
     const Kin k = kinematics(c, s, V);
-    const double d = k.delta;
-    const double base = c.dt * Pc / d;
+    // C and M carry the Gauss weight wq
+    const double base = c.wq * c.dt * Pc * k.idelta;
     double C11, C12, C13, C22, C23, C33;
     if (variant == VP_SVN) {
       const double p1 = pi[(size_t)(q * 3 + 0) * ncell];
       const double p2 = pi[(size_t)(q * 3 + 1) * ncell];
       const double p3 = kSqrt2 * pi[(size_t)(q * 3 + 2) * ncell];
-      const double sn = fmax(1.0, sqrt(2.0 * (p1 * p1 + p2 * p2 + p3 * p3)));
-      const double f = base / (d * sn);
+      const double s2 = 2.0 * (p1 * p1 + p2 * p2 + p3 * p3);
+      const double isn = s2 > 1.0 ? rsqrt_nr(s2) : 1.0;   // 1 / max(1, sqrt(2 p.p))
+      const double f = base * k.idelta * isn;
       C11 = base - f * 2.0 * k.t1 * p1;
       C22 = base - f * 2.0 * k.t2 * p2;
       C33 = base - f * 2.0 * k.t3 * p3;
@@ -382,7 +407,7 @@ __device__ __forceinline__ void cell_blocks(const ElemConst& c, const CellVel& V
       C13 = -f * (k.t1 * p3 + p1 * k.t3);
       C23 = -f * (k.t2 * p3 + p2 * k.t3);
     } else {
-      const double f = 2.0 * base / (d * d);
+      const double f = 2.0 * base * k.idelta * k.idelta;
       C11 = base - f * k.t1 * k.t1;
       C22 = base - f * k.t2 * k.t2;
       C33 = base - f * k.t3 * k.t3;
@@ -391,14 +416,12 @@ __device__ __forceinline__ void cell_blocks(const ElemConst& c, const CellVel& V
       C23 = -f * k.t2 * k.t3;
     }
     const double wx_ = interp(s, O.x) - k.u, wy_ = interp(s, O.y) - k.w;
-    const double wn = sqrt(wx_ * wx_ + wy_ * wy_);
-    const double dr = c.dt * c.cdo;
-    double Mxx = rh + dr * wn, Myy = Mxx, Mxy = 0.0;
-    if (wn > 0.0) {
-      Mxx += dr * wx_ * wx_ / wn;
-      Myy += dr * wy_ * wy_ / wn;
-      Mxy = dr * wx_ * wy_ / wn;
-    }
+    double wn, iwn;
+    norm_inv(wx_, wy_, wn, iwn);   // iwn = 0 for w = 0: the rank-one term vanishes
+    const double dr = c.wq * c.dt * c.cdo;
+    const double Mxx = c.wq * rh + dr * wn + dr * wx_ * wx_ * iwn;
+    const double Myy = c.wq * rh + dr * wn + dr * wy_ * wy_ * iwn;
+    const double Mxy = dr * wx_ * wy_ * iwn;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       // X = B_a^T C (2x3), B_a columns: dof x (c1 gx, c2 gx, s2e gy), dof y (c2 gy, c1 gy, s2e gx)
@@ -450,16 +473,18 @@ __device__ __forceinline__ void store_node_blocks(const ElemConst& c, double* __
   }
 }
 
-__global__ void __launch_bounds__(kTCells)
+template <int TCX, int TCY>
+__global__ void __launch_bounds__(TCX * TCY)
 k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__ pi, int variant,
            const double* __restrict__ vo, const double* __restrict__ P,
            const double* __restrict__ rhoH, double* __restrict__ K) {
-  __shared__ double cv[36 * kTCells];
+  constexpr int NT = TCX * TCY, NX = TCX - 1, NY = TCY - 1;   // threads = cells; nodes NX x NY
+  __shared__ double cv[36 * NT];
   const size_t ncell = (size_t)c.nx * c.ny;
   const int t = threadIdx.x;
-  const int i0 = blockIdx.x * kTN, j0 = blockIdx.y * kTN;
+  const int i0 = blockIdx.x * NX, j0 = blockIdx.y * NY;
   {
-    const int ci = i0 - 1 + (t % kTC), cj = j0 - 1 + (t / kTC);
+    const int ci = i0 - 1 + (t % TCX), cj = j0 - 1 + (t / TCX);
     double acc[36];
 #pragma unroll
     for (int k = 0; k < 36; ++k) acc[k] = 0.0;
@@ -471,14 +496,14 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
       cell_blocks(c, V, O, P[e], rhoH[e], variant, pi + e, ncell, acc);
     }
 #pragma unroll
-    for (int k = 0; k < 36; ++k) cv[k * kTCells + t] = acc[k];
+    for (int k = 0; k < 36; ++k) cv[k * NT + t] = acc[k];
   }
   __syncthreads();
-  const int x = t % kTN, y = t / kTN;
+  const int x = t % NX, y = t / NX;
   const int i = i0 + x, j = j0 + y;
-  if (t >= kTN * kTN || i >= c.nxn || j >= c.nyn) return;
-  const int cNE = (y + 1) * kTC + x + 1, cNW = (y + 1) * kTC + x, cSE = y * kTC + x + 1, cSW = y * kTC + x;
-  auto at = [&](int k, int cell) { return cv[k * kTCells + cell]; };
+  if (t >= NX * NY || i >= c.nxn || j >= c.nyn) return;
+  const int cNE = (y + 1) * TCX + x + 1, cNW = (y + 1) * TCX + x, cSE = y * TCX + x + 1, cSW = y * TCX + x;
+  auto at = [&](int k, int cell) { return cv[k * NT + cell]; };
   double blk[5][4];
   {
     const double sxx = ((at(0, cNE) + at(3, cNW)) + at(6, cSE)) + at(9, cSW);
@@ -522,8 +547,10 @@ void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, d
     launch_q2_assemble(c, v, pi, variant);
     return;
   }
-  hipLaunchKernelGGL(k_assemble, tile_grid(c->ec), dim3(kTCells), 0, c->stream, c->ec, v, pi,
-                     variant, c->vo, c->P, c->rhoH, K);
+  constexpr int TX = kTC, TY = kTC;   // 8-row tiles measured no faster, 4-row tiles slower
+  const dim3 g((unsigned)((c->ec.nxn + TX - 2) / (TX - 1)), (unsigned)((c->ec.nyn + TY - 2) / (TY - 1)));
+  hipLaunchKernelGGL((k_assemble<TX, TY>), g, dim3(TX * TY), 0, c->stream, c->ec, v, pi, variant, c->vo, c->P,
+                     c->rhoH, K);
   VP_LAUNCH_CHECK();
 }
 
@@ -537,7 +564,7 @@ __global__ void k_pi_update(ElemConst c, const double* __restrict__ v, const dou
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ncell) return;
   const int ci = (int)(e % c.nx), cj = (int)(e / c.nx);
-  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  const double ihx = c.ihx, ihy = c.ihy;
   CellVel V, D;
   load_cell(c, v, nullptr, 0.0, ci, cj, V);
   load_cell(c, dv, nullptr, 0.0, ci, cj, D);
@@ -549,7 +576,7 @@ __global__ void k_pi_update(ElemConst c, const double* __restrict__ v, const dou
     double* pq = pi + (size_t)(q * 3) * ncell + e;
     const double p1 = pq[0], p2 = pq[ncell], p3 = kSqrt2 * pq[2 * ncell];
     const double sn = fmax(1.0, sqrt(2.0 * (p1 * p1 + p2 * p2 + p3 * p3)));
-    const double id = 1.0 / k.delta;
+    const double id = k.idelta;
     const double at = k.t1 * kd.t1 + k.t2 * kd.t2 + k.t3 * kd.t3;
     const double pt = p1 * kd.t1 + p2 * kd.t2 + p3 * kd.t3;
     const double g = id * id / sn;
@@ -567,14 +594,14 @@ __global__ void k_pi_init(ElemConst c, const double* __restrict__ v, double* __r
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ncell) return;
   const int ci = (int)(e % c.nx), cj = (int)(e / c.nx);
-  const double ihx = 1.0 / c.hx, ihy = 1.0 / c.hy;
+  const double ihx = c.ihx, ihy = c.ihy;
   CellVel V;
   load_cell(c, v, nullptr, 0.0, ci, cj, V);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const Shape s = shape_at(q, ihx, ihy);
     const Kin k = kinematics(c, s, V);
-    const double id = 1.0 / k.delta;
+    const double id = k.idelta;
     double* pq = pi + (size_t)(q * 3) * ncell + e;
     pq[0] = k.t1 * id;
     pq[ncell] = k.t2 * id;

@@ -135,6 +135,7 @@ struct ElemConst {
   double c1, c2, s2e;            // tau map: c1 = (1+1/e)/2, c2 = (1-1/e)/2, s2e = 1/(sqrt2 e)
   double rho_ice, cdo, cda, fc;  // rho_ice, C_o rho_o, C_a rho_a, f_c
   double P_star, C_strength;
+  double ihx, ihy;               // 1/hx, 1/hy
 };
 
 // ---------------------------------------------------------------------------
