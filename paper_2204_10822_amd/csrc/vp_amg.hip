@@ -1147,7 +1147,8 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
   Rw Wn = wrow(A, nn, nxn, nyn, ic, j0 - 4);
   Vc bn = wvec(b, nxn, nyn, ic, j0 - 4), xn = zv;
   if constexpr (KIND == W4_POST) xn = wvec(xin, nxn, nyn, ic, j0 - 4);
-  for (int R = j0 - 4; R <= Rend; ++R) {   // R is uniform across the wave
+  // One row step; the shifts at its end rotate the register window.
+  auto row = [&] __device__ (const int R) {
     const Rw W0 = Wn;
     const Vc bR = bn, xR = xn;
     Wn = wrow(A, nn, nxn, nyn, ic, R + 1);
@@ -1178,7 +1179,7 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
           {
             // the paired kernels add this step to x in their next sweep, to the
             // rounded product: no contraction into a fused multiply-add here
-#pragma clang fp contract(off)
+  #pragma clang fp contract(off)
             x1 = Vc{uC1.x + d1.x, uC1.y + d1.y};
           }
         }
@@ -1240,7 +1241,21 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
     uS4 = uC4; uC4 = d3; uS3 = uC3; uC3 = d2; uS2 = uC2; uC2 = d1; uS1 = uC1; uC1 = u0;
     rc4 = r3; rc3 = r2; rc2 = r1; rc1 = bR;
     xc4 = x3; xc3 = x2; xc2 = x1;
+  };
+  // Seven steps at a time (the window holds seven rows: the prefetched one, the
+  // current one and five below): after inlining, most of the rotation becomes a
+  // renaming of registers instead of copies.  R is uniform across the wave.
+  int R = j0 - 4;
+  for (; R + 6 <= Rend; R += 7) {
+    row(R);
+    row(R + 1);
+    row(R + 2);
+    row(R + 3);
+    row(R + 4);
+    row(R + 5);
+    row(R + 6);
   }
+  for (; R <= Rend; ++R) row(R);
 }
 
 // Paired sweeps by column walks on the structured coarse levels (3 x 3 blocks, FP32
