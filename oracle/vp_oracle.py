@@ -471,7 +471,9 @@ def line_search_accept(phi_new, phi_old, floor, rn_new, rn_old):
 
 def eisenstat_walker(rn, rn_prev, eta_prev, tol_abs, eta_max=0.1, gamma=0.9):
     """Inner relative tolerance: Eisenstat-Walker choice 2 with safeguard, capped at
-    eta_max and floored at 0.1 * (target residual) / (current residual)."""
+    eta_max and floored at 0.5 * (target residual) / (current residual), Kelley's
+    safeguard against oversolving the last linear system (the paper leaves the
+    inner tolerance open)."""
     if rn_prev is None:
         eta = eta_max
     else:
@@ -479,7 +481,7 @@ def eisenstat_walker(rn, rn_prev, eta_prev, tol_abs, eta_max=0.1, gamma=0.9):
         sg = gamma * eta_prev ** 2
         if sg > 0.1:
             eta = max(eta, sg)
-    eta = max(eta, 0.1 * tol_abs / rn)
+    eta = max(eta, 0.5 * tol_abs / rn)
     return min(eta, eta_max)
 
 

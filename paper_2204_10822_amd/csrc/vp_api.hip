@@ -379,7 +379,9 @@ double ew_eta(vp_ctx c, double rn, double tol_abs, double eta_max) {
     const double sg = 0.9 * c->ew_eta_prev * c->ew_eta_prev;
     if (sg > 0.1) eta = std::max(eta, sg);
   }
-  eta = std::max(eta, 0.1 * tol_abs / rn);
+  // no oversolving near the end: a linear residual of half the distance to the
+  // Newton tolerance is enough (Kelley's safeguard of the Eisenstat-Walker choice)
+  eta = std::max(eta, 0.5 * tol_abs / rn);
   return std::min(eta, eta_max);
 }
 
