@@ -43,6 +43,23 @@ __device__ __forceinline__ int slot1(int i, int n, int nagg, int J) {
   return -1;
 }
 
+// Aggregate-major order of the fine nodes for the Galerkin scratch W: the nodes at
+// position (px, py) < 3 inside their aggregate form one plane indexed like the
+// coarse nodes, so the threads of consecutive coarse nodes read consecutive
+// addresses; the extra nodes of a last aggregate longer than three (at most two
+// columns and two rows, nxn - 3 ncx and nyn - 3 ncy) follow the nine planes.
+__host__ __device__ __forceinline__ size_t gw_size(int nxn, int nyn, int ncx, int ncy) {
+  return (size_t)9 * ncx * ncy + (size_t)(nxn - 3 * ncx) * nyn + (size_t)(nyn - 3 * ncy) * nxn;
+}
+__device__ __forceinline__ size_t gw_index(int i, int j, int nxn, int nyn, int ncx, int ncy) {
+  const int ax = agg_of(i, ncx), ay = agg_of(j, ncy);
+  const int px = i - 3 * ax, py = j - 3 * ay;
+  const size_t ncn = (size_t)ncx * ncy;
+  if (px < 3 && py < 3) return (size_t)(py * 3 + px) * ncn + (size_t)ay * ncx + ax;
+  if (px >= 3) return 9 * ncn + (size_t)(px - 3) * nyn + j;
+  return 9 * ncn + (size_t)(nxn - 3 * ncx) * nyn + (size_t)(py - 3) * nxn + i;
+}
+
 // ---- block access ------------------------------------------------------------
 // 9 directions: 0 self, 1 E, 2 N, 3 NE, 4 NW, 5 W, 6 S, 7 SW, 8 SE
 __constant__ int kDI[9] = {0, 1, 0, 1, -1, -1, 0, -1, 1};
@@ -2072,16 +2089,13 @@ k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
 // Pass 1 (one thread per fine node i): W(i, J) = sum_k A(i,k) P(k,J) for the
 // coarse nodes J = agg(i) + (qx-1, qy-1), q = qy*3 + qx in 0..8 (A P vanishes for
 // every other J: the prolongator columns of k's neighbours reach at most one
-// aggregate further).  W[((q*B + r)*3 + c)*nn + i], zero where J is absent.
+// aggregate further).  W[((q*B + r)*3 + c)*nw + gw_index(i)], nw = gw_size, zero
+// where J is absent.
 template <int B>
-__global__ void __launch_bounds__(kBlock)
-k_galerkin_ap(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
-              const double* __restrict__ P, double* __restrict__ W) {
-  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
-  const int i = (int)(n % nxn), j = (int)(n / nxn);
+__device__ __forceinline__ void galerkin_ap_compute(const double* __restrict__ A, size_t nn, int nxn, int nyn,
+                                                    int ncx, int ncy, const double* __restrict__ P, int i, int j,
+                                                    double (&w)[9][B][3]) {
   const int ax = agg_of(i, ncx), ay = agg_of(j, ncy);
-  double w[9][B][3];
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
@@ -2115,26 +2129,52 @@ k_galerkin_ap(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx
       }
     }
   }
+}
+
+// One thread per fine node in row order (coalesced loads of A and P); the stores
+// follow the aggregate-major order of W, three runs of consecutive addresses per
+// wave.  Measured against the alternatives at 2049^2: threads in the order of W
+// (loads three nodes apart) and a row-order tile transposed through LDS before the
+// stores were both slower.
+template <int B>
+__global__ void __launch_bounds__(kBlock)
+k_galerkin_ap(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
+              const double* __restrict__ P, double* __restrict__ W) {
+  const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % nxn), j = (int)(n / nxn);
+  double w[9][B][3];
+  galerkin_ap_compute<B>(A, nn, nxn, nyn, ncx, ncy, P, i, j, w);
+  const size_t nw = gw_size(nxn, nyn, ncx, ncy), gi = gw_index(i, j, nxn, nyn, ncx, ncy);
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) W[(size_t)((q * B + r) * 3 + c) * nn + n] = w[q][r][c];
+      for (int c = 0; c < 3; ++c) W[(size_t)((q * B + r) * 3 + c) * nw + gi] = w[q][r][c];
 }
 
 // Pass 2 (one thread per coarse node I): Ac(I, J_t) = sum over the fine nodes i of
 // I's prolongator support of P(i,I)^T W(i, J_t) for the 5 stored targets
 // J_t = I + {(0,0), (1,0), (0,1), (1,1), (-1,1)}; the diagonal block is
-// symmetrised and empty coarse dofs get a unit diagonal.
+// symmetrised and empty coarse dofs get a unit diagonal.  A workgroup takes a tile
+// of kPtwTX x kPtwTY coarse nodes (a wave per tile row), so the fine rows that
+// vertically adjacent coarse nodes share are read from L2 within the workgroup;
+// tiles are dealt to the XCDs in contiguous runs (xcd_block), so a tile's
+// neighbours above and below mostly share its L2 too.
+constexpr int kPtwTX = 64, kPtwTY = 4;
 template <int B>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kPtwTX * kPtwTY)
 k_galerkin_ptw(const double* __restrict__ P, const double* __restrict__ W, size_t nn, int nxn, int nyn,
                int ncx, int ncy, double* __restrict__ Ac) {
   const size_t ncn = (size_t)ncx * ncy;
-  const size_t I = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= ncn) return;
-  const int Ix = (int)(I % ncx), Iy = (int)(I / ncx);
+  const int ntx = (ncx + kPtwTX - 1) / kPtwTX;
+  const unsigned tile = xcd_block();
+  const int Ix = (int)(tile % ntx) * kPtwTX + (int)(threadIdx.x % kPtwTX);
+  const int Iy = (int)(tile / ntx) * kPtwTY + (int)(threadIdx.x / kPtwTX);
+  if (Ix >= ncx || Iy >= ncy) return;
+  const size_t I = (size_t)Iy * ncx + Ix;
+  const size_t nw = gw_size(nxn, nyn, ncx, ncy);
   const int tJx[5] = {Ix, Ix + 1, Ix, Ix + 1, Ix - 1};
   const int tJy[5] = {Iy, Iy, Iy + 1, Iy + 1, Iy + 1};
   double acc[5][3][3];
@@ -2155,6 +2195,7 @@ k_galerkin_ptw(const double* __restrict__ P, const double* __restrict__ W, size_
       if (sx < 0) continue;
       const int sl = sx + 2 * sy;
       const size_t n = (size_t)j * nxn + i;
+      const size_t gi = gw_index(i, j, nxn, nyn, ncx, ncy);
       const int ax = agg_of(i, ncx);
       double PI[B][3];
 #pragma unroll
@@ -2170,7 +2211,7 @@ k_galerkin_ptw(const double* __restrict__ P, const double* __restrict__ W, size_
         for (int k = 0; k < B; ++k)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double wv = W[(size_t)((q * B + k) * 3 + c) * nn + n];
+            const double wv = W[(size_t)((q * B + k) * 3 + c) * nw + gi];
 #pragma unroll
             for (int a = 0; a < 3; ++a) acc[t][a][c] += PI[k][a] * wv;
           }
@@ -2669,12 +2710,15 @@ void bf16_copies(vp_ctx c, hipStream_t s, int finest, int coarse) {
   }
 }
 
-// Scratch for the Galerkin products: the largest 9*3*B*nn over the levels that
-// have a coarser level (allocated once per hierarchy).
+// Scratch for the Galerkin products: the largest 9*3*B*gw_size over the levels
+// that have a coarser level (allocated once per hierarchy).
 double* galerkin_work(vp_ctx c) {
   if (!c->gal_work) {
     size_t mx = 0;
-    for (int l = 0; l + 1 < c->nlev; ++l) mx = std::max(mx, (size_t)27 * c->lev[l].B * c->lev[l].nn);
+    for (int l = 0; l + 1 < c->nlev; ++l) {
+      const Level& L = c->lev[l];
+      mx = std::max(mx, (size_t)27 * L.B * gw_size(L.nxn, L.nyn, L.ncx, L.ncy));
+    }
     c->gal_work = dalloc<double>(std::max<size_t>(mx, 1));
   }
   return c->gal_work;
@@ -2814,19 +2858,20 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
                          L.Ptent, L.lmax, omega_scale, L.P64);
     VP_LAUNCH_CHECK();
     Level& N = c->lev[l + 1];
-    const unsigned gc = (unsigned)((N.nn + kBlock - 1) / kBlock);
+    const size_t ptw_tiles = (size_t)((L.ncx + kPtwTX - 1) / kPtwTX) * ((L.ncy + kPtwTY - 1) / kPtwTY);
+    const unsigned gc = grid_for(ptw_tiles, 1);   // one workgroup per tile, a multiple of 8
     double* Wap = galerkin_work(c);
     if (L.B == 2) {
-      hipLaunchKernelGGL(k_galerkin_ap<2>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
-                         L.P64, Wap);
+      hipLaunchKernelGGL(k_galerkin_ap<2>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx,
+                         L.ncy, L.P64, Wap);
       VP_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_galerkin_ptw<2>, dim3(gc), dim3(kBlock), 0, s, L.P64, Wap, L.nn, L.nxn, L.nyn, L.ncx,
+      hipLaunchKernelGGL(k_galerkin_ptw<2>, dim3(gc), dim3(kPtwTX * kPtwTY), 0, s, L.P64, Wap, L.nn, L.nxn, L.nyn, L.ncx,
                          L.ncy, N.A64);
     } else {
-      hipLaunchKernelGGL(k_galerkin_ap<3>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
-                         L.P64, Wap);
+      hipLaunchKernelGGL(k_galerkin_ap<3>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx,
+                         L.ncy, L.P64, Wap);
       VP_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_galerkin_ptw<3>, dim3(gc), dim3(kBlock), 0, s, L.P64, Wap, L.nn, L.nxn, L.nyn, L.ncx,
+      hipLaunchKernelGGL(k_galerkin_ptw<3>, dim3(gc), dim3(kPtwTX * kPtwTY), 0, s, L.P64, Wap, L.nn, L.nxn, L.nyn, L.ncx,
                          L.ncy, N.A64);
     }
     VP_LAUNCH_CHECK();
