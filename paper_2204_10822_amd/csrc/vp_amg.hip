@@ -1134,18 +1134,22 @@ __device__ __forceinline__ WVec<T> wsolve(const WBlk<T>& Di, const T (&r)[2]) {
   return WVec<T>{t0, t1};
 }
 
-constexpr int kWalk4Waves = 2;   // waves (strips) per workgroup: finer packing of the resident slots
-template <int KIND, typename T>
-__global__ void __launch_bounds__(64 * kWalk4Waves)
-k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const T* __restrict__ b,
-             const T* __restrict__ xin, T* __restrict__ rout, T* __restrict__ xout, T c0, T a1, T b1, T a2, T b2,
-             T a3, T b3) {
+
+// One strip of the four-sweep walk.  UP walks from the strip's bottom (sweep k at
+// row R - k, the south neighbour of a sweep's row is older than its row); the
+// mirror image (UP = false) walks from the top (sweep k at row R + k: the south
+// neighbour is the row the previous sweep has just produced, and the operator
+// rows R .. R + 4 suffice, one fewer than upward).  Every node gets the same
+// arithmetic in the same order either way, so both give the outputs bitwise.
+template <int KIND, typename T, bool UP>
+__device__ __forceinline__ void walk4_strip(int TR, int i, int j0, int lane, const T* __restrict__ A, size_t nn,
+                                            int nxn, int nyn, const T* __restrict__ b, const T* __restrict__ xin,
+                                            T* __restrict__ rout, T* __restrict__ xout, T c0, T a1, T b1, T a2, T b2,
+                                            T a3, T b3) {
   using Bk = WBlk<T>;
   using Vc = WVec<T>;
   using Rw = WRow<T>;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 56 - 4 + lane;
-  const int j0 = (blockIdx.y * kWalk4Waves + (int)(threadIdx.x >> 6)) * TR;
+  constexpr int sg = UP ? -1 : 1;   // sweep k works on row R + sg k
   const bool in = i >= 0 && i < nxn;
   const int ic = in ? i : -(1 << 29);   // idle lanes load nothing
   const int lm = (lane + 63) & 63, lp = (lane + 1) & 63;
@@ -1153,26 +1157,32 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
   const Bk z{T(0), T(0), T(0), T(0)};
   const Vc zv{T(0), T(0)};
   const Rw zr{z, z, z, z, z};
-  Rw W1 = zr, W2 = zr, W3 = zr, W4 = zr, W5 = zr;   // blocks of rows R-1 .. R-5
-  Bk D1 = z, D2 = z, D3 = z, D4 = z;                  // block inverses of rows R-1 .. R-4
-  // stage k's input vector at its row minus one (uS) and its row (uC)
-  Vc uS1 = zv, uC1 = zv, uS2 = zv, uC2 = zv, uS3 = zv, uC3 = zv, uS4 = zv, uC4 = zv;
-  Vc rc1 = zv, rc2 = zv, rc3 = zv, rc4 = zv;          // residual entering stage k at its row
-  Vc xc2 = zv, xc3 = zv, xc4 = zv;                    // iterate entering stage k at its row
-  const int Rend = min(j0 + TR + 3, nyn + 3);
-  // row R + 1 is loaded while row R is evaluated
-  Rw Wn = wrow(A, nn, nxn, nyn, ic, j0 - 4);
-  Vc bn = wvec(b, nxn, nyn, ic, j0 - 4), xn = zv;
-  if constexpr (KIND == W4_POST) xn = wvec(xin, nxn, nyn, ic, j0 - 4);
+  Rw W1 = zr, W2 = zr, W3 = zr, W4 = zr, W5 = zr;   // blocks of rows R + sg, ..., R + 5 sg (W5 upward only)
+  Bk D1 = z, D2 = z, D3 = z, D4 = z;                  // block inverses of rows R + sg .. R + 4 sg
+  // sweep k's input vector at its row's far neighbour (uO: the row below upward,
+  // above downward) and at its row (uC)
+  Vc uO1 = zv, uC1 = zv, uO2 = zv, uC2 = zv, uO3 = zv, uC3 = zv, uO4 = zv, uC4 = zv;
+  Vc rc1 = zv, rc2 = zv, rc3 = zv, rc4 = zv;          // residual entering sweep k at its row
+  Vc xc2 = zv, xc3 = zv, xc4 = zv;                    // iterate entering sweep k at its row
+  // sweep k covers rows j0 - 4 + k .. j0 + TR + 3 - k of the grid
+  const int Rfirst = UP ? j0 - 4 : min(j0 + TR + 3, nyn - 1);
+  const int Rlast = UP ? min(j0 + TR + 3, nyn + 3) : j0 - 4;
+  auto active = [&](int j, int k) {
+    return j >= 0 && j < nyn && (UP ? j >= j0 - 4 + k : j <= j0 + TR + 3 - k);
+  };
+  // row R - sg is loaded while row R is evaluated
+  Rw Wn = wrow(A, nn, nxn, nyn, ic, Rfirst);
+  Vc bn = wvec(b, nxn, nyn, ic, Rfirst), xn = zv;
+  if constexpr (KIND == W4_POST) xn = wvec(xin, nxn, nyn, ic, Rfirst);
   // One row step; the shifts at its end rotate the register window.
   auto row = [&] __device__ (const int R) {
     const Rw W0 = Wn;
     const Vc bR = bn, xR = xn;
-    Wn = wrow(A, nn, nxn, nyn, ic, R + 1);
-    bn = wvec(b, nxn, nyn, ic, R + 1);
-    if constexpr (KIND == W4_POST) xn = wvec(xin, nxn, nyn, ic, R + 1);
+    Wn = wrow(A, nn, nxn, nyn, ic, R - sg);
+    bn = wvec(b, nxn, nyn, ic, R - sg);
+    if constexpr (KIND == W4_POST) xn = wvec(xin, nxn, nyn, ic, R - sg);
     const Bk D0 = winv(W0.p0);
-    Vc u0;   // stage 1's input at row R
+    Vc u0;   // sweep 1's input at row R
     if constexpr (KIND == W4_PRE) {
       const T bb[2] = {bR.x, bR.y};
       const Vc t = wsolve(D0, bb);
@@ -1180,12 +1190,21 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
     } else {
       u0 = xR;
     }
+    // y = A u at row j of sweep k: own blocks Wk, the south row's blocks and the
+    // input at rows j - 1, j, j + 1 (the new value un is on the near side)
+    auto apply = [&](T (&y)[2], int j, const Rw& Wk, const Rw& Wfar, const Rw& Wnear, const Vc& uO, const Vc& uC,
+                     const Vc& un) {
+      if constexpr (UP)
+        wapply(y, Wk, Wfar, uO, uC, un, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+      else
+        wapply(y, Wk, Wnear, un, uC, uO, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+    };
     Vc d1 = zv, r1 = zv, x1 = zv;
     {
-      const int j = R - 1;
-      if (j >= 0 && j < nyn && j >= j0 - 3) {
+      const int j = R + sg;
+      if (active(j, 1)) {
         T y[2];
-        wapply(y, W1, W2, uS1, uC1, u0, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+        apply(y, j, W1, W2, W0, uO1, uC1, u0);
         const T r[2] = {rc1.x - y[0], rc1.y - y[1]};
         const Vc t = wsolve(D1, r);
         if constexpr (KIND == W4_PRE) {
@@ -1196,7 +1215,7 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
           {
             // the paired kernels add this step to x in their next sweep, to the
             // rounded product: no contraction into a fused multiply-add here
-  #pragma clang fp contract(off)
+#pragma clang fp contract(off)
             x1 = Vc{uC1.x + d1.x, uC1.y + d1.y};
           }
         }
@@ -1205,10 +1224,10 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
     }
     Vc d2 = zv, r2 = zv, x2 = zv;
     {
-      const int j = R - 2;
-      if (j >= 0 && j < nyn && j >= j0 - 2) {
+      const int j = R + 2 * sg;
+      if (active(j, 2)) {
         T y[2];
-        wapply(y, W2, W3, uS2, uC2, d1, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+        apply(y, j, W2, W3, W1, uO2, uC2, d1);
         const T r[2] = {rc2.x - y[0], rc2.y - y[1]};
         const Vc t = wsolve(D2, r);
         const T a = KIND == W4_PRE ? a2 : a1, bq = KIND == W4_PRE ? b2 : b1;
@@ -1219,10 +1238,10 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
     }
     Vc d3 = zv, r3 = zv, x3 = zv;
     {
-      const int j = R - 3;
-      if (j >= 0 && j < nyn && j >= j0 - 1) {
+      const int j = R + 3 * sg;
+      if (active(j, 3)) {
         T y[2];
-        wapply(y, W3, W4, uS3, uC3, d2, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+        apply(y, j, W3, W4, W2, uO3, uC3, d2);
         const T r[2] = {rc3.x - y[0], rc3.y - y[1]};
         const Vc t = wsolve(D3, r);
         const T a = KIND == W4_PRE ? a3 : a2, bq = KIND == W4_PRE ? b3 : b2;
@@ -1232,10 +1251,10 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
       }
     }
     {
-      const int j = R - 4;   // stage 4: the outputs
-      if (j >= j0 && j < nyn) {
+      const int j = R + 4 * sg;   // sweep 4: the outputs, rows j0 .. j0 + TR - 1
+      if (j >= j0 && j < j0 + TR && j < nyn) {
         T y[2];
-        wapply(y, W4, W5, uS4, uC4, d3, lm, lp, hE, hW, j + 1 < nyn, j > 0);
+        apply(y, j, W4, W5, W3, uO4, uC4, d3);
         const T r[2] = {rc4.x - y[0], rc4.y - y[1]};
         if (in && lane >= 4 && lane < 60) {
           const size_t n = (size_t)j * nxn + i;
@@ -1253,26 +1272,70 @@ k_cheb_walk4(int TR, const T* __restrict__ A, size_t nn, int nxn, int nyn, const
         }
       }
     }
-    W5 = W4; W4 = W3; W3 = W2; W2 = W1; W1 = W0;
+    if constexpr (UP) W5 = W4;
+    W4 = W3; W3 = W2; W2 = W1; W1 = W0;
     D4 = D3; D3 = D2; D2 = D1; D1 = D0;
-    uS4 = uC4; uC4 = d3; uS3 = uC3; uC3 = d2; uS2 = uC2; uC2 = d1; uS1 = uC1; uC1 = u0;
+    uO4 = uC4; uC4 = d3; uO3 = uC3; uC3 = d2; uO2 = uC2; uC2 = d1; uO1 = uC1; uC1 = u0;
     rc4 = r3; rc3 = r2; rc2 = r1; rc1 = bR;
     xc4 = x3; xc3 = x2; xc2 = x1;
   };
-  // Seven steps at a time (the window holds seven rows: the prefetched one, the
-  // current one and five below): after inlining, most of the rotation becomes a
-  // renaming of registers instead of copies.  R is uniform across the wave.
-  int R = j0 - 4;
-  for (; R + 6 <= Rend; R += 7) {
-    row(R);
-    row(R + 1);
-    row(R + 2);
-    row(R + 3);
-    row(R + 4);
-    row(R + 5);
-    row(R + 6);
+  // Steps issued as many at a time as the window has row slots (seven upward: the
+  // prefetched row, the current one and five more; six downward): after inlining,
+  // most of the rotation becomes a renaming of registers instead of copies.  R is
+  // uniform across the wave.
+  int R = Rfirst;
+  if constexpr (UP) {
+    for (; R + 6 <= Rlast; R += 7) {
+      row(R);
+      row(R + 1);
+      row(R + 2);
+      row(R + 3);
+      row(R + 4);
+      row(R + 5);
+      row(R + 6);
+    }
+    for (; R <= Rlast; ++R) row(R);
+  } else {
+    for (; R - 5 >= Rlast; R -= 6) {
+      row(R);
+      row(R - 1);
+      row(R - 2);
+      row(R - 3);
+      row(R - 4);
+      row(R - 5);
+    }
+    for (; R >= Rlast; --R) row(R);
   }
-  for (; R <= Rend; ++R) row(R);
+}
+
+// A workgroup takes two vertically adjacent strips; the lower one walks upward and
+// the upper one downward, so the eight rows the two strips share come in at about
+// the same time, and the upper strip starts where the next workgroup's lower strip
+// starts.  With FP64 blocks each strip is two waves (112 columns) wide, so the waves
+// side by side also read their eight shared columns at the same time on one CU
+// (measured at 2049^2: FP32 131 us with one wave per strip, 135 with two; FP64 314
+// us with two, 332 with one).  Workgroups are dealt to the XCDs in contiguous runs
+// of a column-major order, so vertical and horizontal neighbours mostly share an L2.
+template <typename T>
+constexpr int walk4_cols() { return std::is_same<T, double>::value ? 2 : 1; }
+constexpr int kWalk4Strips = 2;
+template <int KIND, typename T>
+__global__ void __launch_bounds__(64 * kWalk4Strips * walk4_cols<T>())
+k_cheb_walk4(int TR, int ntx, int nty, const T* __restrict__ A, size_t nn, int nxn, int nyn,
+             const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ rout, T* __restrict__ xout, T c0,
+             T a1, T b1, T a2, T b2, T a3, T b3) {
+  constexpr int cols = walk4_cols<T>();
+  const unsigned t = xcd_block();
+  const int tx = (int)(t / nty), ty = (int)(t % nty);
+  if (tx >= ntx) return;
+  const int lane = threadIdx.x & 63, wave = (int)(threadIdx.x >> 6);
+  const int col = wave % cols, strip = wave / cols;
+  const int i = (tx * cols + col) * 56 - 4 + lane;
+  const int j0 = (ty * kWalk4Strips + strip) * TR;
+  if (strip == 0)
+    walk4_strip<KIND, T, true>(TR, i, j0, lane, A, nn, nxn, nyn, b, xin, rout, xout, c0, a1, b1, a2, b2, a3, b3);
+  else
+    walk4_strip<KIND, T, false>(TR, i, j0, lane, A, nn, nxn, nyn, b, xin, rout, xout, c0, a1, b1, a2, b2, a3, b3);
 }
 
 // Paired sweeps by column walks on the structured coarse levels (3 x 3 blocks, FP32
@@ -3214,20 +3277,21 @@ template <int KIND, typename T>
 void launch_walk4(vp_ctx c, const Level& L, const T* A, const T* b, const T* xin, T* rout, T* xout,
                   const ChebCoef& k) {
   int& resident = c->walk4_resident[std::is_same<T, double>::value ? 1 : 0][KIND];
+  constexpr int cols = walk4_cols<T>(), threads = 64 * kWalk4Strips * cols;
   if (resident == 0) {
     int ncu = 0, per_cu = 0;
     VP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
     VP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_cheb_walk4<KIND, T>), 64 * kWalk4Waves, 0));
+        &per_cu, reinterpret_cast<const void*>(&k_cheb_walk4<KIND, T>), threads, 0));
     resident = std::max(1, ncu * per_cu);
   }
-  const int gx = (L.nxn + 55) / 56;
-  const int gy_fit = std::max(1, resident / gx);   // workgroup rows (kWalk4Waves strips each) that fit
+  const int gx = (L.nxn + 56 * cols - 1) / (56 * cols);
+  const int gy_fit = std::max(1, resident / gx);   // workgroup rows (kWalk4Strips strips each) that fit
   const int tr = c->walk4_rows > 0 ? c->walk4_rows
-                                   : std::max(8, (L.nyn + kWalk4Waves * gy_fit - 1) / (kWalk4Waves * gy_fit));
-  const int gy = (L.nyn + kWalk4Waves * tr - 1) / (kWalk4Waves * tr);
-  hipLaunchKernelGGL((k_cheb_walk4<KIND, T>), dim3((unsigned)gx, (unsigned)gy), dim3(64 * kWalk4Waves), 0,
-                     c->stream, tr, A, L.nn, L.nxn, L.nyn, b, xin, rout, xout, (T)k.inv_theta, (T)k.cdd[1],
+                                   : std::max(8, (L.nyn + kWalk4Strips * gy_fit - 1) / (kWalk4Strips * gy_fit));
+  const int gy = (L.nyn + kWalk4Strips * tr - 1) / (kWalk4Strips * tr);
+  hipLaunchKernelGGL((k_cheb_walk4<KIND, T>), dim3(grid_for((size_t)gx * gy, 1)), dim3(threads), 0,
+                     c->stream, tr, gx, gy, A, L.nn, L.nxn, L.nyn, b, xin, rout, xout, (T)k.inv_theta, (T)k.cdd[1],
                      (T)k.cdr[1], (T)k.cdd[2], (T)k.cdr[2], (T)k.cdd[3], (T)k.cdr[3]);
   VP_LAUNCH_CHECK();
 }

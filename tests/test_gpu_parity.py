@@ -409,12 +409,14 @@ def test_paired_sweeps_match_single_sweeps(vp, prec, degree):
     assert np.array_equal(ref, out)
 
 
-@pytest.mark.parametrize("rows", [1, 5, 13, 38, 151])
+@pytest.mark.parametrize("rows", [1, 5, 13, 38, 79, 151])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_walk4_strip_heights(vp, prec, rows):
     """The four-sweep column walk gives bitwise the single sweeps' V-cycle for any
-    strip height: short strips, the 38 rows the launcher picks at 2049^2, and one
-    strip over the whole mesh (the halo rows each strip recomputes are the same)."""
+    strip height: short strips, the 38 (FP32) and 79 (FP64) rows the launcher picks
+    at 2049^2, and one strip over the whole mesh (the halo rows each strip
+    recomputes are the same).  Each workgroup walks its lower strip upward and its
+    upper strip downward; odd strip counts leave an upper strip past the mesh."""
     ref, _ = _vcycle(vp, 200, 150, 8, prec, 4, 9, variant=vp.VP_AMG_VAR_NO_PAIRS)
     out, _ = _vcycle(vp, 200, 150, 8, prec, 4, 9, walk4_rows=rows)
     print(f"[walk4 rows] prec={prec} rows={rows} max |diff| {np.abs(ref - out).max():.2e}", flush=True)
