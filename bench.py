@@ -107,13 +107,14 @@ CALIB_READ_KIB, CALIB_WRITE_KIB = 2 << 20, 1 << 20   # the triad of kernel_seque
 
 
 def counter_traffic(kernel_name):
-    """HBM bytes per launch of `kernel_name` from the committed FETCH_SIZE and
-    WRITE_SIZE summaries: (calibrated, raw).  Calibrated scales each counter by its
-    reading for the calibration triad (FETCH_SIZE counts a read request as 64 B and
-    the triad's requests carry 128 B: factor 2); raw is the counters as read, a
-    lower bound for kernels whose requests carry 64 B.  (None, None) if a summary
-    or the kernel is missing."""
-    def table(fname):
+    """HBM bytes per launch of `kernel_name` from the committed counter summaries:
+    (traffic, FETCH_SIZE + WRITE_SIZE as read).  Traffic counts every L2->memory
+    request at its own size (128/64/32-B reads, 64/32-B writes) from the
+    size-split request counters; without that summary it falls back to the
+    FETCH_SIZE/WRITE_SIZE pair scaled by their reading for the calibration triad
+    (FETCH_SIZE counts a 128-B read request as 64 B).  (None, None) if the kernel
+    is missing."""
+    def table(fname, col):
         path = os.path.join(PROFILES, fname)
         if not os.path.exists(path):
             return None
@@ -121,21 +122,27 @@ def counter_traffic(kernel_name):
         for line in open(path):
             if line.startswith("#") or not line.strip():
                 continue
-            parts = line.rsplit(None, 3)
-            if len(parts) == 4 and parts[1].isdigit():
+            parts = line.rsplit(None, col)
+            if len(parts) == col + 1 and parts[1].isdigit():
                 try:
-                    rows[parts[0].strip()] = float(parts[2])
+                    rows[parts[0].strip()] = [float(x) for x in parts[2:]]
                 except ValueError:
                     pass
         return rows
-    fetch = table("vp_sharp_2048_kernels_fetch_size.txt")
-    write = table("vp_sharp_2048_kernels_write_size.txt")
-    if not fetch or not write or kernel_name not in fetch or kernel_name not in write:
+    fetch = table("vp_sharp_2048_kernels_fetch_size.txt", 3)
+    write = table("vp_sharp_2048_kernels_write_size.txt", 3)
+    raw = None
+    if fetch and write and kernel_name in fetch and kernel_name in write:
+        raw = 1024.0 * (fetch[kernel_name][0] + write[kernel_name][0])
+    req = table("vp_sharp_2048_kernels_requests.txt", 10)
+    if req and kernel_name in req:
+        return 1e6 * req[kernel_name][7], raw   # total_MB column
+    if raw is None:
         return None, None
-    cal_f = max(v for k, v in fetch.items() if "elementwise" in k)
-    cal_w = max(v for k, v in write.items() if "elementwise" in k)
-    calibrated = 1024.0 * (fetch[kernel_name] * CALIB_READ_KIB / cal_f + write[kernel_name] * CALIB_WRITE_KIB / cal_w)
-    raw = 1024.0 * (fetch[kernel_name] + write[kernel_name])
+    cal_f = max(v[0] for k, v in fetch.items() if "elementwise" in k)
+    cal_w = max(v[0] for k, v in write.items() if "elementwise" in k)
+    calibrated = 1024.0 * (fetch[kernel_name][0] * CALIB_READ_KIB / cal_f +
+                           write[kernel_name][0] * CALIB_WRITE_KIB / cal_w)
     return calibrated, raw
 
 
@@ -331,7 +338,7 @@ def main():
     kname = kernel_name(dom, storage_kind(best))
     traffic, traffic_raw = counter_traffic(kname) if kname else (None, None)
     roof = dict(kernel=kname or dom, bound="hbm", achieved=D["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=D["gbs"] / HBM_PEAK_GBS, traffic=traffic, traffic_raw_lower_bound=traffic_raw,
+                frac=D["gbs"] / HBM_PEAK_GBS, traffic=traffic, traffic_fetch_write_size=traffic_raw,
                 bytes_per_launch=D["bytes_per_launch"], avg_us=D["avg_us"])
     spmv = R["kernels"].get("apply_fine")
     out = {
