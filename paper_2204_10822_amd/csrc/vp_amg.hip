@@ -2086,6 +2086,16 @@ __global__ void k_power_final(const double* __restrict__ nrm2, double factor, do
   }
 }
 
+// One device scalar from each of up to kMaxLevels + 1 places into out[0 .. n)
+struct ScalarPtrs {
+  const double* p[kMaxLevels + 1];
+  int n;
+};
+__global__ void k_gather_scalars(ScalarPtrs a, double* __restrict__ out) {
+  const int t = threadIdx.x;
+  if (t < a.n) out[t] = a.p[t][0];
+}
+
 __global__ void k_finish_max(const double* __restrict__ partials, int nblocks, double* __restrict__ out) {
   __shared__ double lds[512];
   double m = 0.0;
@@ -2622,6 +2632,7 @@ void amg_free(vp_ctx c) {
   }
   dfree(c->dense);
   dfree(c->gal_work);
+  dfree(c->lmax_all);
   c->nlev = 0;
   c->amg_struct = false;
   c->amg_ready = false;
@@ -2992,11 +3003,18 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     c->sa_vec64 = vec64;
   }
   c->amg_prec = precision;
-  // spectral bounds to the host (one synchronisation per setup)
-  for (int l = 0; l < c->nlev; ++l)
-    VP_HIP(hipMemcpyAsync(c->hscal + l, c->lev[l].lmax, sizeof(double), hipMemcpyDeviceToHost, s));
-  if (c->order == 2)
-    VP_HIP(hipMemcpyAsync(c->hscal + c->nlev, c->lmax_q2, sizeof(double), hipMemcpyDeviceToHost, s));
+  // spectral bounds to the host: gathered on the device, one copy and one
+  // synchronisation per setup
+  {
+    ScalarPtrs g{};
+    g.n = c->nlev + (c->order == 2 ? 1 : 0);
+    for (int l = 0; l < c->nlev; ++l) g.p[l] = c->lev[l].lmax;
+    if (c->order == 2) g.p[c->nlev] = c->lmax_q2;
+    if (!c->lmax_all) c->lmax_all = dalloc<double>(kMaxLevels + 1);
+    hipLaunchKernelGGL(k_gather_scalars, dim3(1), dim3(64), 0, s, g, c->lmax_all);
+    VP_LAUNCH_CHECK();
+    VP_HIP(hipMemcpyAsync(c->hscal, c->lmax_all, g.n * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
   VP_HIP(hipStreamSynchronize(s));
   for (int l = 0; l < c->nlev + (c->order == 2 ? 1 : 0); ++l)
     if (!(c->hscal[l] > 0.0) || !std::isfinite(c->hscal[l]))

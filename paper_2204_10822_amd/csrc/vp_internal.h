@@ -245,6 +245,7 @@ struct vp_ctx_s {
   double* static_ws = nullptr;     // device address of the static workspace (allocation-free solve)
   int kv_restart = 0;
   double* dense = nullptr;         // coarse dense matrix scratch
+  double* lmax_all = nullptr;      // the levels' spectral bounds gathered for one copy to the host
   double* gal_work = nullptr;      // A P per fine node for the Galerkin product [9*3*B*nn]
   // Newton history (Eisenstat-Walker state)
   double ew_rn_prev = -1.0, ew_eta_prev = 0.1;

@@ -3,7 +3,7 @@
     python -m paper_2204_10822_amd.profsum stats  <kernel_stats.csv>  [top]
     python -m paper_2204_10822_amd.profsum counter <counter_collection.csv> <COUNTER>
     python -m paper_2204_10822_amd.profsum grids <kernel_trace.csv> [top]
-    python -m paper_2204_10822_amd.profsum requests <read_counters.csv> <write_counters.csv>
+    python -m paper_2204_10822_amd.profsum requests <read_counters.csv> <write_counters.csv> [top]
 
 `stats` prints the top kernels by summed duration.  `counter` prints, per kernel
 name, the dispatch count and the mean value of one counter per dispatch (for
@@ -110,7 +110,7 @@ def _means(path: str) -> tuple[dict, dict, dict]:
     return mean, count, grid
 
 
-def requests(rd_path: str, wr_path: str) -> None:
+def requests(rd_path: str, wr_path: str, top: int = 40) -> None:
     rd, n, grid = _means(rd_path)
     wr, _, _ = _means(wr_path)
     print("L2->memory requests per dispatch (means) and the bytes they carry (MB = 1e6 B)")
@@ -128,7 +128,7 @@ def requests(rd_path: str, wr_path: str) -> None:
         rb = (128 * r128 + 64 * r64 + 32 * r32) / 1e6
         wb = (64 * w64 + 32 * w32) / 1e6
         rows.append((rb + wb, k, r128, r64, r32, rb, w64, w32, wb))
-    for tot, k, r128, r64, r32, rb, w64, w32, wb in sorted(rows, key=lambda t: -t[0]):
+    for tot, k, r128, r64, r32, rb, w64, w32, wb in sorted(rows, key=lambda t: -t[0])[:top]:
         print(f"{k[:58]:58s} {n[k]:5d} {r128:11.0f} {r64:9.0f} {r32:9.0f} {rb:9.2f} {w64:10.0f} {w32:9.0f} "
               f"{wb:9.2f} {tot:9.2f} {grid[k]:>10s}")
 
@@ -154,6 +154,6 @@ if __name__ == "__main__":
     elif sys.argv[1] == "grids":
         grids(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 40)
     elif sys.argv[1] == "requests":
-        requests(sys.argv[2], sys.argv[3])
+        requests(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) > 4 else 40)
     else:
         counter(sys.argv[2], sys.argv[3])
