@@ -2052,9 +2052,9 @@ __global__ void k_power_init(double* __restrict__ x, size_t n) {
   }
 }
 
-template <int B, int ST = 0>
+template <int B, int ST = 0, typename TM = double>
 __global__ void __launch_bounds__(kBlock)
-k_power_step(const double* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
+k_power_step(const TM* __restrict__ A, size_t nn, int nxn, int nyn, const double* __restrict__ x,
              const double* __restrict__ nrm2_in, double* __restrict__ y, double* __restrict__ partials) {
   __shared__ double lds[16];
   const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2714,13 +2714,7 @@ void bf16_copies(vp_ctx c, hipStream_t s, int finest, int coarse) {
     Level& L = c->lev[l];
     const size_t na = (size_t)5 * L.B * L.B * L.nn;
     const unsigned g = (unsigned)((L.nn + 255) / 256);
-    if (l == 0 && finest == 0) {
-      if (c->order == 1) {   // Q2: the finest level runs on K2_32
-        if (!L.A32) L.A32 = dalloc<float>(na);
-        convert(s, L.A64, L.A32, na);
-      }
-      continue;
-    }
+    if (l == 0 && finest == 0) continue;   // FP32 finest operator made first (Q2: the finest level runs on K2_32)
     if (!L.dsc64) L.dsc64 = dalloc<double>((size_t)L.B * L.nn);
     if (L.B == 2)
       hipLaunchKernelGGL(k_diag_sqrt<2>, dim3(g), dim3(256), 0, s, L.A64, L.nn, L.dsc64);
@@ -2866,6 +2860,16 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   hipStream_t s = c->stream;
   const bool q2u = c->order == 2;
   if (c->order == 2) q2_smoother_setup(c, precision);
+  // Modes whose V-cycle smooths the finest level with an FP32 copy of the operator
+  // get that copy first, and the finest level's power steps stream it instead of
+  // the FP64 operator (half the bytes; the bound only needs a few digits).
+  const bool fine32 = c->order == 1 && (precision == VP_PREC_FP32 || precision == VP_PREC_FP32_BF16COARSE);
+  if (fine32) {
+    Level& L0 = c->lev[0];
+    const size_t na = (size_t)20 * L0.nn;
+    if (!L0.A32) L0.A32 = dalloc<float>(na);
+    convert(s, L0.A64, L0.A32, na);
+  }
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const unsigned g = (unsigned)((L.nn + kBlock - 1) / kBlock);
@@ -2911,7 +2915,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       for (int k = 0; k < its; ++k) {
         double* xin = (k & 1) ? L.pv1 : L.pv0;
         double* yout = (k & 1) ? L.pv0 : L.pv1;
-        if (L.B == 2)
+        if (l == 0 && fine32)
+          hipLaunchKernelGGL((k_power_step<2, 0, float>), dim3(g), dim3(kBlock), 0, s, (const float*)L.A32, L.nn,
+                             L.nxn, L.nyn, xin, L.pnrm + (k & 1), yout, c->partials);
+        else if (L.B == 2)
           hipLaunchKernelGGL(k_power_step<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, xin,
                              L.pnrm + (k & 1), yout, c->partials);
         else
@@ -2981,7 +2988,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
       const size_t na = (size_t)5 * L.B * L.B * L.nn;
-      if (l > 0 || c->order == 1) {   // Q2: the finest level runs on K2_32
+      if (l > 0) {   // the finest FP32 operator is made first (Q2: the finest level runs on K2_32)
         if (!L.A32) L.A32 = dalloc<float>(na);
         convert(s, L.A64, L.A32, na);
       }
