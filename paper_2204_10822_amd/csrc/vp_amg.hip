@@ -2114,7 +2114,7 @@ template <int B>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
            const double* __restrict__ Ptent, const double* __restrict__ lmax, double omega_scale,
-           double* __restrict__ P) {
+           double* __restrict__ P, float* __restrict__ P32) {
   const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
@@ -2152,6 +2152,7 @@ k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
         if (s == 0) val += Ptent[(size_t)(r * 3 + c) * nn + n];
         if (Jx < 0 || Jy < 0) val = 0.0;
         P[pidx(B, nn, s, n, r, c)] = val;
+        if (P32) P32[pidx(B, nn, s, n, r, c)] = (float)val;   // the FP32 mode's copy
       }
   }
 }
@@ -2931,12 +2932,18 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       VP_LAUNCH_CHECK();
       if (its & 1) std::swap(L.pv0, L.pv1);  // keep the latest iterate in pv0
     }
+    // the FP32 mode's FP32 prolongator is written by the smoothing itself
+    float* p32 = nullptr;
+    if (precision == VP_PREC_FP32) {
+      if (!L.P32) L.P32 = dalloc<float>((size_t)4 * L.B * 3 * L.nn);
+      p32 = L.P32;
+    }
     if (L.B == 2)
       hipLaunchKernelGGL(k_smooth_p<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
-                         L.Ptent, L.lmax, omega_scale, L.P64);
+                         L.Ptent, L.lmax, omega_scale, L.P64, p32);
     else
       hipLaunchKernelGGL(k_smooth_p<3>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
-                         L.Ptent, L.lmax, omega_scale, L.P64);
+                         L.Ptent, L.lmax, omega_scale, L.P64, p32);
     VP_LAUNCH_CHECK();
     Level& N = c->lev[l + 1];
     const size_t ptw_tiles = (size_t)((L.ncx + kPtwTX - 1) / kPtwTX) * ((L.ncy + kPtwTY - 1) / kPtwTY);
@@ -2992,7 +2999,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
         if (!L.A32) L.A32 = dalloc<float>(na);
         convert(s, L.A64, L.A32, na);
       }
-      if (L.P64) {
+      if (L.P64 && (c->order == 2 && l == 0)) {   // smoothed prolongators got theirs from k_smooth_p
         const size_t np = (size_t)4 * L.B * 3 * L.nn;
         if (!L.P32) L.P32 = dalloc<float>(np);
         convert(s, L.P64, L.P32, np);
