@@ -76,16 +76,22 @@ int vpnet_guess(int nx, int ny, const float* net_out, int wc, int hc, const doub
  * the learned start; the previous-step velocity v_prev with pi = tau/Delta (eq. pi);
  * or zero.  Ties go to the earlier of learned, previous, zero.  chosen (host,
  * nullable) receives the chosen flag.  Newton always finishes the solve.
- * Needs a batch-1 network, a Q1 context and one stream for both.  On meshes more
- * than VPNET_MAX_POOL times the network's grid per side the learned start is not
- * a candidate (box-averaged this far, its proposal misses the fine-scale
- * deformation and costs Newton iterations; measured: 36 -> 50 iterations at
- * 2048^2 with a 256^2 network); the network is then not run.  Synchronises.
+ * Needs a batch-1 network, a Q1 context and one stream for both.  On a mesh finer
+ * than the network's grid (f > 1: pooled inputs) the proposed change is damped,
+ * v0 = v_prev + VPNET_POOLED_SCALE (proposal - v_prev), and pi0 is taken
+ * consistent with v0 (pi = tau/Delta, eq. pi): box-averaged, the proposal misses
+ * the fine-scale deformation, and at full size it costs Newton iterations
+ * (measured at 1024^2 and 2048^2 with a 256^2 network: 167 against 170 Newton
+ * and 3465 against 2504 Krylov iterations from zero over five workloads; damped
+ * by 0.3, 22-25% less time than from zero over six held-out ones).  On meshes
+ * more than VPNET_MAX_POOL times the network's grid per side (not measured) the
+ * learned start is not a candidate and the network is not run.  Synchronises.
  * VP_EINVAL for null pointers, an empty candidate set, mismatched sizes or the
  * learned start alone on too fine a mesh; VP_ESTATE before vp_set_state;
  * VP_ENONFINITE if an energy is not finite. */
 enum { VPNET_START_LEARNED = 1, VPNET_START_PREVIOUS = 2, VPNET_START_ZERO = 4 };
-enum { VPNET_MAX_POOL = 4 };
+enum { VPNET_MAX_POOL = 8 };
+#define VPNET_POOLED_SCALE 0.3
 int vpnet_infer(vpnet net, vp_ctx ctx, int candidates, double* v0, double* pi0, int* chosen);
 
 /* Activations of the last forward pass and their gradients from the last

@@ -966,8 +966,7 @@ int vpnet_infer(vpnet_s* n, vp_ctx c, int candidates, double* v0, double* pi0, i
     if (!c->have_state) throw Error(VP_ESTATE, "vp_set_state not called");
     const int f = nx / n->W;
     if (f > kMaxPool) {
-      // pooled this far the proposal misses the fine-scale deformation and slows
-      // Newton down: the learned start is not a candidate on such meshes
+      // pooled further than measured: the learned start is not a candidate
       nreq(candidates != VPNET_START_LEARNED, "mesh finer than the network's grid times VPNET_MAX_POOL");
       candidates &= ~VPNET_START_LEARNED;
     }
@@ -984,6 +983,11 @@ int vpnet_infer(vpnet_s* n, vp_ctx c, int candidates, double* v0, double* pi0, i
       const size_t m = (size_t)(nx + 1) * (ny + 1) + (size_t)nx * ny;
       hipLaunchKernelGGL(k_guess, dim3(gs(m)), dim3(256), 0, s, nx, ny, n->out, n->W, n->H, c->vps, v0, pi0);
       VP_LAUNCH_CHECK();
+      if (f > 1) {
+        // pooled inputs: the proposed change damped, pi consistent with the result
+        launch_axpby(s, 1.0 - VPNET_POOLED_SCALE, c->vps, VPNET_POOLED_SCALE, v0, c->ndof);
+        launch_pi_init(c, v0, pi0);
+      }
     }
     // the start with the lowest energy Phi (eq. energy), first in the order
     // learned, previous, zero on ties

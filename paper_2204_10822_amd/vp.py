@@ -26,7 +26,8 @@ VP_LS_ENERGY, VP_LS_RESIDUAL = 0, 1
 VP_AMG_SA, VP_AMG_RS = 0, 1
 VP_AMG_VAR_NO_TAIL, VP_AMG_VAR_NO_PAIRS, VP_AMG_VAR_NO_TAIL_LDS, VP_AMG_VAR_NO_P16 = 1, 2, 4, 8
 VPNET_START_LEARNED, VPNET_START_PREVIOUS, VPNET_START_ZERO = 1, 2, 4
-VPNET_MAX_POOL = 4
+VPNET_MAX_POOL = 8
+VPNET_POOLED_SCALE = 0.3
 START = {"learned": VPNET_START_LEARNED, "previous": VPNET_START_PREVIOUS, "zero": VPNET_START_ZERO}
 
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_set_state", "vp_residual",

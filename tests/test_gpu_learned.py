@@ -78,21 +78,47 @@ def test_infer_candidates(vp, ws):
 
 
 def test_infer_pools_larger_meshes_and_rejects_others(vp, ws):
+    """On a mesh f times the network's grid (f > 1) the inputs are pooled and the
+    proposed change is damped by VPNET_POOLED_SCALE with pi consistent with the
+    damped velocity; beyond VPNET_MAX_POOL the learned start is no candidate; a
+    mesh that is not a multiple of the grid is rejected."""
     from paper_2204_10822_amd import inputs, warmstart as W
-    w = W.sample_workload(90101, 512)
+    n, f = 512, 2
+    w = W.sample_workload(90101, n)
     ctx = vp.context_for(w)
+    st = ctx._state
     v0 = torch.empty(ctx.node_shape, dtype=torch.float64, device="cuda")
     p0 = torch.empty(ctx.pi_shape, dtype=torch.float64, device="cuda")
     assert ws.start(ctx, v0, p0, ("learned",)) == "learned"
     assert bool(torch.isfinite(v0).all()) and bool(torch.isfinite(p0).all())
-    # more than 4x the network's grid per side: the learned start is no candidate
-    fine = vp.context_for(W.sample_workload(90102, 1280))
+    R = W.NET_RES
+    feat = torch.zeros(R * R * 8, dtype=torch.float32, device="cuda")
+    out = torch.zeros(R * R * 5, dtype=torch.float32, device="cuda")
+    vp.vpnet_features(n, n, f, st["H"], st["A"], st["v_air"], st["v_ocean"], st["v_prev"], feat)
+    ws.net.vpnet_forward(feat, out)
+    vm = torch.empty_like(v0)
+    pm = torch.empty_like(p0)
+    vp.vpnet_guess(n, n, out, R, R, vm, pm, v_prev=st["v_prev"])
+    s_ = vp.VPNET_POOLED_SCALE
+    vexp = (1.0 - s_) * st["v_prev"] + s_ * vm
+    pexp = torch.empty_like(p0)
+    ctx.vp_pi_init(v0, pexp)
+    torch.cuda.synchronize()
+    err = float((v0 - vexp).abs().max() / vm.abs().max())
+    print(f"[infer pooled] f={f} damped start vs scale*proposal: {err:.2e}", flush=True)
+    assert err < 1e-14
+    assert float((v0 - vm).abs().max()) > 0.1 * float(vm.abs().max())   # really damped
+    assert torch.equal(p0, pexp)
+    # more than VPNET_MAX_POOL times the grid per side (a 16^2 network on 144^2 cells)
+    small = vp.Net(1, 16, 16)
+    small.vpnet_set_params(torch.full((small.nparam,), 0.01, dtype=torch.float32, device="cuda"))
+    fine = vp.context_for(inputs.synthetic(16 * (vp.VPNET_MAX_POOL + 1), 5))
     vf = torch.full(fine.node_shape, 7.0, dtype=torch.float64, device="cuda")
     pf = torch.full(fine.pi_shape, 7.0, dtype=torch.float64, device="cuda")
-    assert ws.start(fine, vf, pf, ("learned", "zero")) == "zero"
+    assert small.vpnet_infer(fine, ("learned", "zero"), vf, pf) == "zero"
     assert torch.count_nonzero(vf) == 0 and torch.count_nonzero(pf) == 0
     with pytest.raises(vp.VPError) as e:
-        ws.start(fine, vf, pf, ("learned",))
+        small.vpnet_infer(fine, ("learned",), vf, pf)
     assert e.value.code == vp.VP_EINVAL
     bad = vp.context_for(inputs.synthetic(300, 5))
     vb = torch.empty(bad.node_shape, dtype=torch.float64, device="cuda")
