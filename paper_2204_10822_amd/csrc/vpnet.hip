@@ -17,6 +17,15 @@
 #include <memory>
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// eight consecutive BF16 values of an LDS row (8-byte aligned: two 8-byte loads)
+__device__ __forceinline__ v8bf lds_frag8(const short* p) {
+  const v4s lo = *reinterpret_cast<const v4s*>(p), hi = *reinterpret_cast<const v4s*>(p + 4);
+  const v8s v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(v8bf, v);
+}
 typedef float v4f __attribute__((ext_vector_type(4)));
 using bf16 = __hip_bfloat16;
 
@@ -26,11 +35,12 @@ namespace net {
 // ---------------------------------------------------------------------------
 // GEMM on the matrix cores.  A is [M][K] (lda) or, with AT, [K][M]; B is [K][N]
 // or, with BT, [N][K].  Workgroup tile 64x64, K step 32, four waves each owning a
-// 32x32 quadrant computed as 2x2 MFMA 16x16x16 tiles.
+// 32x32 quadrant computed as 2x2 tiles of the 16x16x32 BF16 MFMA (gfx950's
+// double-K form: one instruction per 32-deep K step).
 // Epilogue: OUT_BF16 stores relu?(C + bias) in BF16; otherwise FP32 C (+ bias) is
 // stored to C32 + split*M*ldc (split-K partial when gridDim.z > 1).
 // ---------------------------------------------------------------------------
-constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int BM = 64, BN = 64, BK = 32, KPAD = 4;   // LDS rows padded to 72 B (fewer bank conflicts than 80)
 
 __device__ __forceinline__ short bf_bits(bf16 x) {
   short s;
@@ -44,7 +54,7 @@ __device__ __forceinline__ short bf_bits(bf16 x) {
 // one 16-byte load when the ld is a multiple of 8 and the vector is in bounds.
 template <bool KMAJOR>
 __device__ __forceinline__ void stage_tile(const bf16* __restrict__ X, int rows, int kend, int ld, int r0, int k0,
-                                           short (*T)[BK + 4], int tid) {
+                                           short (*T)[BK + KPAD], int tid) {
   const unsigned short* Xs = reinterpret_cast<const unsigned short*>(X);
   if (!KMAJOR) {
     const int r = tid >> 2, c = (tid & 3) * 8;
@@ -86,8 +96,8 @@ __global__ void __launch_bounds__(256)
 k_gemm(const bf16* __restrict__ A, const bf16* __restrict__ B, int M, int N, int K, int lda, int ldb,
        const float* __restrict__ bias, int relu, bf16* __restrict__ Cb, float* __restrict__ C32, int ldc,
        int k_per_split) {
-  __shared__ short As[BM][BK + 4];   // [m][k]
-  __shared__ short Bs[BN][BK + 4];   // [n][k] (B kept transposed: fragments are contiguous)
+  __shared__ short As[BM][BK + KPAD];   // [m][k]
+  __shared__ short Bs[BN][BK + KPAD];   // [n][k] (B kept transposed: fragments are contiguous)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int kbeg = blockIdx.z * k_per_split;
@@ -103,25 +113,25 @@ k_gemm(const bf16* __restrict__ A, const bf16* __restrict__ B, int M, int N, int
     stage_tile<AT>(A, M, kend, lda, m0, k0, As, tid);
     stage_tile<!BT>(B, N, kend, ldb, n0, k0, Bs, tid);
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      v4s af[2], bfr[2];
-      const int kq = kk + 4 * (lane >> 4);
+    {
+      // lane: row (A) or column (B) lane % 16, k = 8 (lane / 16) .. + 7 of the step
+      v8bf af[2], bfr[2];
+      const int kq = 8 * (lane >> 4);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int row = wm + 16 * i + (lane & 15);
-        af[i] = *reinterpret_cast<const v4s*>(&As[row][kq]);
+        af[i] = lds_frag8(&As[row][kq]);
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int col = wn + 16 * j + (lane & 15);
-        bfr[j] = *reinterpret_cast<const v4s*>(&Bs[col][kq]);
+        bfr[j] = lds_frag8(&Bs[col][kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
