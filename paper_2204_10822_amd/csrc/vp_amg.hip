@@ -1955,9 +1955,9 @@ __global__ void k_tentative(int nxn, int nyn, int ncx, int ncy, const double* __
 
 // Per-workgroup max of the Gershgorin bound of D^{-1} A (block Jacobi):
 // max over rows of sum over blocks of |D^{-1} A_nm| row sums.
-template <int B>
+template <int B, typename TM = double>
 __global__ void __launch_bounds__(kBlock)
-k_gershgorin(const double* __restrict__ A, size_t nn, int nxn, int nyn, double* __restrict__ partials) {
+k_gershgorin(const TM* __restrict__ A, size_t nn, int nxn, int nyn, double* __restrict__ partials) {
   __shared__ double lds[16];
   const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double best = 0.0;
@@ -2887,7 +2887,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       VP_LAUNCH_CHECK();
       continue;
     }
-    if (L.B == 2)
+    if (l == 0 && fine32)   // the bound from the FP32 copy (half the bytes)
+      hipLaunchKernelGGL((k_gershgorin<2, float>), dim3(g), dim3(kBlock), 0, s, (const float*)L.A32, L.nn, L.nxn,
+                         L.nyn, c->partials);
+    else if (L.B == 2)
       hipLaunchKernelGGL(k_gershgorin<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, c->partials);
     else
       hipLaunchKernelGGL(k_gershgorin<3>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, c->partials);
