@@ -149,7 +149,11 @@ typedef struct {
                             FP16 Jacobi-scaled on every level;
                             FP16 Jacobi-scaled finest smoothing with the residual
                             after the coarse-grid correction in FP32, and FP32
-                            Jacobi-scaled coarse levels                            */
+                            Jacobi-scaled coarse levels.  In the FP32 and FP32 +
+                            BF16-coarse modes the first coarse operator is the
+                            Galerkin product of the FP32 finest operator and
+                            prolongator (A P accumulated in FP32, the coarse sums
+                            in FP64); every other product is FP64               */
   double cheb_ratio;     /* smoothing interval [lmax/ratio, lmax]                  */
   double omega_scale;    /* prolongator damping scale (1 = 4/(3 lmax))             */
   int kind;              /* VP_AMG_SA or VP_AMG_RS                                 */

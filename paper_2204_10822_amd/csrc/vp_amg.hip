@@ -2164,23 +2164,27 @@ k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
 // coarse nodes J = agg(i) + (qx-1, qy-1), q = qy*3 + qx in 0..8 (A P vanishes for
 // every other J: the prolongator columns of k's neighbours reach at most one
 // aggregate further).  W[((q*B + r)*3 + c)*nw + gw_index(i)], nw = gw_size, zero
-// where J is absent.
-template <int B>
-__device__ __forceinline__ void galerkin_ap_compute(const double* __restrict__ A, size_t nn, int nxn, int nyn,
-                                                    int ncx, int ncy, const double* __restrict__ P, int i, int j,
-                                                    double (&w)[9][B][3]) {
+// where J is absent.  TM is the operator's and prolongator's storage type and TW
+// that of W, which is also the accumulation type: FP64 throughout, or, in the modes
+// whose finest level runs in FP32, the FP32 copies of A and P the V-cycle applies
+// with W accumulated and stored in FP32 (half the bytes of the product's largest
+// pass; the coarse sums of the second pass stay FP64).
+template <int B, typename TM, typename TW>
+__device__ __forceinline__ void galerkin_ap_compute(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
+                                                    int ncx, int ncy, const TM* __restrict__ P, int i, int j,
+                                                    TW (&w)[9][B][3]) {
   const int ax = agg_of(i, ncx), ay = agg_of(j, ncy);
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) w[q][r][c] = 0.0;
+      for (int c = 0; c < 3; ++c) w[q][r][c] = (TW)0;
 #pragma unroll
   for (int d = 0; d < 9; ++d) {
     const int ii = i + kDI[d], jj = j + kDJ[d];
     if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
-    double blk[B][B];
+    TW blk[B][B];
     load_block<B>(A, nn, nxn, i, j, d, blk);
     const size_t m = (size_t)jj * nxn + ii;
 #pragma unroll
@@ -2196,7 +2200,7 @@ __device__ __forceinline__ void galerkin_ap_compute(const double* __restrict__ A
         for (int k = 0; k < B; ++k)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double pv = P[pidx(B, nn, sl, m, k, c)];
+            const TW pv = (TW)P[pidx(B, nn, sl, m, k, c)];
 #pragma unroll
             for (int r = 0; r < B; ++r) w[qy * 3 + qx][r][c] += blk[r][k] * pv;
           }
@@ -2210,14 +2214,14 @@ __device__ __forceinline__ void galerkin_ap_compute(const double* __restrict__ A
 // wave.  Measured against the alternatives at 2049^2: threads in the order of W
 // (loads three nodes apart) and a row-order tile transposed through LDS before the
 // stores were both slower.
-template <int B>
+template <int B, typename TM = double, typename TW = double>
 __global__ void __launch_bounds__(kBlock)
-k_galerkin_ap(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
-              const double* __restrict__ P, double* __restrict__ W) {
+k_galerkin_ap(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
+              const TM* __restrict__ P, TW* __restrict__ W) {
   const size_t n = (size_t)xcd_block() * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int i = (int)(n % nxn), j = (int)(n / nxn);
-  double w[9][B][3];
+  TW w[9][B][3];
   galerkin_ap_compute<B>(A, nn, nxn, nyn, ncx, ncy, P, i, j, w);
   const size_t nw = gw_size(nxn, nyn, ncx, ncy), gi = gw_index(i, j, nxn, nyn, ncx, ncy);
 #pragma unroll
@@ -2237,9 +2241,9 @@ k_galerkin_ap(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx
 // tiles are dealt to the XCDs in contiguous runs (xcd_block), so a tile's
 // neighbours above and below mostly share its L2 too.
 constexpr int kPtwTX = 64, kPtwTY = 4;
-template <int B>
+template <int B, typename TM = double, typename TW = double>
 __global__ void __launch_bounds__(kPtwTX * kPtwTY)
-k_galerkin_ptw(const double* __restrict__ P, const double* __restrict__ W, size_t nn, int nxn, int nyn,
+k_galerkin_ptw(const TM* __restrict__ P, const TW* __restrict__ W, size_t nn, int nxn, int nyn,
                int ncx, int ncy, double* __restrict__ Ac) {
   const size_t ncn = (size_t)ncx * ncy;
   const int ntx = (ncx + kPtwTX - 1) / kPtwTX;
@@ -2275,7 +2279,7 @@ k_galerkin_ptw(const double* __restrict__ P, const double* __restrict__ W, size_
 #pragma unroll
       for (int r = 0; r < B; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) PI[r][c] = P[pidx(B, nn, sl, n, r, c)];
+        for (int c = 0; c < 3; ++c) PI[r][c] = (double)P[pidx(B, nn, sl, n, r, c)];
 #pragma unroll
       for (int t = 0; t < 5; ++t) {
         const int qx = tJx[t] - ax + 1, qy = tJy[t] - ay + 1;
@@ -2285,7 +2289,7 @@ k_galerkin_ptw(const double* __restrict__ P, const double* __restrict__ W, size_
         for (int k = 0; k < B; ++k)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double wv = W[(size_t)((q * B + k) * 3 + c) * nw + gi];
+            const double wv = (double)W[(size_t)((q * B + k) * 3 + c) * nw + gi];
 #pragma unroll
             for (int a = 0; a < 3; ++a) acc[t][a][c] += PI[k][a] * wv;
           }
@@ -2935,9 +2939,12 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       VP_LAUNCH_CHECK();
       if (its & 1) std::swap(L.pv0, L.pv1);  // keep the latest iterate in pv0
     }
-    // the FP32 mode's FP32 prolongator is written by the smoothing itself
+    // the FP32 mode's FP32 prolongator is written by the smoothing itself; the
+    // BF16-coarse mode's finest one too, for the FP32 Galerkin product below (its
+    // scaled copy for the V-cycle overwrites it once the coarse diagonal is known)
     float* p32 = nullptr;
-    if (precision == VP_PREC_FP32) {
+    const bool gal32 = l == 0 && fine32;
+    if (precision == VP_PREC_FP32 || gal32) {
       if (!L.P32) L.P32 = dalloc<float>((size_t)4 * L.B * 3 * L.nn);
       p32 = L.P32;
     }
@@ -2952,7 +2959,13 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     const size_t ptw_tiles = (size_t)((L.ncx + kPtwTX - 1) / kPtwTX) * ((L.ncy + kPtwTY - 1) / kPtwTY);
     const unsigned gc = grid_for(ptw_tiles, 1);   // one workgroup per tile, a multiple of 8
     double* Wap = galerkin_work(c);
-    if (L.B == 2) {
+    if (gal32) {
+      hipLaunchKernelGGL((k_galerkin_ap<2, float, float>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s,
+                         (const float*)L.A32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const float*)L.P32, (float*)Wap);
+      VP_LAUNCH_CHECK();
+      hipLaunchKernelGGL((k_galerkin_ptw<2, float, float>), dim3(gc), dim3(kPtwTX * kPtwTY), 0, s,
+                         (const float*)L.P32, (const float*)Wap, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
+    } else if (L.B == 2) {
       hipLaunchKernelGGL(k_galerkin_ap<2>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx,
                          L.ncy, L.P64, Wap);
       VP_LAUNCH_CHECK();

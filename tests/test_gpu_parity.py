@@ -320,15 +320,20 @@ def _prolongator_matrix(P, nxn, nyn, B):
     return M, np.concatenate(absent)
 
 
-@pytest.mark.parametrize("nx,ny,seed", [(64, 48, 5), (100, 37, 4)])
-def test_galerkin_coarse_operators(vp, nx, ny, seed):
+@pytest.mark.parametrize("nx,ny,seed,prec", [(64, 48, 5, 0), (100, 37, 4, 0), (100, 37, 4, 1), (64, 48, 5, 2)])
+def test_galerkin_coarse_operators(vp, nx, ny, seed, prec):
     """Every coarse operator equals P^T A P of the level above (exported through the
     C ABI and multiplied on the host), empty coarse dofs aside (unit diagonal), and
-    prolongator entries of absent slots are zero."""
+    prolongator entries of absent slots are zero.  In the FP32 and FP32 +
+    BF16-coarse modes the first product takes the FP32 copies of the finest A and
+    P, with A P accumulated in FP32: FP32 rounding of inputs and of about 18-term
+    sums, times the cancellation of P^T A P, bounded here by 1e-5 relative; every
+    later product is FP64."""
     w, prob, ctx = _case(vp, nx, ny, seed)
     v = O.newton_solve(prob, maxit=2).v
     ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
     n, a, k = vp.default_opts()
+    a.precision = prec
     ctx.vp_amg_setup(a)
     levels = ctx.vp_amg_info()
     print(f"[galerkin] levels {levels}", flush=True)
@@ -351,8 +356,8 @@ def test_galerkin_coarse_operators(vp, nx, ny, seed):
         cx, cy, cB = levels[l + 1]
         Ac = _stencil_matrix(mats[l + 1][0], cx, cy, cB).toarray()
         err = np.linalg.norm(Ac - G) / np.linalg.norm(G)
-        print(f"[galerkin] level {l}->{l + 1}: rel err {err:.2e}", flush=True)
-        assert err < 1e-12
+        print(f"[galerkin] prec {prec} level {l}->{l + 1}: rel err {err:.2e}", flush=True)
+        assert err < (1e-5 if (l == 0 and prec in (1, 2)) else 1e-12)
 
 
 _VC_CASES = {}
