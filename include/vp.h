@@ -188,7 +188,9 @@ int vp_amg_info(vp_ctx ctx, int* levels, int* nxn, int* nyn, int* dofs_per_node)
  *    coarse dof c) for the coarse node in slot s = sx + 2*sy.  Along x, sx = 0
  *    names the aggregate holding the node (aggregates are runs of 3 nodes, the
  *    last run 3..5) and sx = 1 the neighbouring aggregate that a run's first or
- *    last node also touches; the same along y.  Absent slots hold 0.
+ *    last node also touches; the same along y.  Absent slots hold 0.  On the
+ *    finest level of the FP32 and FP32 + BF16-coarse modes the prolongator is
+ *    made in FP32 only (from the FP32 operator): its values widened to FP64.
  * Asynchronous on the context's stream.  VP_ESTATE before vp_amg_setup; VP_EINVAL
  * for a level out of range or P asked for on the coarsest level. */
 int vp_amg_export(vp_ctx ctx, int level, double* A, double* P);

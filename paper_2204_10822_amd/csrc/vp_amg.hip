@@ -2109,10 +2109,13 @@ __global__ void k_finish_max(const double* __restrict__ partials, int nblocks, d
   if (threadIdx.x == 0) out[0] = lds[0];
 }
 
-// Smoothed prolongator P = (I - omega D^{-1} A) Ptent, omega = omega_scale * 4/(3 lmax)
-template <int B>
+// Smoothed prolongator P = (I - omega D^{-1} A) Ptent, omega = omega_scale * 4/(3 lmax),
+// computed in FP64 and stored in FP64 (P), FP32 (P32) or both.  TM = float: from the
+// FP32 copy of the operator (the finest level of the FP32 modes, whose V-cycle and
+// first Galerkin product use the FP32 prolongator only).
+template <int B, typename TM = double>
 __global__ void __launch_bounds__(kBlock)
-k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
+k_smooth_p(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
            const double* __restrict__ Ptent, const double* __restrict__ lmax, double omega_scale,
            double* __restrict__ P, float* __restrict__ P32) {
   const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2124,35 +2127,55 @@ k_smooth_p(const double* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, i
   invert_block<B>(D, Di);
   const int ax[2] = {agg_of(i, ncx), agg_other(i, nxn, ncx)};
   const int ay[2] = {agg_of(j, ncy), agg_other(j, nyn, ncy)};
-  for (int s = 0; s < 4; ++s) {
-    const int Jx = ax[s & 1], Jy = ay[s >> 1];
-    double acc[B][3];
+  // (A Ptent) restricted to each slot's aggregate: every neighbour lies in the
+  // node's own aggregate or the adjacent one along each axis, so one pass over the
+  // nine neighbours adds each term to its slot (in the order of d, per slot)
+  double acc[4][B][3];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
     for (int r = 0; r < B; ++r)
-      for (int c = 0; c < 3; ++c) acc[r][c] = 0.0;
-    if (Jx >= 0 && Jy >= 0) {
-      for (int d = 0; d < 9; ++d) {
-        const int ii = i + kDI[d], jj = j + kDJ[d];
-        if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
-        if (agg_of(ii, ncx) != Jx || agg_of(jj, ncy) != Jy) continue;
-        double blk[B][B];
-        load_block<B>(A, nn, nxn, i, j, d, blk);
-        const size_t m = (size_t)jj * nxn + ii;
-        for (int r = 0; r < B; ++r)
-          for (int k = 0; k < B; ++k) {
-            const double a = blk[r][k];
-            for (int c = 0; c < 3; ++c) acc[r][c] += a * Ptent[(size_t)(k * 3 + c) * nn + m];
-          }
-      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[sl][r][c] = 0.0;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const int ii = i + kDI[d], jj = j + kDJ[d];
+    if (ii < 0 || jj < 0 || ii >= nxn || jj >= nyn) continue;
+    const int sl = (agg_of(ii, ncx) == ax[0] ? 0 : 1) + (agg_of(jj, ncy) == ay[0] ? 0 : 2);
+    double blk[B][B];
+    load_block<B>(A, nn, nxn, i, j, d, blk);
+    const size_t m = (size_t)jj * nxn + ii;
+    double pt[B][3];
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pt[k][c] = Ptent[(size_t)(k * 3 + c) * nn + m];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (s != sl) continue;
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[s][r][c] += blk[r][k] * pt[k][c];
     }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const bool ok = ax[s & 1] >= 0 && ay[s >> 1] >= 0;
+#pragma unroll
     for (int r = 0; r < B; ++r)
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
         double t = 0.0;
-        for (int k = 0; k < B; ++k) t += Di[r][k] * acc[k][c];
+#pragma unroll
+        for (int k = 0; k < B; ++k) t += Di[r][k] * acc[s][k][c];
         double val = -omega * t;
         if (s == 0) val += Ptent[(size_t)(r * 3 + c) * nn + n];
-        if (Jx < 0 || Jy < 0) val = 0.0;
-        P[pidx(B, nn, s, n, r, c)] = val;
-        if (P32) P32[pidx(B, nn, s, n, r, c)] = (float)val;   // the FP32 mode's copy
+        if (!ok) val = 0.0;
+        if (P) P[pidx(B, nn, s, n, r, c)] = val;
+        if (P32) P32[pidx(B, nn, s, n, r, c)] = (float)val;
       }
   }
 }
@@ -2432,8 +2455,8 @@ __global__ void k_scale_to_16(const double* __restrict__ A, size_t nn, int nxn, 
 }
 
 // P^ = diag(dsc_f) P diag(1/dsc_c) in FP32 (dsc_f = null: no row scaling, finest level)
-template <int B>
-__global__ void k_scale_p(const double* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
+template <int B, typename TP = double>
+__global__ void k_scale_p(const TP* __restrict__ P, size_t nn, int nxn, int nyn, int ncx, int ncy,
                           const double* __restrict__ dsc_f, const double* __restrict__ dsc_c,
                           float* __restrict__ Ps) {
   const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2449,7 +2472,7 @@ __global__ void k_scale_p(const double* __restrict__ P, size_t nn, int nxn, int 
       for (int c = 0; c < 3; ++c) {
         const size_t k = pidx(B, nn, s, n, r, c);
         const double fr = dsc_f ? dsc_f[n * B + r] : 1.0;
-        Ps[k] = ok ? (float)(fr * P[k] / dsc_c[J * 3 + c]) : 0.0f;
+        Ps[k] = ok ? (float)(fr * (double)P[k] / dsc_c[J * 3 + c]) : 0.0f;
       }
   }
 }
@@ -2613,6 +2636,17 @@ void convert(hipStream_t s, const TS* src, TD* dst, size_t n) {
 
 }  // namespace
 
+// The smoothed prolongator of a level in FP64 (12*B*nn values): the FP64 one, or
+// the FP32 one widened where only that exists (finest level of the FP32 modes).
+void amg_export_p(vp_ctx c, int level, double* P) {
+  const Level& L = c->lev[level];
+  const size_t np = (size_t)12 * L.B * L.nn;
+  if (L.p64_stale)
+    launch_cast(c->stream, (const float*)(c->amg_prec == VP_PREC_FP32_BF16COARSE ? L.P32u : L.P32), P, np);
+  else
+    VP_HIP(hipMemcpyAsync(P, L.P64, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+}
+
 void amg_free(vp_ctx c) {
   for (int l = 0; l < kMaxLevels; ++l) {
     Level& L = c->lev[l];
@@ -2621,6 +2655,7 @@ void amg_free(vp_ctx c) {
     dfree(L.Ptent);
     dfree(L.P64);
     dfree(L.P32);
+    dfree(L.P32u);
     dfree(L.Ph);
     dfree(L.Bnull);
     dfree(L.lmax);
@@ -2759,7 +2794,10 @@ void bf16_copies(vp_ctx c, hipStream_t s, int finest, int coarse) {
     const size_t np = (size_t)4 * L.B * 3 * L.nn;
     if (!L.P32) L.P32 = dalloc<float>(np);
     const unsigned g = (unsigned)((L.nn + 255) / 256);
-    if (L.B == 2)
+    if (L.p64_stale)   // the finest prolongator of the FP32 + BF16-coarse mode exists in FP32 only
+      hipLaunchKernelGGL((k_scale_p<2, float>), dim3(g), dim3(256), 0, s, (const float*)L.P32u, L.nn, L.nxn, L.nyn,
+                         L.ncx, L.ncy, (const double*)nullptr, (const double*)N.dsc64, L.P32);
+    else if (L.B == 2)
       hipLaunchKernelGGL(k_scale_p<2>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          (const double*)(finest_scaled ? L.dsc64 : nullptr), (const double*)N.dsc64, L.P32);
     else
@@ -2875,6 +2913,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     if (!L0.A32) L0.A32 = dalloc<float>(na);
     convert(s, L0.A64, L0.A32, na);
   }
+  for (int l = 0; l < c->nlev; ++l) c->lev[l].p64_stale = false;
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const unsigned g = (unsigned)((L.nn + kBlock - 1) / kBlock);
@@ -2939,16 +2978,23 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       VP_LAUNCH_CHECK();
       if (its & 1) std::swap(L.pv0, L.pv1);  // keep the latest iterate in pv0
     }
-    // the FP32 mode's FP32 prolongator is written by the smoothing itself; the
-    // BF16-coarse mode's finest one too, for the FP32 Galerkin product below (its
-    // scaled copy for the V-cycle overwrites it once the coarse diagonal is known)
+    // The FP32 mode's FP32 prolongator is written by the smoothing itself.  On the
+    // finest level of the FP32 modes only the FP32 prolongator is made, from the FP32
+    // operator: the V-cycle and the first Galerkin product read nothing else (the
+    // BF16-coarse mode keeps it unscaled in P32u; its scaled copy for the V-cycle is
+    // made once the coarse diagonal is known).
     float* p32 = nullptr;
     const bool gal32 = l == 0 && fine32;
+    float*& pdst = gal32 && precision == VP_PREC_FP32_BF16COARSE ? L.P32u : L.P32;
     if (precision == VP_PREC_FP32 || gal32) {
-      if (!L.P32) L.P32 = dalloc<float>((size_t)4 * L.B * 3 * L.nn);
-      p32 = L.P32;
+      if (!pdst) pdst = dalloc<float>((size_t)4 * L.B * 3 * L.nn);
+      p32 = pdst;
     }
-    if (L.B == 2)
+    L.p64_stale = gal32;
+    if (gal32)
+      hipLaunchKernelGGL((k_smooth_p<2, float>), dim3(g), dim3(kBlock), 0, s, (const float*)L.A32, L.nn, L.nxn, L.nyn,
+                         L.ncx, L.ncy, L.Ptent, L.lmax, omega_scale, (double*)nullptr, p32);
+    else if (L.B == 2)
       hipLaunchKernelGGL(k_smooth_p<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          L.Ptent, L.lmax, omega_scale, L.P64, p32);
     else
@@ -2961,10 +3007,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     double* Wap = galerkin_work(c);
     if (gal32) {
       hipLaunchKernelGGL((k_galerkin_ap<2, float, float>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s,
-                         (const float*)L.A32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const float*)L.P32, (float*)Wap);
+                         (const float*)L.A32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const float*)p32, (float*)Wap);
       VP_LAUNCH_CHECK();
       hipLaunchKernelGGL((k_galerkin_ptw<2, float, float>), dim3(gc), dim3(kPtwTX * kPtwTY), 0, s,
-                         (const float*)L.P32, (const float*)Wap, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
+                         (const float*)p32, (const float*)Wap, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
     } else if (L.B == 2) {
       hipLaunchKernelGGL(k_galerkin_ap<2>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx,
                          L.ncy, L.P64, Wap);

@@ -8,6 +8,7 @@
 
 namespace vp {
 void amg_free(vp_ctx c);
+void amg_export_p(vp_ctx c, int level, double* P);
 void amg_build_structure(vp_ctx c, double* K, int max_coarse);
 void amg_setup_numeric(vp_ctx c, int precision, double omega_scale);
 void amg_apply(vp_ctx c, const double* r, double* z);
@@ -674,9 +675,7 @@ int vp_amg_export(vp_ctx c, int level, double* A, double* P) {
     if (A)
       VP_HIP(hipMemcpyAsync(A, L.A64, (size_t)5 * L.B * L.B * L.nn * sizeof(double), hipMemcpyDeviceToDevice,
                             c->stream));
-    if (P)
-      VP_HIP(hipMemcpyAsync(P, L.P64, (size_t)12 * L.B * L.nn * sizeof(double), hipMemcpyDeviceToDevice,
-                            c->stream));
+    if (P) amg_export_p(c, level, P);
     return VP_OK;
   });
 }

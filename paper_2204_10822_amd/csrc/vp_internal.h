@@ -157,6 +157,8 @@ struct Level {
   double* Ptent = nullptr;       // [B*3][nn]  own-aggregate tentative block per node
   double* P64 = nullptr;         // [4 slots][B*3][nn] smoothed prolongator
   float* P32 = nullptr;
+  float* P32u = nullptr;         // unscaled FP32 prolongator (finest level, FP32 + BF16-coarse mode)
+  bool p64_stale = false;        // finest level of the FP32 modes: the prolongator exists in FP32 only
   double* Bnull = nullptr;       // near-null space at this level [B*3][nn] (levels >= 1)
   double* lmax = nullptr;        // device scalar: bound on lmax(D^-1 A)
   double* pv0 = nullptr;         // power-iteration vectors (FP64, B*nn), warm across setups

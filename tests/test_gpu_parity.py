@@ -360,6 +360,38 @@ def test_galerkin_coarse_operators(vp, nx, ny, seed, prec):
         assert err < (1e-5 if (l == 0 and prec in (1, 2)) else 1e-12)
 
 
+def test_fp32_finest_prolongator_close_to_fp64(vp):
+    """The FP32 modes smooth the finest prolongator from the FP32 operator and keep
+    it in FP32 only (exported widened): it matches the FP64 mode's to FP32 rounding
+    (fresh contexts, so the spectral estimates start alike), and the coarser
+    prolongators, made in FP64 from the first coarse operator, match to the
+    latter's difference."""
+    nx, ny, seed = 100, 37, 4
+    outs = {}
+    for prec in (0, 1, 2):
+        w, prob, ctx = _case(vp, nx, ny, seed)
+        v = O.newton_solve(prob, maxit=2).v
+        ctx.vp_newton_assemble(_dev(v.reshape(-1, 2)), _dev(prob.pi_consistent(v)), vp.VP_SVN)
+        n, a, k = vp.default_opts()
+        a.precision = prec
+        ctx.vp_amg_setup(a)
+        levels = ctx.vp_amg_info()
+        Ps = []
+        for l in range(2):
+            nxn, nyn, B = levels[l]
+            Pt = torch.zeros(12 * B * nxn * nyn, dtype=torch.float64, device="cuda")
+            ctx.vp_amg_export(l, None, Pt)
+            Ps.append(_host(Pt))
+        outs[prec] = Ps
+    for prec in (1, 2):
+        d0 = _relerr(outs[prec][0], outs[0][0])
+        d1 = _relerr(outs[prec][1], outs[0][1])
+        f32 = np.array_equal(outs[prec][0], outs[prec][0].astype(np.float32).astype(np.float64))
+        print(f"[prolongator] prec {prec}: finest rel diff {d0:.2e} (FP32 values: {f32}), next {d1:.2e}", flush=True)
+        assert f32 and 0 < d0 < 1e-6
+        assert d1 < 1e-5
+
+
 _VC_CASES = {}
 
 
