@@ -150,10 +150,10 @@ typedef struct {
                             FP16 Jacobi-scaled finest smoothing with the residual
                             after the coarse-grid correction in FP32, and FP32
                             Jacobi-scaled coarse levels.  In the FP32 and FP32 +
-                            BF16-coarse modes the first coarse operator is the
-                            Galerkin product of the FP32 finest operator and
-                            prolongator (A P accumulated in FP32, the coarse sums
-                            in FP64); every other product is FP64               */
+                            BF16-coarse modes the hierarchy is built from FP32
+                            copies: spectral bounds, prolongator smoothing and
+                            the Galerkin products (A P accumulated in FP32, the
+                            coarse sums in FP64) read each level's FP32 operator */
   double cheb_ratio;     /* smoothing interval [lmax/ratio, lmax]                  */
   double omega_scale;    /* prolongator damping scale (1 = 4/(3 lmax))             */
   int kind;              /* VP_AMG_SA or VP_AMG_RS                                 */
@@ -188,9 +188,9 @@ int vp_amg_info(vp_ctx ctx, int* levels, int* nxn, int* nyn, int* dofs_per_node)
  *    coarse dof c) for the coarse node in slot s = sx + 2*sy.  Along x, sx = 0
  *    names the aggregate holding the node (aggregates are runs of 3 nodes, the
  *    last run 3..5) and sx = 1 the neighbouring aggregate that a run's first or
- *    last node also touches; the same along y.  Absent slots hold 0.  On the
- *    finest level of the FP32 and FP32 + BF16-coarse modes the prolongator is
- *    made in FP32 only (from the FP32 operator): its values widened to FP64.
+ *    last node also touches; the same along y.  Absent slots hold 0.  In the
+ *    FP32 and FP32 + BF16-coarse modes the prolongators are made in FP32 only
+ *    (from the FP32 operators): their values widened to FP64.
  * Asynchronous on the context's stream.  VP_ESTATE before vp_amg_setup; VP_EINVAL
  * for a level out of range or P asked for on the coarsest level. */
 int vp_amg_export(vp_ctx ctx, int level, double* A, double* P);

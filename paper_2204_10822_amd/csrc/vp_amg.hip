@@ -2794,9 +2794,13 @@ void bf16_copies(vp_ctx c, hipStream_t s, int finest, int coarse) {
     const size_t np = (size_t)4 * L.B * 3 * L.nn;
     if (!L.P32) L.P32 = dalloc<float>(np);
     const unsigned g = (unsigned)((L.nn + 255) / 256);
-    if (L.p64_stale)   // the finest prolongator of the FP32 + BF16-coarse mode exists in FP32 only
+    if (L.p64_stale && L.B == 2)   // the FP32 + BF16-coarse mode's prolongators exist in FP32 only
       hipLaunchKernelGGL((k_scale_p<2, float>), dim3(g), dim3(256), 0, s, (const float*)L.P32u, L.nn, L.nxn, L.nyn,
-                         L.ncx, L.ncy, (const double*)nullptr, (const double*)N.dsc64, L.P32);
+                         L.ncx, L.ncy, (const double*)(finest_scaled ? L.dsc64 : nullptr), (const double*)N.dsc64,
+                         L.P32);
+    else if (L.p64_stale)
+      hipLaunchKernelGGL((k_scale_p<3, float>), dim3(g), dim3(256), 0, s, (const float*)L.P32u, L.nn, L.nxn, L.nyn,
+                         L.ncx, L.ncy, (const double*)L.dsc64, (const double*)N.dsc64, L.P32);
     else if (L.B == 2)
       hipLaunchKernelGGL(k_scale_p<2>, dim3(g), dim3(256), 0, s, L.P64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          (const double*)(finest_scaled ? L.dsc64 : nullptr), (const double*)N.dsc64, L.P32);
@@ -2903,16 +2907,12 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   hipStream_t s = c->stream;
   const bool q2u = c->order == 2;
   if (c->order == 2) q2_smoother_setup(c, precision);
-  // Modes whose V-cycle smooths the finest level with an FP32 copy of the operator
-  // get that copy first, and the finest level's power steps stream it instead of
-  // the FP64 operator (half the bytes; the bound only needs a few digits).
+  // Modes whose V-cycle smooths with FP32 (or BF16) operators build the hierarchy
+  // from FP32 copies: each level's operator is copied to FP32 as soon as it exists,
+  // and its spectral bounds, smoothed prolongator (kept in FP32 only) and Galerkin
+  // product read that copy (half the bytes).  The coarse operators themselves are
+  // summed in FP64 and kept in FP64 for the next level's copy and the scalings.
   const bool fine32 = c->order == 1 && (precision == VP_PREC_FP32 || precision == VP_PREC_FP32_BF16COARSE);
-  if (fine32) {
-    Level& L0 = c->lev[0];
-    const size_t na = (size_t)20 * L0.nn;
-    if (!L0.A32) L0.A32 = dalloc<float>(na);
-    convert(s, L0.A64, L0.A32, na);
-  }
   for (int l = 0; l < c->nlev; ++l) c->lev[l].p64_stale = false;
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
@@ -2930,9 +2930,17 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       VP_LAUNCH_CHECK();
       continue;
     }
-    if (l == 0 && fine32)   // the bound from the FP32 copy (half the bytes)
-      hipLaunchKernelGGL((k_gershgorin<2, float>), dim3(g), dim3(kBlock), 0, s, (const float*)L.A32, L.nn, L.nxn,
-                         L.nyn, c->partials);
+    const float* A32 = nullptr;
+    if (fine32) {
+      const size_t na = (size_t)5 * L.B * L.B * L.nn;
+      if (!L.A32) L.A32 = dalloc<float>(na);
+      convert(s, L.A64, L.A32, na);
+      A32 = L.A32;
+    }
+    if (A32 && L.B == 2)
+      hipLaunchKernelGGL((k_gershgorin<2, float>), dim3(g), dim3(kBlock), 0, s, A32, L.nn, L.nxn, L.nyn, c->partials);
+    else if (A32)
+      hipLaunchKernelGGL((k_gershgorin<3, float>), dim3(g), dim3(kBlock), 0, s, A32, L.nn, L.nxn, L.nyn, c->partials);
     else if (L.B == 2)
       hipLaunchKernelGGL(k_gershgorin<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, c->partials);
     else
@@ -2962,15 +2970,19 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       for (int k = 0; k < its; ++k) {
         double* xin = (k & 1) ? L.pv1 : L.pv0;
         double* yout = (k & 1) ? L.pv0 : L.pv1;
-        if (l == 0 && fine32)
-          hipLaunchKernelGGL((k_power_step<2, 0, float>), dim3(g), dim3(kBlock), 0, s, (const float*)L.A32, L.nn,
-                             L.nxn, L.nyn, xin, L.pnrm + (k & 1), yout, c->partials);
+        const double* nrm = L.pnrm + (k & 1);
+        if (A32 && L.B == 2)
+          hipLaunchKernelGGL((k_power_step<2, 0, float>), dim3(g), dim3(kBlock), 0, s, A32, L.nn, L.nxn, L.nyn, xin,
+                             nrm, yout, c->partials);
+        else if (A32)
+          hipLaunchKernelGGL((k_power_step<3, 0, float>), dim3(g), dim3(kBlock), 0, s, A32, L.nn, L.nxn, L.nyn, xin,
+                             nrm, yout, c->partials);
         else if (L.B == 2)
-          hipLaunchKernelGGL(k_power_step<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, xin,
-                             L.pnrm + (k & 1), yout, c->partials);
+          hipLaunchKernelGGL(k_power_step<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, xin, nrm, yout,
+                             c->partials);
         else
-          hipLaunchKernelGGL(k_power_step<3>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, xin,
-                             L.pnrm + (k & 1), yout, c->partials);
+          hipLaunchKernelGGL(k_power_step<3>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, xin, nrm, yout,
+                             c->partials);
         VP_LAUNCH_CHECK();
         launch_finish_sum(s, c->partials, (int)g, 1, L.pnrm + ((k + 1) & 1));
       }
@@ -2978,22 +2990,24 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       VP_LAUNCH_CHECK();
       if (its & 1) std::swap(L.pv0, L.pv1);  // keep the latest iterate in pv0
     }
-    // The FP32 mode's FP32 prolongator is written by the smoothing itself.  On the
-    // finest level of the FP32 modes only the FP32 prolongator is made, from the FP32
-    // operator: the V-cycle and the first Galerkin product read nothing else (the
-    // BF16-coarse mode keeps it unscaled in P32u; its scaled copy for the V-cycle is
-    // made once the coarse diagonal is known).
+    // The FP32 mode's FP32 prolongator is written by the smoothing itself.  In the
+    // FP32 modes only the FP32 prolongator is made, from the FP32 operator: the
+    // V-cycle and the Galerkin product read nothing else (the BF16-coarse mode keeps
+    // it unscaled in P32u; its scaled copy for the V-cycle is made once the coarse
+    // diagonal is known).
     float* p32 = nullptr;
-    const bool gal32 = l == 0 && fine32;
-    float*& pdst = gal32 && precision == VP_PREC_FP32_BF16COARSE ? L.P32u : L.P32;
-    if (precision == VP_PREC_FP32 || gal32) {
+    float*& pdst = A32 && precision == VP_PREC_FP32_BF16COARSE ? L.P32u : L.P32;
+    if (precision == VP_PREC_FP32 || A32) {
       if (!pdst) pdst = dalloc<float>((size_t)4 * L.B * 3 * L.nn);
       p32 = pdst;
     }
-    L.p64_stale = gal32;
-    if (gal32)
-      hipLaunchKernelGGL((k_smooth_p<2, float>), dim3(g), dim3(kBlock), 0, s, (const float*)L.A32, L.nn, L.nxn, L.nyn,
-                         L.ncx, L.ncy, L.Ptent, L.lmax, omega_scale, (double*)nullptr, p32);
+    L.p64_stale = A32 != nullptr;
+    if (A32 && L.B == 2)
+      hipLaunchKernelGGL((k_smooth_p<2, float>), dim3(g), dim3(kBlock), 0, s, A32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         L.Ptent, L.lmax, omega_scale, (double*)nullptr, p32);
+    else if (A32)
+      hipLaunchKernelGGL((k_smooth_p<3, float>), dim3(g), dim3(kBlock), 0, s, A32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
+                         L.Ptent, L.lmax, omega_scale, (double*)nullptr, p32);
     else if (L.B == 2)
       hipLaunchKernelGGL(k_smooth_p<2>, dim3(g), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx, L.ncy,
                          L.Ptent, L.lmax, omega_scale, L.P64, p32);
@@ -3005,12 +3019,19 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     const size_t ptw_tiles = (size_t)((L.ncx + kPtwTX - 1) / kPtwTX) * ((L.ncy + kPtwTY - 1) / kPtwTY);
     const unsigned gc = grid_for(ptw_tiles, 1);   // one workgroup per tile, a multiple of 8
     double* Wap = galerkin_work(c);
-    if (gal32) {
-      hipLaunchKernelGGL((k_galerkin_ap<2, float, float>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s,
-                         (const float*)L.A32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, (const float*)p32, (float*)Wap);
+    float* W32 = reinterpret_cast<float*>(Wap);
+    if (A32 && L.B == 2) {
+      hipLaunchKernelGGL((k_galerkin_ap<2, float, float>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A32, L.nn, L.nxn,
+                         L.nyn, L.ncx, L.ncy, (const float*)p32, W32);
       VP_LAUNCH_CHECK();
       hipLaunchKernelGGL((k_galerkin_ptw<2, float, float>), dim3(gc), dim3(kPtwTX * kPtwTY), 0, s,
-                         (const float*)p32, (const float*)Wap, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
+                         (const float*)p32, (const float*)W32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
+    } else if (A32) {
+      hipLaunchKernelGGL((k_galerkin_ap<3, float, float>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A32, L.nn, L.nxn,
+                         L.nyn, L.ncx, L.ncy, (const float*)p32, W32);
+      VP_LAUNCH_CHECK();
+      hipLaunchKernelGGL((k_galerkin_ptw<3, float, float>), dim3(gc), dim3(kPtwTX * kPtwTY), 0, s,
+                         (const float*)p32, (const float*)W32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
     } else if (L.B == 2) {
       hipLaunchKernelGGL(k_galerkin_ap<2>, dim3(grid_for(L.nn)), dim3(kBlock), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.ncx,
                          L.ncy, L.P64, Wap);
@@ -3057,8 +3078,8 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
       const size_t na = (size_t)5 * L.B * L.B * L.nn;
-      if (l > 0) {   // the finest FP32 operator is made first (Q2: the finest level runs on K2_32)
-        if (!L.A32) L.A32 = dalloc<float>(na);
+      if (l > 0 && c->order == 2) {   // order 1: every FP32 operator was made in the loop (Q2: the finest
+        if (!L.A32) L.A32 = dalloc<float>(na);   // level runs on K2_32)
         convert(s, L.A64, L.A32, na);
       }
       if (L.P64 && (c->order == 2 && l == 0)) {   // smoothed prolongators got theirs from k_smooth_p
