@@ -2434,24 +2434,42 @@ __device__ __forceinline__ void store16(__hip_bfloat16* p, double v) { *p = __fl
 __device__ __forceinline__ void store16(_Float16* p, double v) { *p = (_Float16)(float)v; }
 __device__ __forceinline__ void store16(float* p, double v) { *p = (float)v; }
 
-// S = D^{-1/2} A D^{-1/2} stored in 16 bits (BF16 or FP16; same 5-block layout)
+// S = D^{-1/2} A D^{-1/2} stored in 16 bits (BF16 or FP16; same 5-block layout).
+// One thread per stored entry, so consecutive lanes write consecutive values and
+// every store covers whole lines (one thread per node wrote 2 bytes per lane at a
+// stride of B*B entries: partial lines, each fetched before it was written).
+// Entry k = (blk*nn + n)*B*B + r*B + c; the host guarantees 5*B*B*nn < 2^32.
 template <int B, typename T16>
-__global__ void k_scale_to_16(const double* __restrict__ A, size_t nn, int nxn, int nyn,
-                              const double* __restrict__ dsc, T16* __restrict__ S) {
-  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
-  const int i = (int)(n % nxn), j = (int)(n / nxn);
-  for (int blk = 0; blk < 5; ++blk) {
-    const int ii = i + kDI[blk], jj = j + kDJ[blk];
+__global__ void __launch_bounds__(kBlock)
+k_scale_to_16(const double* __restrict__ A, unsigned nn, int nxn, int nyn, const double* __restrict__ dsc,
+              T16* __restrict__ S) {
+  constexpr int DI[5] = {0, 1, 0, 1, -1};
+  constexpr int DJ[5] = {0, 0, 1, 1, 1};
+  const unsigned total = 5u * B * B * nn;
+  for (unsigned k = (unsigned)xcd_block() * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+    const unsigned bn = k / (B * B);   // blk*nn + n
+    const int rc = (int)(k - bn * (B * B));
+    const int r = rc / B, c = rc - r * B;
+    const int blk = (int)(bn / nn);
+    const unsigned n = bn - (unsigned)blk * nn;
+    const int j = (int)(n / (unsigned)nxn), i = (int)(n - (unsigned)j * nxn);
+    int ii = i, jj = j;
+#pragma unroll
+    for (int b = 1; b < 5; ++b)
+      if (blk == b) { ii = i + DI[b]; jj = j + DJ[b]; }
     const bool ok = ii >= 0 && jj >= 0 && ii < nxn && jj < nyn;
     const size_t m = ok ? (size_t)jj * nxn + ii : n;
-    for (int r = 0; r < B; ++r)
-      for (int c = 0; c < B; ++c) {
-        const size_t k = aidx(B, nn, blk, n, r, c);
-        const double v = ok ? A[k] / (dsc[n * B + r] * dsc[m * B + c]) : 0.0;
-        store16(S + k, v);
-      }
+    const double v = ok ? A[k] / (dsc[(size_t)n * B + r] * dsc[m * B + c]) : 0.0;
+    store16(S + k, v);
   }
+}
+template <int B, typename T16>
+void launch_scale_to_16(hipStream_t s, const Level& L, T16* S) {
+  const size_t total = (size_t)5 * B * B * L.nn;
+  if (total >= ((size_t)1 << 32)) throw Error(VP_EINVAL, "operator too large for the 16-bit scaling kernel");
+  hipLaunchKernelGGL((k_scale_to_16<B, T16>), dim3(grid_for(total)), dim3(kBlock), 0, s, (const double*)L.A64,
+                     (unsigned)L.nn, L.nxn, L.nyn, (const double*)L.dsc64, S);
+  VP_LAUNCH_CHECK();
 }
 
 // P^ = diag(dsc_f) P diag(1/dsc_c) in FP32 (dsc_f = null: no row scaling, finest level)
@@ -2764,27 +2782,21 @@ void bf16_copies(vp_ctx c, hipStream_t s, int finest, int coarse) {
     if (l > 0 && coarse == 2) {
       if (!L.A32) L.A32 = dalloc<float>(na);
       if (L.B == 2)
-        hipLaunchKernelGGL((k_scale_to_16<2, float>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
-                           L.A32);
+        launch_scale_to_16<2>(s, L, L.A32);
       else
-        hipLaunchKernelGGL((k_scale_to_16<3, float>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
-                           L.A32);
+        launch_scale_to_16<3>(s, L, L.A32);
     } else if ((l == 0 && finest == 2) || (l > 0 && coarse_fp16)) {
       if (!L.Ah) L.Ah = dalloc<_Float16>(na);
       if (L.B == 2)
-        hipLaunchKernelGGL((k_scale_to_16<2, _Float16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
-                           L.Ah);
+        launch_scale_to_16<2>(s, L, L.Ah);
       else
-        hipLaunchKernelGGL((k_scale_to_16<3, _Float16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn, L.dsc64,
-                           L.Ah);
+        launch_scale_to_16<3>(s, L, L.Ah);
     } else {
       if (!L.Abf) L.Abf = dalloc<__hip_bfloat16>(na);
       if (L.B == 2)
-        hipLaunchKernelGGL((k_scale_to_16<2, __hip_bfloat16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn,
-                           L.dsc64, L.Abf);
+        launch_scale_to_16<2>(s, L, L.Abf);
       else
-        hipLaunchKernelGGL((k_scale_to_16<3, __hip_bfloat16>), dim3(g), dim3(256), 0, s, L.A64, L.nn, L.nxn, L.nyn,
-                           L.dsc64, L.Abf);
+        launch_scale_to_16<3>(s, L, L.Abf);
     }
     VP_LAUNCH_CHECK();
   }
@@ -3070,8 +3082,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
       Level& L0 = c->lev[0];
       const size_t na0 = (size_t)20 * L0.nn;
       if (!L0.A32) L0.A32 = dalloc<float>(na0);
-      hipLaunchKernelGGL((k_scale_to_16<2, float>), dim3((unsigned)((L0.nn + 255) / 256)), dim3(256), 0, s, L0.A64,
-                         L0.nn, L0.nxn, L0.nyn, L0.dsc64, L0.A32);
+      launch_scale_to_16<2>(s, L0, L0.A32);
       VP_LAUNCH_CHECK();
     }
   } else if (precision != VP_PREC_FP64) {
