@@ -2482,15 +2482,26 @@ __global__ void k_scale_p(const TP* __restrict__ P, size_t nn, int nxn, int nyn,
   const int i = (int)(n % nxn), j = (int)(n / nxn);
   const int ax[2] = {agg_of(i, ncx), agg_other(i, nxn, ncx)};
   const int ay[2] = {agg_of(j, ncy), agg_other(j, nyn, ncy)};
+  // every load is unconditional (an absent slot reads coarse node 0 and stores 0),
+  // so a thread's loads are all in flight at once
+  double fr[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) fr[r] = dsc_f ? dsc_f[n * B + r] : 1.0;
+#pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int Jx = ax[s & 1], Jy = ay[s >> 1];
     const bool ok = Jx >= 0 && Jy >= 0;
     const size_t J = ok ? (size_t)Jy * ncx + Jx : 0;
+    double dc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dc[c] = dsc_c[J * 3 + c];
+#pragma unroll
     for (int r = 0; r < B; ++r)
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
         const size_t k = pidx(B, nn, s, n, r, c);
-        const double fr = dsc_f ? dsc_f[n * B + r] : 1.0;
-        Ps[k] = ok ? (float)(fr * (double)P[k] / dsc_c[J * 3 + c]) : 0.0f;
+        const float v = (float)(fr[r] * (double)P[k] / dc[c]);
+        Ps[k] = ok ? v : 0.0f;
       }
   }
 }
