@@ -2255,6 +2255,57 @@ k_galerkin_ap(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, in
       for (int c = 0; c < 3; ++c) W[(size_t)((q * B + r) * 3 + c) * nw + gi] = w[q][r][c];
 }
 
+// Pass 1 with threads in the order of W, for FP32 W: a workgroup of three waves
+// takes 64 aggregates of one fine row, wave w the nodes at position w in them, so
+// each store writes 64 consecutive values of a class plane (whole lines: a partial
+// line is fetched before it is written); the loads are three nodes apart and the
+// three waves share their lines.  Per row, one more workgroup takes the nodes past
+// the last full run of 3 (positions 3 and 4 of a longer last run), and the rows past
+// the last full run in y go in row order (their W entries are stored in row order).
+// Workgroups are numbered row by row and dealt to the XCDs in contiguous runs.
+constexpr int kApWThreads = 192;
+template <int B, typename TM, typename TW>
+__global__ void __launch_bounds__(kApWThreads)
+k_galerkin_ap_w(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy, int gx,
+                const TM* __restrict__ P, TW* __restrict__ W) {
+  const unsigned t = xcd_block();
+  const int j = (int)(t / (unsigned)gx), b = (int)(t % (unsigned)gx);
+  if (j >= nyn) return;
+  const int nbx = (ncx + 63) / 64;
+  int i;
+  if (j < 3 * ncy) {
+    if (b < nbx) {
+      const int ax = b * 64 + (int)(threadIdx.x & 63);
+      if (ax >= ncx) return;
+      i = 3 * ax + (int)(threadIdx.x >> 6);
+    } else if (b == nbx) {
+      i = 3 * ncx + (int)threadIdx.x;
+      if (i >= nxn) return;
+    } else {
+      return;
+    }
+  } else {
+    i = b * kApWThreads + (int)threadIdx.x;
+    if (i >= nxn) return;
+  }
+  TW w[9][B][3];
+  galerkin_ap_compute<B>(A, nn, nxn, nyn, ncx, ncy, P, i, j, w);
+  const size_t nw = gw_size(nxn, nyn, ncx, ncy), gi = gw_index(i, j, nxn, nyn, ncx, ncy);
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) W[(size_t)((q * B + r) * 3 + c) * nw + gi] = w[q][r][c];
+}
+template <int B, typename TM, typename TW>
+void launch_galerkin_ap_w(hipStream_t s, const Level& L, const TM* A, const TM* P, TW* W) {
+  const int gx = std::max((L.ncx + 63) / 64 + 1, (L.nxn + kApWThreads - 1) / kApWThreads);
+  hipLaunchKernelGGL((k_galerkin_ap_w<B, TM, TW>), dim3(grid_for((size_t)gx * L.nyn, 1)), dim3(kApWThreads), 0, s, A,
+                     L.nn, L.nxn, L.nyn, L.ncx, L.ncy, gx, P, W);
+  VP_LAUNCH_CHECK();
+}
+
 // Pass 2 (one thread per coarse node I): Ac(I, J_t) = sum over the fine nodes i of
 // I's prolongator support of P(i,I)^T W(i, J_t) for the 5 stored targets
 // J_t = I + {(0,0), (1,0), (0,1), (1,1), (-1,1)}; the diagonal block is
@@ -3044,15 +3095,11 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     double* Wap = galerkin_work(c);
     float* W32 = reinterpret_cast<float*>(Wap);
     if (A32 && L.B == 2) {
-      hipLaunchKernelGGL((k_galerkin_ap<2, float, float>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A32, L.nn, L.nxn,
-                         L.nyn, L.ncx, L.ncy, (const float*)p32, W32);
-      VP_LAUNCH_CHECK();
+      launch_galerkin_ap_w<2>(s, L, A32, (const float*)p32, W32);
       hipLaunchKernelGGL((k_galerkin_ptw<2, float, float>), dim3(gc), dim3(kPtwTX * kPtwTY), 0, s,
                          (const float*)p32, (const float*)W32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
     } else if (A32) {
-      hipLaunchKernelGGL((k_galerkin_ap<3, float, float>), dim3(grid_for(L.nn)), dim3(kBlock), 0, s, A32, L.nn, L.nxn,
-                         L.nyn, L.ncx, L.ncy, (const float*)p32, W32);
-      VP_LAUNCH_CHECK();
+      launch_galerkin_ap_w<3>(s, L, A32, (const float*)p32, W32);
       hipLaunchKernelGGL((k_galerkin_ptw<3, float, float>), dim3(gc), dim3(kPtwTX * kPtwTY), 0, s,
                          (const float*)p32, (const float*)W32, L.nn, L.nxn, L.nyn, L.ncx, L.ncy, N.A64);
     } else if (L.B == 2) {
