@@ -2111,8 +2111,8 @@ __global__ void k_finish_max(const double* __restrict__ partials, int nblocks, d
 
 // Smoothed prolongator P = (I - omega D^{-1} A) Ptent, omega = omega_scale * 4/(3 lmax),
 // computed in FP64 and stored in FP64 (P), FP32 (P32) or both.  TM = float: from the
-// FP32 copy of the operator (the finest level of the FP32 modes, whose V-cycle and
-// first Galerkin product use the FP32 prolongator only).
+// FP32 copy of the operator (the FP32 modes, whose V-cycle and Galerkin products use
+// the FP32 prolongator only).
 template <int B, typename TM = double>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_p(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int ncy,
@@ -2188,10 +2188,9 @@ k_smooth_p(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, int n
 // every other J: the prolongator columns of k's neighbours reach at most one
 // aggregate further).  W[((q*B + r)*3 + c)*nw + gw_index(i)], nw = gw_size, zero
 // where J is absent.  TM is the operator's and prolongator's storage type and TW
-// that of W, which is also the accumulation type: FP64 throughout, or, in the modes
-// whose finest level runs in FP32, the FP32 copies of A and P the V-cycle applies
-// with W accumulated and stored in FP32 (half the bytes of the product's largest
-// pass; the coarse sums of the second pass stay FP64).
+// that of W, which is also the accumulation type: FP64 throughout, or, in the FP32
+// modes, the FP32 copies of A and P the V-cycle applies with W accumulated and
+// stored in FP32 (half the bytes; the coarse sums of the second pass stay FP64).
 template <int B, typename TM, typename TW>
 __device__ __forceinline__ void galerkin_ap_compute(const TM* __restrict__ A, size_t nn, int nxn, int nyn,
                                                     int ncx, int ncy, const TM* __restrict__ P, int i, int j,
@@ -2257,9 +2256,9 @@ k_galerkin_ap(const TM* __restrict__ A, size_t nn, int nxn, int nyn, int ncx, in
 
 // Pass 1 with threads in the order of W, for FP32 W: a workgroup of three waves
 // takes 64 aggregates of one fine row, wave w the nodes at position w in them, so
-// each store writes 64 consecutive values of a class plane (whole lines: a partial
-// line is fetched before it is written); the loads are three nodes apart and the
-// three waves share their lines.  Per row, one more workgroup takes the nodes past
+// each store writes 64 consecutive values of a class plane (whole lines; measured
+// faster than the row-order threads' three partial runs per store); the loads are
+// three nodes apart and the three waves share their lines.  Per row, one more workgroup takes the nodes past
 // the last full run of 3 (positions 3 and 4 of a longer last run), and the rows past
 // the last full run in y go in row order (their W entries are stored in row order).
 // Workgroups are numbered row by row and dealt to the XCDs in contiguous runs.
@@ -2487,8 +2486,8 @@ __device__ __forceinline__ void store16(float* p, double v) { *p = (float)v; }
 
 // S = D^{-1/2} A D^{-1/2} stored in 16 bits (BF16 or FP16; same 5-block layout).
 // One thread per stored entry, so consecutive lanes write consecutive values and
-// every store covers whole lines (one thread per node wrote 2 bytes per lane at a
-// stride of B*B entries: partial lines, each fetched before it was written).
+// every store covers whole lines (one thread per node, writing 2 bytes per lane at a
+// stride of B*B entries, was measured slower).
 // Entry k = (blk*nn + n)*B*B + r*B + c; the host guarantees 5*B*B*nn < 2^32.
 template <int B, typename T16>
 __global__ void __launch_bounds__(kBlock)
@@ -2717,7 +2716,7 @@ void convert(hipStream_t s, const TS* src, TD* dst, size_t n) {
 }  // namespace
 
 // The smoothed prolongator of a level in FP64 (12*B*nn values): the FP64 one, or
-// the FP32 one widened where only that exists (finest level of the FP32 modes).
+// the FP32 one widened where only that exists (the FP32 modes).
 void amg_export_p(vp_ctx c, int level, double* P) {
   const Level& L = c->lev[level];
   const size_t np = (size_t)12 * L.B * L.nn;
@@ -3147,8 +3146,10 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
       const size_t na = (size_t)5 * L.B * L.B * L.nn;
-      if (l > 0 && c->order == 2) {   // order 1: every FP32 operator was made in the loop (Q2: the finest
-        if (!L.A32) L.A32 = dalloc<float>(na);   // level runs on K2_32)
+      // Q1: every FP32 operator was made in the level loop; Q2: the coarse ones here
+      // (the finest level runs on K2_32)
+      if (l > 0 && c->order == 2) {
+        if (!L.A32) L.A32 = dalloc<float>(na);
         convert(s, L.A64, L.A32, na);
       }
       if (L.P64 && (c->order == 2 && l == 0)) {   // smoothed prolongators got theirs from k_smooth_p
