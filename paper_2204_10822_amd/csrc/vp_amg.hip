@@ -2727,6 +2727,7 @@ void amg_export_p(vp_ctx c, int level, double* P) {
 }
 
 void amg_free(vp_ctx c) {
+  c->a32_assembled = false;
   for (int l = 0; l < kMaxLevels; ++l) {
     Level& L = c->lev[l];
     if (l > 0) dfree(L.A64);
@@ -2987,6 +2988,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
   // summed in FP64 and kept in FP64 for the next level's copy and the scalings.
   const bool fine32 = c->order == 1 && (precision == VP_PREC_FP32 || precision == VP_PREC_FP32_BF16COARSE);
   for (int l = 0; l < c->nlev; ++l) c->lev[l].p64_stale = false;
+  if (!fine32) c->a32_assembled = false;   // other modes may overwrite the finest FP32 buffer
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const unsigned g = (unsigned)((L.nn + kBlock - 1) / kBlock);
@@ -3007,7 +3009,7 @@ void amg_setup_numeric(vp_ctx c, int precision, double omega_scale) {
     if (fine32) {
       const size_t na = (size_t)5 * L.B * L.B * L.nn;
       if (!L.A32) L.A32 = dalloc<float>(na);
-      convert(s, L.A64, L.A32, na);
+      if (!(l == 0 && c->a32_assembled)) convert(s, L.A64, L.A32, na);   // else written by the assembly
       A32 = L.A32;
     }
     if (A32 && L.B == 2)

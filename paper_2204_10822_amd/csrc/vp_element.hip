@@ -449,7 +449,7 @@ __device__ __forceinline__ void cell_blocks(const ElemConst& c, const CellVel& V
 // Write node (i, j)'s five stored blocks (self, E, N, NE, NW) with the Dirichlet
 // rows and columns: identity at boundary nodes, no coupling to them.
 __device__ __forceinline__ void store_node_blocks(const ElemConst& c, double* __restrict__ K, int i, int j,
-                                                  const double (&blk)[5][4]) {
+                                                  const double (&blk)[5][4], float* __restrict__ K32 = nullptr) {
   const size_t nn = (size_t)c.nxn * c.nyn;
   const size_t n = (size_t)j * c.nxn + i;
   const bool bn = is_boundary(c, i, j);
@@ -470,6 +470,9 @@ __device__ __forceinline__ void store_node_blocks(const ElemConst& c, double* __
     double2* dst = reinterpret_cast<double2*>(K + aidx(2, nn, b, n, 0, 0));
     dst[0] = make_double2(val[0], val[1]);
     dst[1] = make_double2(val[2], val[3]);
+    if (K32)   // the FP32 copy the FP32 modes' AMG setup reads (the same rounding as a conversion)
+      *reinterpret_cast<float4*>(K32 + aidx(2, nn, b, n, 0, 0)) =
+          make_float4((float)val[0], (float)val[1], (float)val[2], (float)val[3]);
   }
 }
 
@@ -477,7 +480,7 @@ template <int TCX, int TCY>
 __global__ void __launch_bounds__(TCX * TCY)
 k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__ pi, int variant,
            const double* __restrict__ vo, const double* __restrict__ P,
-           const double* __restrict__ rhoH, double* __restrict__ K) {
+           const double* __restrict__ rhoH, double* __restrict__ K, float* __restrict__ K32) {
   constexpr int NT = TCX * TCY, NX = TCX - 1, NY = TCY - 1;   // threads = cells; nodes NX x NY
   __shared__ double cv[36 * NT];
   const size_t ncell = (size_t)c.nx * c.ny;
@@ -518,7 +521,7 @@ k_assemble(ElemConst c, const double* __restrict__ v, const double* __restrict__
     blk[3][k] = at(kB03 + k, cNE);
     blk[4][k] = at(kB12 + k, cNW);
   }
-  store_node_blocks(c, K, i, j, blk);
+  store_node_blocks(c, K, i, j, blk, K32);
 }
 
 
@@ -542,16 +545,25 @@ unsigned residual_blocks(const ElemConst& c) {
 
 // K receives the Q1 operator; with Q2 elements the operator goes to c->K2 (the AMG
 // builds its first coarse level from it and K is not used).
+// When the last AMG setup ran in an FP32 mode (its hierarchy starts from an FP32
+// copy of this operator), the assembly writes that copy too and the next setup
+// skips the conversion.
 void launch_assemble(vp_ctx c, const double* v, const double* pi, int variant, double* K) {
+  c->a32_assembled = false;
   if (c->order == 2) {
     launch_q2_assemble(c, v, pi, variant);
     return;
   }
+  float* K32 = nullptr;
+  if (K == c->lev[0].A64 && c->lev[0].A32 && c->amg_kind == VP_AMG_SA &&
+      (c->amg_prec == VP_PREC_FP32 || c->amg_prec == VP_PREC_FP32_BF16COARSE))
+    K32 = c->lev[0].A32;
   constexpr int TX = kTC, TY = kTC;   // 8-row tiles measured no faster, 4-row tiles slower
   const dim3 g((unsigned)((c->ec.nxn + TX - 2) / (TX - 1)), (unsigned)((c->ec.nyn + TY - 2) / (TY - 1)));
   hipLaunchKernelGGL((k_assemble<TX, TY>), g, dim3(TX * TY), 0, c->stream, c->ec, v, pi, variant, c->vo, c->P,
-                     c->rhoH, K);
+                     c->rhoH, K, K32);
   VP_LAUNCH_CHECK();
+  c->a32_assembled = K32 != nullptr;
 }
 
 // ---------------------------------------------------------------------------

@@ -224,6 +224,7 @@ struct vp_ctx_s {
   bool amg_ready = false;
   bool amg_struct = false;
   int amg_prec = 0;
+  bool a32_assembled = false;      // the last assembly also wrote lev[0].A32 (FP32 copy, FP32 modes)
   int amg_kind = 0;                // VP_AMG_SA or VP_AMG_RS
   bool sa_vec64 = false;           // the SA V-cycle vectors are FP64
   bool ph_transfers = false;       // finest restriction/prolongation read the FP16 prolongator

@@ -520,3 +520,28 @@ def test_coarse_paired_sweeps_match_single_sweeps(vp, prec, degree):
     assert levels[1][0] * levels[1][1] >= 100000
     print(f"[coarse pairs] prec={prec} degree={degree} max |diff| {np.abs(ref - out).max():.2e}", flush=True)
     assert np.array_equal(ref, out)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_fp32_copy_from_assembly_matches_conversion(vp, prec):
+    """After a setup in an FP32 mode the next assembly also writes the FP32 copy of the
+    operator that the setup would otherwise convert.  The two copies are bitwise
+    equal: two Newton solves of the same inputs in one context (the first one's first
+    step converts, every later step uses the assembly's copy) give bitwise the same
+    velocity, dual field and iteration counts (a solve restarts its spectral
+    estimates, so it is a function of its inputs only)."""
+    w = inputs.sharp_step(160)
+    ctx = vp.context_for(w)
+    outs = []
+    for rep in range(2):
+        v = torch.zeros(ctx.node_shape, dtype=torch.float64, device="cuda")
+        pi = torch.zeros(ctx.pi_shape, dtype=torch.float64, device="cuda")
+        n, a, k = vp.default_opts()
+        a.precision = prec
+        rc, info, _ = ctx.vp_newton_solve(v, pi, 200, n, a, k, history=False)
+        print(f"[fp32 copy] prec={prec} solve {rep}: rc={rc} its={info.iterations} krylov={info.krylov_iters}",
+              flush=True)
+        assert rc == 0
+        outs.append((_host(v).copy(), _host(pi).copy(), info.iterations, info.krylov_iters))
+    assert outs[0][2:] == outs[1][2:]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
